@@ -1,0 +1,355 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the pin it implements. None of them compares the oracle with
+a retyped copy of itself: every expected value comes from a closed form, a
+library routine on a special case, an independent quadrature, an invariant, or
+a number printed in the paper.
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import workloads as wl
+from oracle import spectral as sp
+from oracle.bkw import bkw_dfdt, bkw_f, bkw_grid, error_norms
+from oracle.brute import q_brute
+from oracle.direct import q_direct
+from oracle.sigma import mixture, q_sigma
+from oracle import stepping
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _mix(d, N, L, seed=3):
+    return wl.mixture_cells(d, N, L, 1, seed)[0]
+
+
+# ------------------------------------------------------------------ P1 DFT
+
+@pytest.mark.parametrize("d,N", [(2, 8), (2, 12), (3, 6)])
+def test_p1_single_mode_dft(d, N):
+    """A single real Fourier mode cos(2 pi k0.j/N) has f_hat = (delta_k0 + delta_-k0)/2."""
+    rng = np.random.default_rng(0)
+    k0 = rng.integers(-N // 2 + 1, N // 2, size=d)
+    j = np.indices((N,) * d)
+    ph = 2 * math.pi * sum(k0[a] * j[a] for a in range(d)) / N
+    fh = sp.forward_dft(np.cos(ph), d)
+    want = np.zeros((N,) * d, complex)
+    want[tuple(k0 % N)] += 0.5
+    want[tuple((-k0) % N)] += 0.5
+    assert np.abs(fh - want).max() < 1e-15 * N ** d
+    # inverse of a unit spike at mode k0 is exp(+i 2 pi k0.j/N)
+    z = np.zeros((N,) * d, complex)
+    z[tuple(k0 % N)] = 1.0
+    assert np.abs(sp.inverse_dft(z, d) - np.exp(1j * ph)).max() < 1e-13
+    modes = sp.mode_indices(N)
+    assert modes[N // 2] == -N // 2 and modes[1] == 1 and modes[-1] == -1
+
+
+# -------------------------------------------------------------- P2 filters
+
+@pytest.mark.parametrize("s", [0.0, 1e-6, 0.3, 1.7, 5.2])
+def test_p2_segment_filters(s):
+    R = 3.1
+    re = integrate.quad(lambda r: math.cos(r * s), -R, R, epsabs=1e-14, epsrel=1e-14, limit=200)[0]
+    assert abs(sp.phi_segment(np.array([s]), R)[0] - re) < 1e-12
+    re3 = integrate.quad(lambda r: abs(r) * math.cos(r * s), -R, R, points=[0.0],
+                         epsabs=1e-14, epsrel=1e-14, limit=200)[0]
+    assert abs(sp.phi_weighted_segment(np.array([s]), R)[0] - re3) < 1e-12
+    # sine parts vanish: both filters are real and even
+    im = integrate.quad(lambda r: math.sin(r * s), -R, R, epsabs=1e-14)[0]
+    assert abs(im) < 1e-13
+
+
+@pytest.mark.parametrize("t", [0.0, 0.4, 2.3])
+def test_p2_disc_filter(t):
+    """Psi3(t) = integral over a disc of radius R of exp(i m.y), |m_inplane| = t."""
+    R = 2.2
+    val = integrate.dblquad(lambda psi, r: r * math.cos(t * r * math.cos(psi)),
+                            0.0, R, 0.0, 2 * math.pi, epsabs=1e-13, epsrel=1e-13)[0]
+    assert abs(sp.psi_disc(np.array([t]), R)[0] - val) < 1e-10
+
+
+def test_p2_hs2d_expansion():
+    """Full-rank expansion == Gauss-Legendre double sum of sqrt(r^2+r'^2) cos(r s) cos(r' t)
+    over the model's nodes; the truncated one stays within the dropped-eigenvalue
+    bound; the model quadrature is close to the exact double integral (dblquad)."""
+    R = 7.0
+    lam, rp, wp, V = sp.hs2d_radial_expansion(R, 32, 32)
+    lam5, _, _, V5 = sp.hs2d_radial_expansion(R, 32, None, 1e-4)
+    assert len(lam5) == 5
+    x, w = np.polynomial.legendre.leggauss(32)
+    rho = np.concatenate([-0.5 * R * (x + 1), 0.5 * R * (x + 1)])
+    wr = np.concatenate([0.5 * R * w, 0.5 * R * w])
+    K = np.sqrt(rho[:, None] ** 2 + rho[None, :] ** 2)
+    for s, t in [(0.0, 0.0), (0.7, -1.3), (2.1, 0.4)]:
+        direct = np.sum(np.outer(wr * np.exp(1j * rho * s), wr * np.exp(1j * rho * t)) * K).real
+        full = sum(lam[j] * sp.hs2d_phi(np.array([s]), rp, wp, V[:, j])[0]
+                   * sp.hs2d_phi(np.array([t]), rp, wp, V[:, j])[0] for j in range(len(lam)))
+        assert abs(full - direct) < 1e-11 * abs(direct) + 1e-11
+        trunc = sum(lam5[j] * sp.hs2d_phi(np.array([s]), rp, wp, V5[:, j])[0]
+                    * sp.hs2d_phi(np.array([t]), rp, wp, V5[:, j])[0] for j in range(5))
+        bound = np.sum(np.abs(lam[5:])) * (np.sum(np.sqrt(wp)) ** 2)
+        assert abs(trunc - direct) <= bound
+    exact = integrate.dblquad(lambda b, a: math.sqrt(a * a + b * b) * math.cos(0.7 * a) * math.cos(-1.3 * b),
+                              -R, R, -R, R, epsabs=1e-12, epsrel=1e-12)[0]
+    gl = np.sum(np.outer(wr * np.cos(0.7 * rho), wr * np.cos(-1.3 * rho)) * K)
+    assert abs(gl - exact) < 1e-6 * abs(exact)
+
+
+# ------------------------------------------------------- P3 / P4 structure
+
+@pytest.mark.parametrize("kernel,N", [("maxwell", 6), ("maxwell", 8), ("hard_sphere", 6), ("hard_sphere", 8)])
+def test_p3_p4_2d_brute_and_direct(kernel, N):
+    s = sp.Setup(d=2, N=N, L=4.0, kernel=kernel, M=8, K_r=32 if kernel == "hard_sphere" else None)
+    f = _mix(2, N, 4.0)
+    q1 = sp.q_fast(f, s)
+    sc = np.abs(q1).max()
+    q2 = q_direct(f, s)
+    assert np.abs(q1 - q2).max() < 1e-12 * sc
+    q3 = q_brute(f, s).reshape(N, N)
+    assert np.abs(q1 - q3).max() < 1e-12 * sc
+
+
+def test_p4_2d_direct_n12_and_truncated_hs():
+    f = _mix(2, 12, 5.0, seed=9)
+    for kern, K in [("maxwell", None), ("hard_sphere", None)]:
+        s = sp.Setup(d=2, N=12, L=5.0, kernel=kern, M=8, K_r=K)
+        q1 = sp.q_fast(f, s)
+        assert np.abs(q1 - q_direct(f, s)).max() < 1e-12 * np.abs(q1).max()
+
+
+def test_p3_2d_brute_n12_subset():
+    N = 12
+    s = sp.Setup(d=2, N=N, L=5.0, kernel="maxwell", M=8)
+    f = _mix(2, N, 5.0, seed=11)
+    idx = np.arange(0, N * N, 11)
+    q1 = sp.q_fast(f, s).reshape(-1)[idx]
+    q3 = q_brute(f, s, node_idx=idx)
+    assert np.abs(q1 - q3).max() < 1e-12 * np.abs(q1).max()
+
+
+@pytest.mark.parametrize("N,M", [(4, 2), (4, 8), (6, 2)])
+def test_p3_p4_3d(N, M):
+    L = 3.0
+    s = sp.Setup(d=3, N=N, L=L, kernel="hard_sphere", M=M)
+    f = _mix(3, N, L, seed=4)
+    q1 = sp.q_fast(f, s)
+    sc = np.abs(q1).max()
+    assert np.abs(q1 - q_direct(f, s)).max() < 1e-12 * sc
+    idx = np.arange(0, N ** 3, 17 if N == 4 else 53)
+    q3 = q_brute(f, s, node_idx=idx)
+    assert np.abs(q1.reshape(-1)[idx] - q3).max() < 1e-11 * sc
+
+
+def test_fields_are_real():
+    """Filters are real, even and Nyquist-free, so every inverse transform is real."""
+    for s in [sp.Setup(d=2, N=16, L=8.0, kernel="hard_sphere", M=8),
+              sp.Setup(d=3, N=8, L=6.0, kernel="hard_sphere", M=8)]:
+        f = _mix(s.d, s.N, s.L)
+        fh = sp.forward_dft(f, s.d)
+        for W, a, ap in sp.filter_bank(s)[:6]:
+            for filt in (a, ap):
+                g = sp.inverse_dft(filt * fh, s.d)
+                assert np.abs(g.imag).max() < 1e-13 * max(1.0, np.abs(g.real).max())
+
+
+def test_2d_pairing_h_equals_rotated_g():
+    """With M even, e_perp of direction p is direction p + M/2, so alpha'_p = alpha_{p+M/2}."""
+    s = sp.Setup(d=2, N=16, L=8.0, kernel="hard_sphere", M=8)
+    bank = sp.filter_bank(s)
+    K = len(bank) // s.M
+    for p in range(s.M):
+        for j in range(K):
+            q = (p + s.M // 2) % s.M
+            assert np.abs(bank[p * K + j][2] - bank[q * K + j][1]).max() < 1e-12
+
+
+# ------------------------------------------------------------- P5 / P6 / P8
+
+@pytest.mark.parametrize("d,N,L,kernel,M", [(2, 16, 8.0, "maxwell", 8), (2, 32, 8.0, "hard_sphere", 8),
+                                            (2, 24, 6.0, "hard_sphere", 16), (3, 8, 6.0, "hard_sphere", 8)])
+def test_p5_mass_conservation(d, N, L, kernel, M):
+    s = sp.Setup(d=d, N=N, L=L, kernel=kernel, M=M)
+    f = wl.mixture_cells(d, N, L, 3, 21)
+    q = sp.q_fast(f, s)
+    axes = tuple(range(1, d + 1))
+    assert np.all(np.abs(q.sum(axis=axes)) <= 1e-14 * np.abs(q).sum(axis=axes) * 10)
+
+
+@pytest.mark.parametrize("kernel,floor10", [("maxwell", 2e-8), ("hard_sphere", 2e-7)])
+def test_p6_maxwellian_equilibrium_spectral_decay(kernel, floor10):
+    """Q(M, M) = 0 in the continuum for any direction set; on the grid the residual
+    comes from interpolation (falls spectrally with N) and from periodic wrap of
+    the Carleman segments (a floor set by L, section 3.3's support condition)."""
+    for L, floor in [(8.0, 3e-5), (10.0, floor10)]:
+        vals = []
+        for N in (16, 24, 32, 48):
+            s = sp.Setup(d=2, N=N, L=L, kernel=kernel, M=8)
+            f = wl.maxwellian(2, N, L, [1.0], [[0.0, 0.0]], [1.0])[0]
+            q, gain, _ = sp.q_fast(f, s, return_parts=True)
+            vals.append(np.abs(q).max() / np.abs(gain).max())
+        assert vals[1] < vals[0] / 30 and vals[2] <= vals[1] * 1.01
+        assert vals[3] < floor
+
+
+def test_p8_equivariance_and_scaling():
+    N, L = 16, 6.0
+    f = _mix(2, N, L, seed=8)
+    s = sp.Setup(d=2, N=N, L=L, kernel="hard_sphere", M=8)
+    q = sp.q_fast(f, s)
+    sc = np.abs(q).max()
+    # periodic shift by one node
+    assert np.abs(sp.q_fast(np.roll(f, (1, -3), axis=(0, 1)), s) - np.roll(q, (1, -3), axis=(0, 1))).max() < 1e-13 * sc
+    # rotation by 90 degrees about v = 0: f'(v1, v2) = f(v2, -v1); node -v is index (N - i) mod N
+    neg = (N - np.arange(N)) % N
+    rot = lambda a: a.T[:, neg]   # noqa: E731  a'[i1, i2] = a[i2, neg[i1]]
+    assert np.abs(sp.q_fast(rot(f), s) - rot(q)).max() < 1e-13 * sc
+    # reflection v1 -> -v1
+    ref = lambda a: a[neg, :]     # noqa: E731
+    assert np.abs(sp.q_fast(ref(f), s) - ref(q)).max() < 1e-13 * sc
+    # quadratic homogeneity
+    assert np.abs(sp.q_fast(2.5 * f, s) - 6.25 * q).max() < 1e-13 * 6.25 * sc
+
+
+def test_p8_3d_rotation_about_z():
+    N, L = 8, 5.0
+    f = _mix(3, N, L, seed=2)
+    s = sp.Setup(d=3, N=N, L=L, kernel="hard_sphere", M=32)
+    q = sp.q_fast(f, s)
+    neg = (N - np.arange(N)) % N
+    rot = lambda a: np.transpose(a, (1, 0, 2))[neg, :, :]   # noqa: E731  (v1,v2,v3)->(-v2,v1,v3)
+    assert np.abs(sp.q_fast(rot(f), s) - rot(q)).max() < 1e-12 * np.abs(q).max()
+
+
+# ------------------------------------------------------------------- P7 BKW
+
+def test_p7_bkw_closed_form_moments():
+    """Unit mass, energy 2, fourth moment 8 - 2 exp(-t/4), and the analytic d f/dt."""
+    for t in (0.0, 0.7, 3.0):
+        r = np.linspace(0, 40, 400001)
+        fr = bkw_f(r ** 2, t) * 2 * math.pi * r
+        mass = integrate.simpson(fr, x=r)
+        e = integrate.simpson(fr * r ** 2, x=r)
+        m4 = integrate.simpson(fr * r ** 4, x=r)
+        assert abs(mass - 1) < 1e-10 and abs(e - 2) < 1e-9
+        assert abs(m4 - (8 - 2 * math.exp(-t / 4))) < 1e-8
+        v2 = np.linspace(0, 30, 7)
+        h = 1e-5
+        fd = (bkw_f(v2, t + h) - bkw_f(v2, t - h)) / (2 * h)
+        assert np.abs(fd - bkw_dfdt(v2, t)).max() < 1e-9
+
+
+@pytest.mark.parametrize("N,L,tol", [(32, 8.0, 3e-4), (64, 8.0, 1e-6), (64, 12.0, 1e-6)])
+def test_p7_bkw_operator_matches_time_derivative(N, L, tol):
+    """Q_h(f_BKW(t)) must reproduce d f_BKW / dt: pins b_0 = 1/(2 pi), W and B~."""
+    s = sp.Setup(d=2, N=N, L=L, kernel="maxwell", M=16)
+    v = -L + np.arange(N) * 2 * L / N
+    g1, g2 = np.meshgrid(v, v, indexing="ij")
+    for t in (0.0, 0.5, 2.0):
+        q = sp.q_fast(bkw_grid(N, L, t), s)
+        ex = bkw_dfdt(g1 ** 2 + g2 ** 2, t)
+        assert np.abs(q - ex).max() < tol * np.abs(ex).max()
+
+
+def test_p7_bkw_paper_table_order_of_magnitude():
+    """RK4 (dt=1e-3) to t=0.1 on [-12,12]^2 reproduces the paper's printed errors to
+    within an order of magnitude (grid convention differs, so not exactly)."""
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, "bkw_paper_table.txt")) if ln[0] != "#"]
+    table = {int(r[0]): float(r[2]) for r in rows}
+    for N in (16, 32, 64):
+        s = sp.Setup(d=2, N=N, L=12.0, kernel="maxwell", M=16)
+        bank = sp.filter_bank(s)
+        f = bkw_grid(N, 12.0, 0.0)
+        dt = 1e-3
+        for _ in range(100):
+            k1 = sp.q_fast(f, s, bank)
+            k2 = sp.q_fast(f + 0.5 * dt * k1, s, bank)
+            k3 = sp.q_fast(f + 0.5 * dt * k2, s, bank)
+            k4 = sp.q_fast(f + dt * k3, s, bank)
+            f = f + dt / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+        l1 = error_norms(f, bkw_grid(N, 12.0, 0.1))[0]
+        assert table[N] / 10 < l1 < table[N] * 10
+
+
+def test_p7_config1_explicit_euler_error_decreases():
+    """Config-1 run: 100 explicit Euler steps (dt = 0.01) from the BKW datum; errors vs
+    the closed form fall with N and with dt."""
+    errs = {}
+    for N, dt in [(16, 0.01), (32, 0.01), (32, 0.005)]:
+        s = sp.Setup(d=2, N=N, L=8.0, kernel="maxwell", M=16)
+        bank = sp.filter_bank(s)
+        f = bkw_grid(N, 8.0, 0.0)
+        for _ in range(int(round(1.0 / dt))):
+            f = f + dt * sp.q_fast(f, s, bank)
+        errs[(N, dt)] = error_norms(f, bkw_grid(N, 8.0, 1.0))
+    assert errs[(32, 0.01)][0] < errs[(16, 0.01)][0]
+    assert errs[(32, 0.005)][0] < 0.7 * errs[(32, 0.01)][0]
+
+
+# ----------------------------------------------------------- P10 sigma form
+
+@pytest.mark.parametrize("kernel,tol", [("maxwell", 1e-7), ("hard_sphere", 1e-5)])
+def test_p10_sigma_form_2d(kernel, tol):
+    params = [(1.2, np.array([0.3, -0.2]), 0.8), (0.7, np.array([-0.4, 0.1]), 1.3)]
+    fun = mixture(params)
+    L, N = 12.0, 64
+    v = -L + np.arange(N) * 2 * L / N
+    g = np.stack(np.meshgrid(v, v, indexing="ij"), -1).reshape(-1, 2)
+    s = sp.Setup(d=2, N=N, L=L, kernel=kernel, M=32, K_r=None if kernel == "maxwell" else 16)
+    q = sp.q_fast(fun(g).reshape(N, N), s).reshape(-1)
+    idx = [32 * N + 32, 35 * N + 30, 27 * N + 36, 40 * N + 33]
+    qs = q_sigma(fun, g[idx], kernel, 1 / (2 * math.pi), 9.0, 96, 64)
+    assert np.abs(q[idx] - qs).max() < tol * np.abs(q).max()
+
+
+@pytest.mark.slow
+def test_p10_sigma_form_3d_hard_spheres():
+    params = [(1.2, np.array([0.3, -0.2, 0.1]), 0.8), (0.7, np.array([-0.4, 0.1, 0.2]), 1.3)]
+    fun = mixture(params)
+    L, N = 10.0, 32
+    v = -L + np.arange(N) * 2 * L / N
+    g = np.stack(np.meshgrid(v, v, v, indexing="ij"), -1).reshape(-1, 3)
+    s = sp.Setup(d=3, N=N, L=L, kernel="hard_sphere", M=72)
+    q = sp.q_fast(fun(g).reshape(N, N, N), s).reshape(-1)
+    c = N // 2
+    idx = [c * N * N + c * N + c, (c + 2) * N * N + (c - 1) * N + c + 1]
+    qs = q_sigma(fun, g[idx], "hard_sphere", 1 / (4 * math.pi), 7.0, 36, 10)
+    assert np.abs(q[idx] - qs).max() < 1e-4 * np.abs(q).max()
+
+
+# ------------------------------------------------------ P11 / P12 host math
+
+def test_p11_projection():
+    d, N, L = 2, 16, 8.0
+    q = np.random.default_rng(1).standard_normal((3, N, N))
+    qc = sp.project_conservative(q, d, L)
+    assert np.abs(sp.moments(qc, d, L)).max() < 1e-12
+    assert np.abs(sp.project_conservative(qc, d, L) - qc).max() < 1e-13
+    # no-op on an already conservative field; minimal change means the
+    # correction lies in the span of phi
+    assert np.abs(sp.project_conservative(qc, d, L) - qc).max() < 1e-13
+    C = sp.moment_matrix(d, N, L)
+    diff = (q - qc).reshape(3, -1)
+    coef = np.linalg.lstsq(C.T, diff.T, rcond=None)[0]
+    assert np.abs(C.T @ coef - diff.T).max() < 1e-12
+
+
+def test_p12_imex_euler():
+    d, N, L = 2, 16, 8.0
+    f = wl.mixture_cells(d, N, L, 2, 5)
+    s = sp.Setup(d=2, N=N, L=L, kernel="maxwell", M=8)
+    q = sp.q_fast(f, s)
+    rho = stepping.density(f, d, L)
+    maxw = wl.maxwellian(d, N, L, rho, np.zeros((2, 2)), np.ones(2))  # any Maxwellian cancels
+    for dt, eps in [(0.01, 1.0), (0.05, 1e-3)]:
+        a = stepping.imex_euler_penalized(f, q, dt, eps, d, L)
+        b = stepping.imex_euler_penalized_literal(f, q, maxw, dt, eps, d, L)
+        assert np.abs(a - b).max() < 1e-13 * np.abs(f).max()
+    a = stepping.imex_euler_penalized(f, q, 1e-9, 1.0, d, L)
+    e = stepping.explicit_euler(f, q, 1e-9, 1.0)
+    assert np.abs(a - e).max() < 1e-15 * np.abs(f).max() + 1e-20
