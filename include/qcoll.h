@@ -1,0 +1,129 @@
+/*
+ * qcoll -- fast spectral Boltzmann collision operator on MI355X (gfx950).
+ *
+ * C ABI of libqcoll.so. Plain pointers and sizes only. Device pointers are HIP
+ * device addresses on the device that was current when the plan was created.
+ *
+ * The operation (section 3.3 of Boscheri & Dimarco, "High order finite volume
+ * schemes with IMEX time stepping for the Boltzmann model on unstructured
+ * meshes"): for every space cell independently, given the discrete velocity
+ * distribution f on the Cartesian grid of section 3.1 (eq. disc_space), compute
+ * the spectral approximation Q_h(f, f) of the collision integral of eq.
+ * (Boltzmann) written in the Carleman form (eqs. defQBCarleman, Btilde) with the
+ * kernel modes of eq. (FKM) replaced by a sum over A = M collision directions,
+ * evaluated as A discrete convolutions by DFT.
+ *
+ * Conventions fixed by this library (the paper leaves them open):
+ *   - velocity nodes v_i = -L + i*2L/N per axis, i = 0..N-1 (period 2L);
+ *   - f and Q are cell-major arrays [cells][N^d] with the LAST velocity axis
+ *     fastest (row-major N x N in 2D);
+ *   - Carleman truncation radius R = 4L/(3+sqrt 2) (QCOLL_R_LITERAL: 2L/(3+sqrt 2));
+ *   - Fourier modes with a component equal to -N/2 are removed from every filter;
+ *   - 2D: M equispaced directions on the half circle (M even);
+ *     3D: M = 2 n^2 directions, n Gauss-Legendre nodes in cos(theta) on (0,1)
+ *     times 2n equispaced azimuths;
+ *   - b <= 0 selects b = 1/|S^(d-1)|.
+ *
+ * Errors: every entry point returns QCOLL_OK (0) or a negative code; argument
+ * errors are reported synchronously before any device work is queued. Calls
+ * that take a stream are asynchronous with respect to the host.
+ */
+#ifndef QCOLL_H
+#define QCOLL_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qcoll_plan_s* qcoll_plan_t;
+
+/* Collision kernel B of eq. (Boltzmann). Maxwell pseudo-molecules B = b
+ * (section 2); hard spheres B = b |q|. Supported: 2D Maxwell, 2D and 3D hard
+ * spheres. */
+enum { QCOLL_MAXWELL = 0, QCOLL_HARD_SPHERE = 1 };
+
+/* Arithmetic of the velocity DFTs (all variants compute the same Q_h):
+ *   QCOLL_FP32     DFT-GEMMs on FP32 MFMA, FP32 spectra and filters.
+ *   QCOLL_MIX_FX16 DFT-GEMMs on FP16 MFMA with a three-part split of both
+ *                  operands: a fixed-point leading part whose products sum
+ *                  exactly in the FP32 accumulator, plus an FP16 hi/lo
+ *                  remainder (six products, two accumulators); spectra,
+ *                  filters and all elementwise work in FP64. */
+enum { QCOLL_FP32 = 1, QCOLL_MIX_FX16 = 4 };
+
+/* Stage update of qcoll_step (section 3.4, homogeneous case). */
+enum { QCOLL_EXPLICIT_EULER = 0, QCOLL_IMEX_EULER_PENALIZED = 1 };
+
+enum {
+  QCOLL_OK = 0,
+  QCOLL_EINVAL = -1,      /* bad argument (dimension, N, M, L, pointer, count) */
+  QCOLL_ENOMEM = -2,      /* host or device allocation failed                  */
+  QCOLL_EDEVICE = -3,     /* HIP runtime error or no device                    */
+  QCOLL_EUNSUPPORTED = -4 /* valid but not implemented (size, kernel, mode)    */
+};
+
+/* Plan flags. */
+#define QCOLL_CONSERVE 0x1u   /* FP64 moment projection; Q written as double   */
+#define QCOLL_R_LITERAL 0x2u  /* Carleman radius 2L/(3+sqrt 2)                  */
+#define QCOLL_HOST_ONLY 0x100u /* build the FP64 host tables only (no device)  */
+
+/* Build a plan (section 3.3: directions, filters, loss multiplier; section
+ * 3.1: grid). d in {2,3}; n_per_dim = N (currently N = 32 for d = 2 on the
+ * device); L > 0 half-width of the velocity box; kernel QCOLL_MAXWELL or
+ * QCOLL_HARD_SPHERE; b kernel constant (<= 0: default); M number of collision
+ * directions (the paper's A; even in 2D); K_r radial rank of the 2D
+ * hard-sphere expansion (0: smallest rank with eigenvalue ratio < 1e-4;
+ * ignored otherwise); precision one of the QCOLL_FP32 / QCOLL_MIX_FX16 values;
+ * flags a combination of QCOLL_* flags. The plan owns its host and device
+ * tables; it is immutable after creation and may be used from several streams
+ * at once. On error *out is set to NULL. */
+int qcoll_plan(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, double b,
+               int M, int K_r, int precision, unsigned flags);
+
+/* Q = Q_h(f) for `cells` cells. f: device, float[cells][N^d]; Q: device,
+ * float[cells][N^d], or double[cells][N^d] when the plan has QCOLL_CONSERVE
+ * (then every cell's discrete mass, momentum and energy of Q vanish up to FP64
+ * rounding). f and Q must not overlap. cells == 0 is a no-op. Caller owns both
+ * buffers. Returns QCOLL_EINVAL for a NULL pointer or negative count,
+ * QCOLL_EUNSUPPORTED for a host-only plan. */
+int qcoll_eval(qcoll_plan_t plan, const float* f, void* Q, int64_t cells, hipStream_t stream);
+
+/* One space-homogeneous step of d f/dt = Q(f)/eps in place (section 3.4):
+ *   QCOLL_EXPLICIT_EULER:        f <- f + (dt/eps) Q(f)
+ *   QCOLL_IMEX_EULER_PENALIZED:  f <- f + (dt/eps) Q(f) / (1 + dt rho(f)/eps)
+ * (the penalised IMEX Euler stage of eqs. (GIMEXb)-(GIMEX1b) with nu = rho; the
+ * BGK terms cancel exactly because the moments are conserved). rho is
+ * computed in FP64. status: device int32[cells] or NULL; when given, each
+ * cell's entry is set to 0, or to 1 if the updated f has a non-finite value.
+ * dt > 0 and eps > 0 are required. */
+int qcoll_step(qcoll_plan_t plan, float* f, int64_t cells, double dt, double eps, int scheme,
+               int32_t* status, hipStream_t stream);
+
+/* Plan properties: number of DFT passes per cell (packed transforms incl. the
+ * loss), radial rank, Carleman radius, and the device bytes the plan holds. */
+int qcoll_plan_info(qcoll_plan_t plan, int* transforms, int* K_r, double* R, int64_t* device_bytes);
+
+/* FP64 host tables for verification. which:
+ *   0 alpha_t(k)  (index t over directions x radial ranks, out[N^d], FFT order)
+ *   1 alpha'_t(k) (same)
+ *   2 W_t         (out[terms], index ignored)
+ *   3 loss multiplier l(k) = sum_t W_t alpha_t alpha'_t (out[N^d])
+ *   4 radial eigenvalues lambda_j (out[K_r]; {1} for separable kernels)
+ *   5 inverse Gram matrix of phi = (1, v, |v|^2) on the grid (out[(d+2)^2])
+ * n is the capacity of out; returns the number of values written or QCOLL_EINVAL. */
+int qcoll_plan_table(qcoll_plan_t plan, int which, int index, double* out, int64_t n);
+
+/* Release the plan and its device tables (after all its work has completed). */
+void qcoll_plan_destroy(qcoll_plan_t plan);
+
+/* Static string for an error code. */
+const char* qcoll_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QCOLL_H */

@@ -1,0 +1,72 @@
+"""Build libqcoll.so in-tree with hipcc for gfx950.
+
+    python -m paper_2103_14890_amd.build [--verbose]
+"""
+
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB = os.path.join(PKG, "libqcoll.so")
+
+HOST_SOURCES = ["plan.cpp", "api.cpp"]
+DEVICE_SOURCES = ["kernels_2d.hip"]
+ARCH = "gfx950"
+
+COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}", "-I/opt/rocm/include", "-D__HIP_PLATFORM_AMD__"]
+# Packed FP32 VALU instructions are disabled in all device code.
+DEVICE_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-ffp-contract=fast"]
+
+
+def _hipcc() -> str:
+    for cand in (shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found")
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError(f"build step failed: {' '.join(cmd[:3])} ...")
+    if verbose and res.stderr.strip():
+        sys.stderr.write(res.stderr)
+
+
+def build(verbose: bool = False, extra: list[str] | None = None) -> str:
+    """Compile every source and link libqcoll.so next to this file. Always rebuilds."""
+    hipcc = _hipcc()
+    extra = list(extra or [])
+    with tempfile.TemporaryDirectory(prefix="qcoll_build_") as tmp:
+        objs = []
+        for src in HOST_SOURCES:
+            obj = os.path.join(tmp, src + ".o")
+            _run([hipcc, "-x", "c++", *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+            objs.append(obj)
+        for src in DEVICE_SOURCES:
+            obj = os.path.join(tmp, src + ".o")
+            _run([hipcc, "-x", "hip", *COMMON, *DEVICE_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj],
+                 verbose)
+            objs.append(obj)
+        tmp_lib = os.path.join(tmp, "libqcoll.so")
+        _run([hipcc, "-shared", f"--offload-arch={ARCH}", *objs, "-o", tmp_lib], verbose)
+        shutil.copyfile(tmp_lib, LIB + ".tmp")
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="--verbose" in sys.argv)
+    print(LIB)

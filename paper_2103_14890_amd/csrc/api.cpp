@@ -1,0 +1,311 @@
+// C ABI of libqcoll.so: argument checks, device tables, dispatch.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "qcoll.h"
+
+struct qcoll_plan_s {
+  qcoll::HostPlan hp;
+  int precision = 0;
+  unsigned flags = 0;
+  int device = -1;
+  bool on_device = false;
+  // device tables
+  void* econst = nullptr;
+  double* filt = nullptr;
+  int* filt_exp = nullptr;
+  double* loss = nullptr;
+  int loss_exp = 0;
+  float* filt32 = nullptr;
+  float* loss32 = nullptr;
+  int64_t device_bytes = 0;
+  int64_t max_blocks = 0;
+};
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Row order of the contraction index in a 32 x 32 MFMA result tile.
+inline int rrow(int v, int h) { return 8 * (v >> 2) + 4 * h + (v & 3); }
+
+// Exponent e with x < 2^e (x > 0).
+int exp_above(double x) {
+  if (!(x > 0.0)) return 0;
+  int e;
+  std::frexp(x, &e);
+  return e;
+}
+
+template <class T>
+int upload(const std::vector<T>& host, T** dev, int64_t& bytes) {
+  size_t nb = host.size() * sizeof(T);
+  if (hipMalloc(reinterpret_cast<void**>(dev), nb) != hipSuccess) return QCOLL_ENOMEM;
+  if (hipMemcpy(*dev, host.data(), nb, hipMemcpyHostToDevice) != hipSuccess) return QCOLL_EDEVICE;
+  bytes += static_cast<int64_t>(nb);
+  return QCOLL_OK;
+}
+
+void free_device(qcoll_plan_s* p) {
+  hipFree(p->econst);
+  hipFree(p->filt);
+  hipFree(p->filt_exp);
+  hipFree(p->loss);
+  hipFree(p->filt32);
+  hipFree(p->loss32);
+  p->econst = nullptr;
+  p->filt = p->loss = nullptr;
+  p->filt_exp = nullptr;
+  p->filt32 = p->loss32 = nullptr;
+}
+
+// Device tables of the 2D N = 32 kernels. Lane l = 32 h + c of a wavefront
+// holds, for register v, the mode (k1, k2) = (rrow(v, h), c) of a spectrum and
+// the DFT-matrix rows rrow(.., h) of the right-hand operands.
+int build_device_2d32(qcoll_plan_s* p) {
+  const auto& hp = p->hp;
+  const int N = 32;
+  const int P = static_cast<int>(hp.packed.size());
+  if (p->precision == QCOLL_MIX_FX16) {
+    // E[k][j] = exp(2 pi i k j / N) scaled by 2^9, split into lead/hi/lo halves:
+    // [lane][mat (Er, Ei, -Ei)][K-slice s][part][t], value at row rrow(8s+t, h), column c
+    std::vector<_Float16> ec(64 * 3 * 2 * 3 * 8);
+    for (int lane = 0; lane < 64; ++lane) {
+      int h = lane >> 5, c = lane & 31;
+      for (int m = 0; m < 3; ++m)
+        for (int s = 0; s < 2; ++s)
+          for (int t = 0; t < 8; ++t) {
+            int k = rrow(8 * s + t, h);
+            double ang = 2.0 * kPi * static_cast<double>((k * c) % N) / N;
+            double val = m == 0 ? std::cos(ang) : (m == 1 ? std::sin(ang) : -std::sin(ang));
+            double y = 512.0 * val;
+            double lead = std::nearbyint(y);
+            float r = static_cast<float>(y - lead);
+            _Float16 hi = static_cast<_Float16>(r);
+            _Float16 lo = static_cast<_Float16>(r - static_cast<float>(hi));
+            size_t base = ((((static_cast<size_t>(lane) * 3 + m) * 2 + s) * 3) * 8) + t;
+            ec[base + 0 * 8] = static_cast<_Float16>(static_cast<float>(lead));
+            ec[base + 1 * 8] = hi;
+            ec[base + 2 * 8] = lo;
+          }
+    }
+    _Float16* d = nullptr;
+    int rc = upload(ec, &d, p->device_bytes);
+    p->econst = d;
+    if (rc) return rc;
+    std::vector<double> ft(static_cast<size_t>(P) * 64 * 32);
+    std::vector<int> fe(P > 0 ? P : 1, 0);
+    for (int q = 0; q < P; ++q) {
+      double mx = 0.0;
+      for (const auto& z : hp.packed[q]) mx = std::fmax(mx, std::abs(z));
+      int e = exp_above(mx);
+      fe[q] = e;
+      double sc = std::ldexp(1.0, -e);
+      for (int lane = 0; lane < 64; ++lane) {
+        int h = lane >> 5, c = lane & 31;
+        for (int v = 0; v < 16; ++v) {
+          int k = rrow(v, h) * N + c;
+          size_t o = (static_cast<size_t>(q) * 64 + lane) * 32 + 2 * v;
+          ft[o] = hp.packed[q][k].real() * sc;
+          ft[o + 1] = hp.packed[q][k].imag() * sc;
+        }
+      }
+    }
+    if ((rc = upload(ft, &p->filt, p->device_bytes))) return rc;
+    if ((rc = upload(fe, &p->filt_exp, p->device_bytes))) return rc;
+    double lmx = 0.0;
+    for (double x : hp.loss_scaled) lmx = std::fmax(lmx, std::fabs(x));
+    p->loss_exp = exp_above(lmx);
+    std::vector<double> lt(64 * 16);
+    for (int lane = 0; lane < 64; ++lane)
+      for (int v = 0; v < 16; ++v)
+        lt[lane * 16 + v] =
+            std::ldexp(hp.loss_scaled[rrow(v, lane >> 5) * N + (lane & 31)], -p->loss_exp);
+    if ((rc = upload(lt, &p->loss, p->device_bytes))) return rc;
+  } else {
+    // FP32 32x32x2 operands: [lane][mat][v] = Mat[rrow(v, h)][c]
+    std::vector<float> ec(64 * 48);
+    for (int lane = 0; lane < 64; ++lane) {
+      int h = lane >> 5, c = lane & 31;
+      for (int v = 0; v < 16; ++v) {
+        int k = rrow(v, h);
+        double ang = 2.0 * kPi * static_cast<double>((k * c) % N) / N;
+        ec[lane * 48 + v] = static_cast<float>(std::cos(ang));
+        ec[lane * 48 + 16 + v] = static_cast<float>(std::sin(ang));
+        ec[lane * 48 + 32 + v] = static_cast<float>(-std::sin(ang));
+      }
+    }
+    float* d = nullptr;
+    int rc = upload(ec, &d, p->device_bytes);
+    p->econst = d;
+    if (rc) return rc;
+    std::vector<float> ft(static_cast<size_t>(P) * 64 * 32);
+    for (int q = 0; q < P; ++q)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int v = 0; v < 16; ++v) {
+          int k = rrow(v, lane >> 5) * N + (lane & 31);
+          size_t o = (static_cast<size_t>(q) * 64 + lane) * 32 + 2 * v;
+          ft[o] = static_cast<float>(hp.packed[q][k].real());
+          ft[o + 1] = static_cast<float>(hp.packed[q][k].imag());
+        }
+    if ((rc = upload(ft, &p->filt32, p->device_bytes))) return rc;
+    std::vector<float> lt(64 * 16);
+    for (int lane = 0; lane < 64; ++lane)
+      for (int v = 0; v < 16; ++v)
+        lt[lane * 16 + v] = static_cast<float>(hp.loss_scaled[rrow(v, lane >> 5) * N + (lane & 31)]);
+    if ((rc = upload(lt, &p->loss32, p->device_bytes))) return rc;
+  }
+  return QCOLL_OK;
+}
+
+qcoll::KernelArgs make_args(const qcoll_plan_s* p) {
+  qcoll::KernelArgs a;
+  a.econst = p->econst;
+  a.filt = p->filt;
+  a.filt_exp = p->filt_exp;
+  a.loss = p->loss;
+  a.loss_exp = p->loss_exp;
+  a.filt32 = p->filt32;
+  a.loss32 = p->loss32;
+  a.P = static_cast<int>(p->hp.packed.size());
+  for (int i = 0; i < 16 && i < static_cast<int>(p->hp.gram_inv.size()); ++i) a.gram_inv[i] = p->hp.gram_inv[i];
+  a.L = p->hp.L;
+  a.dv = 2.0 * p->hp.L / p->hp.N;
+  a.max_blocks = p->max_blocks;
+  return a;
+}
+
+bool device_supported(const qcoll::HostPlan& hp) { return hp.d == 2 && hp.N == 32; }
+
+}  // namespace
+
+extern "C" {
+
+int qcoll_plan(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, double b, int M,
+               int K_r, int precision, unsigned flags) {
+  if (!out) return QCOLL_EINVAL;
+  *out = nullptr;
+  if (precision != QCOLL_FP32 && precision != QCOLL_MIX_FX16) return QCOLL_EINVAL;
+  if (flags & ~(QCOLL_CONSERVE | QCOLL_R_LITERAL | QCOLL_HOST_ONLY)) return QCOLL_EINVAL;
+  qcoll_plan_s* p = new (std::nothrow) qcoll_plan_s;
+  if (!p) return QCOLL_ENOMEM;
+  p->precision = precision;
+  p->flags = flags;
+  int rc = qcoll::build_host_plan(p->hp, d, n_per_dim, L, kernel, b, M, K_r, flags);
+  if (rc) {
+    delete p;
+    return rc;
+  }
+  if (!(flags & QCOLL_HOST_ONLY)) {
+    if (!device_supported(p->hp)) {
+      delete p;
+      return QCOLL_EUNSUPPORTED;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1 || hipGetDevice(&p->device) != hipSuccess) {
+      delete p;
+      return QCOLL_EDEVICE;
+    }
+    hipDeviceProp_t prop;
+    int cus = 256;
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) cus = prop.multiProcessorCount;
+    p->max_blocks = static_cast<int64_t>(cus) * 8;
+    rc = build_device_2d32(p);
+    if (rc) {
+      free_device(p);
+      delete p;
+      return rc;
+    }
+    p->on_device = true;
+  }
+  *out = p;
+  return QCOLL_OK;
+}
+
+int qcoll_eval(qcoll_plan_t p, const float* f, void* Q, int64_t cells, hipStream_t stream) {
+  if (!p || cells < 0) return QCOLL_EINVAL;
+  if (!p->on_device) return QCOLL_EUNSUPPORTED;
+  if (cells == 0) return QCOLL_OK;
+  if (!f || !Q) return QCOLL_EINVAL;
+  int64_t n = static_cast<int64_t>(p->hp.N) * p->hp.N;
+  if (cells > (INT64_MAX / 8) / n) return QCOLL_EINVAL;
+  qcoll::KernelArgs a = make_args(p);
+  a.f = f;
+  a.q = Q;
+  a.cells = cells;
+  int out_kind = (p->flags & QCOLL_CONSERVE) ? 1 : 0;
+  return qcoll::launch_2d32(a, p->precision, out_kind, stream) ? QCOLL_EDEVICE : QCOLL_OK;
+}
+
+int qcoll_step(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps, int scheme,
+               int32_t* status, hipStream_t stream) {
+  if (!p || cells < 0) return QCOLL_EINVAL;
+  if (!(dt > 0.0) || !(eps > 0.0) || !std::isfinite(dt) || !std::isfinite(eps)) return QCOLL_EINVAL;
+  if (scheme != QCOLL_EXPLICIT_EULER && scheme != QCOLL_IMEX_EULER_PENALIZED) return QCOLL_EINVAL;
+  if (!p->on_device) return QCOLL_EUNSUPPORTED;
+  if (cells == 0) return QCOLL_OK;
+  if (!f) return QCOLL_EINVAL;
+  qcoll::KernelArgs a = make_args(p);
+  a.f = f;
+  a.cells = cells;
+  a.dt_eps = dt / eps;
+  a.scheme = scheme;
+  a.status = status;
+  return qcoll::launch_2d32(a, p->precision, 2, stream) ? QCOLL_EDEVICE : QCOLL_OK;
+}
+
+int qcoll_plan_info(qcoll_plan_t p, int* transforms, int* K_r, double* R, int64_t* device_bytes) {
+  if (!p) return QCOLL_EINVAL;
+  if (transforms) *transforms = static_cast<int>(p->hp.packed.size()) + 1;
+  if (K_r) *K_r = p->hp.K_r;
+  if (R) *R = p->hp.R;
+  if (device_bytes) *device_bytes = p->device_bytes;
+  return QCOLL_OK;
+}
+
+int qcoll_plan_table(qcoll_plan_t p, int which, int index, double* out, int64_t n) {
+  if (!p || !out || n < 0) return QCOLL_EINVAL;
+  const auto& hp = p->hp;
+  const std::vector<double>* src = nullptr;
+  switch (which) {
+    case 0:
+    case 1:
+      if (index < 0 || index >= static_cast<int>(hp.alpha.size())) return QCOLL_EINVAL;
+      src = which == 0 ? &hp.alpha[index] : &hp.alphap[index];
+      break;
+    case 2: src = &hp.W; break;
+    case 3: src = &hp.loss; break;
+    case 4: src = &hp.lambda; break;
+    case 5: src = &hp.gram_inv; break;
+    default: return QCOLL_EINVAL;
+  }
+  if (static_cast<int64_t>(src->size()) > n) return QCOLL_EINVAL;
+  std::memcpy(out, src->data(), src->size() * sizeof(double));
+  return static_cast<int>(src->size());
+}
+
+void qcoll_plan_destroy(qcoll_plan_t p) {
+  if (!p) return;
+  if (p->on_device) free_device(p);
+  delete p;
+}
+
+const char* qcoll_strerror(int code) {
+  switch (code) {
+    case QCOLL_OK: return "ok";
+    case QCOLL_EINVAL: return "invalid argument";
+    case QCOLL_ENOMEM: return "out of memory";
+    case QCOLL_EDEVICE: return "HIP device error";
+    case QCOLL_EUNSUPPORTED: return "unsupported configuration";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

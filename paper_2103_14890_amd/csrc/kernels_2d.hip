@@ -1,0 +1,464 @@
+// Fast spectral collision operator, 2D velocity grid N = 32, gfx950.
+//
+// One wavefront evaluates one cell; a 256-thread workgroup holds four cells
+// and walks the cell range in a grid-stride loop. Everything a cell needs
+// between the load of f and the store of Q stays in registers.
+//
+// Dataflow per cell (section 3.3): forward 2D DFT of f -> f_hat; for every
+// packed filter q the spectrum m_q * f_hat and its inverse 2D DFT, whose real
+// and imaginary parts are the two real fields g and h of one or two collision
+// directions (their product is the gain contribution); one more inverse DFT
+// of l * f_hat gives the loss field; Q = gain - f * loss.
+//
+// Each 1-D DFT pass is a dense DFT-matrix GEMM on MFMA with the DATA as the
+// left operand and the DFT matrix as the right operand. The MFMA result tile
+// holds its column index on the lanes and its row index in registers, which
+// is exactly the left-operand layout of the next MFMA with rows and columns
+// swapped; so consecutive passes chain in registers and the transposition
+// between the two axes of the 2D transform costs nothing. The register order
+// of the contraction index is the result-tile row order
+//   r(v, h) = 8 (v / 4) + 4 h + v % 4   (register v, lane half h),
+// and the DFT-matrix operands are stored with their rows in that order.
+//
+// Two arithmetic variants compute the same operator:
+//  * FX16: both GEMM operands are split into a fixed-point leading part on a
+//    9-bit grid (|lead| <= 512, so the 64 lead*lead products of a K = 64
+//    contraction sum exactly in FP32) plus an FP16 hi/lo remainder. Six MFMA
+//    products feed two accumulators (exact lead*lead, and the rest). Spectra,
+//    filters and elementwise arithmetic are FP64.
+//  * FP32: plain FP32 MFMA (32x32x2) with FP32 spectra and filters.
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace qcoll {
+namespace {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kN = 32;
+constexpr int kWaves = 4;  // wavefronts (cells) per workgroup
+
+__device__ __forceinline__ int rrow(int v, int h) { return 8 * (v >> 2) + 4 * h + (v & 3); }
+
+__device__ __forceinline__ float wave_max(float x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o));
+  return x;
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+// Exponent e with x < 2^e for x > 0 (0 for x == 0 or non-finite input).
+__device__ __forceinline__ int exp_above(float x) {
+  if (!(x > 0.0f) || !(x <= 3.0e38f)) return 0;
+  int e;
+  frexpf(x, &e);
+  return e;
+}
+
+// ------------------------------------------------------------- epilogue
+
+// Store Q, or apply the conservation projection (FP64 moments, wave
+// reductions) and store Q as double, or apply the stage update to f.
+template <int OUT>
+__device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, double* q, int h,
+                            int c) {
+  if (OUT == 0) {
+    float* Qc = reinterpret_cast<float*>(a.q) + cell * (kN * kN);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) Qc[rrow(v, h) * kN + c] = static_cast<float>(q[v]);
+    return;
+  }
+  if (OUT == 1) {
+    // moments sum_j phi(v_j) Q_j with phi = (1, v1, v2, |v|^2); lambda = G^-1 m
+    const double v2c = -a.L + a.dv * c;
+    double m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const double v1 = -a.L + a.dv * rrow(v, h);
+      m0 += q[v];
+      m1 += v1 * q[v];
+      m2 += v2c * q[v];
+      m3 += (v1 * v1 + v2c * v2c) * q[v];
+    }
+    m0 = wave_sum(m0);
+    m1 = wave_sum(m1);
+    m2 = wave_sum(m2);
+    m3 = wave_sum(m3);
+    double lam[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      lam[i] = a.gram_inv[i * 4 + 0] * m0 + a.gram_inv[i * 4 + 1] * m1 + a.gram_inv[i * 4 + 2] * m2 +
+               a.gram_inv[i * 4 + 3] * m3;
+    double* Qc = reinterpret_cast<double*>(a.q) + cell * (kN * kN);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const double v1 = -a.L + a.dv * rrow(v, h);
+      double corr = lam[0] + lam[1] * v1 + lam[2] * v2c + lam[3] * (v1 * v1 + v2c * v2c);
+      Qc[rrow(v, h) * kN + c] = q[v] - corr;
+    }
+    return;
+  }
+  // OUT == 2: stage update in place
+  double rho = 0.0;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) rho += static_cast<double>(fv[v]);
+  rho = wave_sum(rho) * a.dv * a.dv;
+  const double k = a.scheme == 1 ? a.dt_eps / (1.0 + a.dt_eps * rho) : a.dt_eps;
+  float* fcell = const_cast<float*>(a.f) + cell * (kN * kN);
+  int bad = 0;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    float nv = static_cast<float>(static_cast<double>(fv[v]) + k * q[v]);
+    bad |= !(fabsf(nv) <= 3.0e38f);
+    fcell[rrow(v, h) * kN + c] = nv;
+  }
+  if (a.status) {
+    bad = __any(bad) ? 1 : 0;
+    if ((threadIdx.x & 63) == 0) a.status[cell] = bad;
+  }
+}
+
+// ------------------------------------------------------------ FX16 helpers
+
+struct Split3 {
+  half8 l, h, o;  // fixed-point lead, FP16 hi and lo of the remainder
+};
+
+__device__ __forceinline__ f32x16 mfma16(half8 a, half8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+
+// acc0 += a.l*b.l (exact); acc1 += the five remaining products down to 2^-20.
+__device__ __forceinline__ void mma6(const Split3& a, const Split3& b, f32x16& acc0, f32x16& acc1) {
+  acc0 = mfma16(a.l, b.l, acc0);
+  acc1 = mfma16(a.l, b.h, acc1);
+  acc1 = mfma16(a.h, b.l, acc1);
+  acc1 = mfma16(a.l, b.o, acc1);
+  acc1 = mfma16(a.h, b.h, acc1);
+  acc1 = mfma16(a.o, b.l, acc1);
+}
+
+struct H3 {
+  _Float16 l, h, o;
+};
+
+// Split y (|y| < 512.5) into lead = rint(y) and an FP16 hi/lo remainder.
+__device__ __forceinline__ H3 split_f64(double y) {
+  double n0 = __builtin_rint(y);
+  float r = static_cast<float>(y - n0);
+  H3 s;
+  s.l = static_cast<_Float16>(static_cast<float>(n0));
+  s.h = static_cast<_Float16>(r);
+  s.o = static_cast<_Float16>(r - static_cast<float>(s.h));
+  return s;
+}
+
+// Same from an accumulator pair (a0 exact, a1 small) scaled by a power of two.
+__device__ __forceinline__ H3 split_acc(float a0, float a1, float c) {
+  float y0 = a0 * c, y1 = a1 * c;
+  float n0 = __builtin_rintf(y0 + y1);
+  float r = (y0 - n0) + y1;
+  H3 s;
+  s.l = static_cast<_Float16>(n0);
+  s.h = static_cast<_Float16>(r);
+  s.o = static_cast<_Float16>(r - static_cast<float>(s.h));
+  return s;
+}
+
+__device__ __forceinline__ void put(Split3& A, int t, const H3& s) {
+  A.l[t] = s.l;
+  A.h[t] = s.h;
+  A.o[t] = s.o;
+}
+
+// Left operand (K = 64: real part rows, then imaginary part rows) from a
+// complex result tile held as accumulator pairs.
+__device__ __forceinline__ void slice_tiles(const f32x16& r0, const f32x16& r1, const f32x16& i0,
+                                            const f32x16& i1, float c, Split3 A[4]) {
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    put(A[v >> 3], v & 7, split_acc(r0[v], r1[v], c));
+    put(A[2 + (v >> 3)], v & 7, split_acc(i0[v], i1[v], c));
+  }
+}
+
+__device__ __forceinline__ float tile_absmax(const f32x16& r0, const f32x16& r1, const f32x16& i0,
+                                             const f32x16& i1) {
+  float m = 0.0f;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    m = fmaxf(m, fabsf(r0[v] + r1[v]));
+    m = fmaxf(m, fabsf(i0[v] + i1[v]));
+  }
+  return wave_max(m);
+}
+
+// One complex DFT pass (K = 64) with DFT-matrix operands:
+//   real out = A_re * B[re_a] + A_im * B[re_b],  imag out = A_re * B[im_a] + A_im * B[im_b]
+// where the B index selects Er, Ei or -Ei (0, 1, 2).
+__device__ __forceinline__ void pass64(const Split3 A[4], const Split3 E[3][2], int re_a, int re_b,
+                                       int im_a, int im_b, bool want_im, f32x16& r0, f32x16& r1,
+                                       f32x16& i0, f32x16& i1) {
+  r0 = r1 = i0 = i1 = f32x16{};
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    mma6(A[s], E[re_a][s], r0, r1);
+    mma6(A[2 + s], E[re_b][s], r0, r1);
+    if (want_im) {
+      mma6(A[s], E[im_a][s], i0, i1);
+      mma6(A[2 + s], E[im_b][s], i0, i1);
+    }
+  }
+}
+
+enum { kEr = 0, kEi = 1, kNEi = 2 };
+
+template <int OUT>  // OUT: 0 eval float, 1 eval double (conserve), 2 step
+__global__ __launch_bounds__(256) void fx16_kernel(KernelArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int h = lane >> 5, c = lane & 31;
+  const int64_t wave = static_cast<int64_t>(blockIdx.x) * kWaves + (threadIdx.x >> 6);
+  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * kWaves;
+
+  // DFT-matrix operands (Er, Ei, -Ei; two K-slices; lead/hi/lo), per lane.
+  Split3 E[3][2];
+  {
+    const half8* src = reinterpret_cast<const half8*>(a.econst) + lane * 18;
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        E[m][s].l = src[(m * 2 + s) * 3 + 0];
+        E[m][s].h = src[(m * 2 + s) * 3 + 1];
+        E[m][s].o = src[(m * 2 + s) * 3 + 2];
+      }
+  }
+
+  for (int64_t cell = wave; cell < a.cells; cell += nwaves) {
+    const float* fc = a.f + cell * (kN * kN);
+    float fv[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) fv[v] = fc[rrow(v, h) * kN + c];
+
+    // ---- forward pass 1 (real input, contraction over the first axis)
+    float fm = 0.0f;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) fm = fmaxf(fm, fabsf(fv[v]));
+    fm = wave_max(fm);
+    const int a0 = 9 - exp_above(fm);
+    const float cf = ldexpf(1.0f, a0);
+    Split3 A[4];
+#pragma unroll
+    for (int v = 0; v < 16; ++v)
+      put(A[v >> 3], v & 7, split_f64(static_cast<double>(fv[v] * cf)));
+    f32x16 r0{}, r1{}, i0{}, i1{};
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      mma6(A[s], E[kEr][s], r0, r1);
+      mma6(A[s], E[kNEi][s], i0, i1);
+    }
+    int sc = -(a0 + 9);  // true value = accumulator * 2^sc
+
+    // ---- forward pass 2 (complex, contraction over the second axis)
+    int a1 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
+    slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a1), A);
+    pass64(A, E, kEr, kEi, kNEi, kEr, true, r0, r1, i0, i1);
+    sc = sc - a1 - 9;
+
+    // unnormalised spectrum in FP64, rescaled so that |f_hat| < 2^9
+    double fr[16], fi[16];
+    float fhm = 0.0f;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      fr[v] = static_cast<double>(r0[v]) + static_cast<double>(r1[v]);
+      fi[v] = static_cast<double>(i0[v]) + static_cast<double>(i1[v]);
+      fhm = fmaxf(fhm, fmaxf(fabsf(static_cast<float>(fr[v])), fabsf(static_cast<float>(fi[v]))));
+    }
+    fhm = wave_max(fhm * 1.0000002f);
+    const int bsh = 9 - (exp_above(fhm) + 1);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      fr[v] = ldexp(fr[v], bsh);
+      fi[v] = ldexp(fi[v], bsh);
+    }
+    const int s_fh = sc - bsh;  // true f_hat = fr * 2^s_fh
+
+    double gain[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) gain[v] = 0.0;
+
+    for (int q = 0; q <= a.P; ++q) {
+      const bool loss = (q == a.P);
+      int sq;
+      if (!loss) {
+        const double* mq = a.filt + (static_cast<int64_t>(q) * 64 + lane) * 32;
+        sq = a.filt_exp[q];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          double mr = mq[2 * v], mi = mq[2 * v + 1];
+          double yr = mr * fr[v] - mi * fi[v];
+          double yi = mr * fi[v] + mi * fr[v];
+          put(A[v >> 3], v & 7, split_f64(yr));
+          put(A[2 + (v >> 3)], v & 7, split_f64(yi));
+        }
+      } else {
+        const double* lq = a.loss + lane * 16;
+        sq = a.loss_exp;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          double m = lq[v];
+          put(A[v >> 3], v & 7, split_f64(m * fr[v]));
+          put(A[2 + (v >> 3)], v & 7, split_f64(m * fi[v]));
+        }
+      }
+      // inverse pass A (contraction over the first axis)
+      pass64(A, E, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
+      int sd = sq + s_fh - 9;
+      const int a2 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
+      slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a2), A);
+      // inverse pass B (second axis); the loss needs only the real part
+      pass64(A, E, kEr, kNEi, kEi, kEr, !loss, r0, r1, i0, i1);
+      sd = sd - a2 - 9;
+      if (!loss) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          double re = static_cast<double>(r0[v]) + static_cast<double>(r1[v]);
+          double im = static_cast<double>(i0[v]) + static_cast<double>(i1[v]);
+          gain[v] = fma(ldexp(re, 2 * sd), im, gain[v]);
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          double lf = ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), sd);
+          gain[v] = gain[v] - static_cast<double>(fv[v]) * lf;  // gain now holds Q
+        }
+      }
+    }
+    finish_cell<OUT>(a, cell, fv, gain, h, c);
+  }
+}
+
+// ------------------------------------------------------------ FP32 variant
+
+__device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+template <int OUT>
+__global__ __launch_bounds__(256) void fp32_kernel(KernelArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int h = lane >> 5, c = lane & 31;
+  const int64_t wave = static_cast<int64_t>(blockIdx.x) * kWaves + (threadIdx.x >> 6);
+  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * kWaves;
+  float Er[16], Ei[16], Ne[16];
+  {
+    const float* src = reinterpret_cast<const float*>(a.econst) + lane * 48;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      Er[v] = src[v];
+      Ei[v] = src[16 + v];
+      Ne[v] = src[32 + v];
+    }
+  }
+  for (int64_t cell = wave; cell < a.cells; cell += nwaves) {
+    const float* fc = a.f + cell * (kN * kN);
+    float fv[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) fv[v] = fc[rrow(v, h) * kN + c];
+    f32x16 re{}, im{};
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      re = mfma32(fv[v], Er[v], re);
+      im = mfma32(fv[v], Ne[v], im);
+    }
+    f32x16 fre{}, fim{};
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      fre = mfma32(re[v], Er[v], fre);
+      fre = mfma32(im[v], Ei[v], fre);
+      fim = mfma32(re[v], Ne[v], fim);
+      fim = mfma32(im[v], Er[v], fim);
+    }
+    double gain[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) gain[v] = 0.0;
+    for (int q = 0; q <= a.P; ++q) {
+      const bool loss = (q == a.P);
+      float zr[16], zi[16];
+      if (!loss) {
+        const float* mq = a.filt32 + (static_cast<int64_t>(q) * 64 + lane) * 32;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          float mr = mq[2 * v], mi = mq[2 * v + 1];
+          zr[v] = mr * fre[v] - mi * fim[v];
+          zi[v] = mr * fim[v] + mi * fre[v];
+        }
+      } else {
+        const float* lq = a.loss32 + lane * 16;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          zr[v] = lq[v] * fre[v];
+          zi[v] = lq[v] * fim[v];
+        }
+      }
+      f32x16 dr{}, di{};
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        dr = mfma32(zr[v], Er[v], dr);
+        dr = mfma32(zi[v], Ne[v], dr);
+        di = mfma32(zr[v], Ei[v], di);
+        di = mfma32(zi[v], Er[v], di);
+      }
+      f32x16 yr{}, yi{};
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        yr = mfma32(dr[v], Er[v], yr);
+        yr = mfma32(di[v], Ne[v], yr);
+        if (!loss) {
+          yi = mfma32(dr[v], Ei[v], yi);
+          yi = mfma32(di[v], Er[v], yi);
+        }
+      }
+      if (!loss) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) gain[v] += static_cast<double>(yr[v] * yi[v]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          gain[v] = gain[v] - static_cast<double>(fv[v]) * static_cast<double>(yr[v]);
+      }
+    }
+    finish_cell<OUT>(a, cell, fv, gain, h, c);
+  }
+}
+
+}  // namespace
+
+int launch_2d32(const KernelArgs& args, int precision, int out_kind, hipStream_t stream) {
+  if (args.cells <= 0) return 0;
+  int64_t blocks = (args.cells + kWaves - 1) / kWaves;
+  if (blocks > args.max_blocks) blocks = args.max_blocks;
+  dim3 grid(static_cast<unsigned>(blocks)), block(64 * kWaves);
+  if (precision == 4) {
+    if (out_kind == 0) hipLaunchKernelGGL(fx16_kernel<0>, grid, block, 0, stream, args);
+    else if (out_kind == 1) hipLaunchKernelGGL(fx16_kernel<1>, grid, block, 0, stream, args);
+    else hipLaunchKernelGGL(fx16_kernel<2>, grid, block, 0, stream, args);
+  } else {
+    if (out_kind == 0) hipLaunchKernelGGL(fp32_kernel<0>, grid, block, 0, stream, args);
+    else if (out_kind == 1) hipLaunchKernelGGL(fp32_kernel<1>, grid, block, 0, stream, args);
+    else hipLaunchKernelGGL(fp32_kernel<2>, grid, block, 0, stream, args);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+}  // namespace qcoll
