@@ -18,13 +18,14 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libqcoll.so")
 
 HOST_SOURCES = ["plan.cpp", "api.cpp"]
-DEVICE_SOURCES = ["kernels_2d.hip"]
+DEVICE_SOURCES = ["kernels_2d.hip", "kernels_2d16.hip"]
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}", "-I/opt/rocm/include", "-D__HIP_PLATFORM_AMD__"]
 # Packed FP32 VALU instructions are disabled in all device code.
+# MFMA accumulators are kept in VGPRs so that VALU code reads them directly.
 DEVICE_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                "-ffp-contract=fast"]
+                "-ffp-contract=fast", "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 
 
 def _hipcc() -> str:

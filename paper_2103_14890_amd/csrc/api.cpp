@@ -71,8 +71,14 @@ void free_device(qcoll_plan_s* p) {
 // the DFT-matrix rows rrow(.., h) of the right-hand operands.
 int build_device_2d32(qcoll_plan_s* p) {
   const auto& hp = p->hp;
-  const int N = 32;
+  const int n = hp.N;  // grid size <= 32; rows and columns >= n of the tile are zero
   const int P = static_cast<int>(hp.packed.size());
+  auto emat = [&](int m, int k, int j) -> double {
+    if (k >= n || j >= n) return 0.0;
+    double ang = 2.0 * kPi * static_cast<double>((k * j) % n) / n;
+    return m == 0 ? std::cos(ang) : (m == 1 ? std::sin(ang) : -std::sin(ang));
+  };
+  auto mode = [&](int r, int c) -> int64_t { return (r < n && c < n) ? static_cast<int64_t>(r) * n + c : -1; };
   if (p->precision == QCOLL_MIX_FX16) {
     // E[k][j] = exp(2 pi i k j / N) scaled by 2^9, split into lead/hi/lo halves:
     // [lane][mat (Er, Ei, -Ei)][K-slice s][part][t], value at row rrow(8s+t, h), column c
@@ -82,10 +88,7 @@ int build_device_2d32(qcoll_plan_s* p) {
       for (int m = 0; m < 3; ++m)
         for (int s = 0; s < 2; ++s)
           for (int t = 0; t < 8; ++t) {
-            int k = rrow(8 * s + t, h);
-            double ang = 2.0 * kPi * static_cast<double>((k * c) % N) / N;
-            double val = m == 0 ? std::cos(ang) : (m == 1 ? std::sin(ang) : -std::sin(ang));
-            double y = 512.0 * val;
+            double y = 512.0 * emat(m, rrow(8 * s + t, h), c);
             double lead = std::nearbyint(y);
             float r = static_cast<float>(y - lead);
             _Float16 hi = static_cast<_Float16>(r);
@@ -100,46 +103,41 @@ int build_device_2d32(qcoll_plan_s* p) {
     int rc = upload(ec, &d, p->device_bytes);
     p->econst = d;
     if (rc) return rc;
-    std::vector<double> ft(static_cast<size_t>(P) * 64 * 32);
-    std::vector<int> fe(P > 0 ? P : 1, 0);
-    for (int q = 0; q < P; ++q) {
+    // packed gain filters q < P, then the loss multiplier as entry P (imaginary
+    // part zero); each entry scaled by 2^-e so that its complex modulus is < 1
+    std::vector<double> ft(static_cast<size_t>(P + 1) * 64 * 32);
+    std::vector<int> fe(P + 1, 0);
+    for (int q = 0; q <= P; ++q) {
+      auto val = [&](int64_t k) -> std::complex<double> {
+        if (k < 0) return {0.0, 0.0};
+        return q < P ? hp.packed[q][k] : std::complex<double>(hp.loss_scaled[k], 0.0);
+      };
       double mx = 0.0;
-      for (const auto& z : hp.packed[q]) mx = std::fmax(mx, std::abs(z));
+      for (int64_t k = 0; k < static_cast<int64_t>(n) * n; ++k) mx = std::fmax(mx, std::abs(val(k)));
       int e = exp_above(mx);
       fe[q] = e;
       double sc = std::ldexp(1.0, -e);
       for (int lane = 0; lane < 64; ++lane) {
         int h = lane >> 5, c = lane & 31;
         for (int v = 0; v < 16; ++v) {
-          int k = rrow(v, h) * N + c;
+          int64_t k = mode(rrow(v, h), c);
           size_t o = (static_cast<size_t>(q) * 64 + lane) * 32 + 2 * v;
-          ft[o] = hp.packed[q][k].real() * sc;
-          ft[o + 1] = hp.packed[q][k].imag() * sc;
+          ft[o] = val(k).real() * sc;
+          ft[o + 1] = val(k).imag() * sc;
         }
       }
     }
     if ((rc = upload(ft, &p->filt, p->device_bytes))) return rc;
     if ((rc = upload(fe, &p->filt_exp, p->device_bytes))) return rc;
-    double lmx = 0.0;
-    for (double x : hp.loss_scaled) lmx = std::fmax(lmx, std::fabs(x));
-    p->loss_exp = exp_above(lmx);
-    std::vector<double> lt(64 * 16);
-    for (int lane = 0; lane < 64; ++lane)
-      for (int v = 0; v < 16; ++v)
-        lt[lane * 16 + v] =
-            std::ldexp(hp.loss_scaled[rrow(v, lane >> 5) * N + (lane & 31)], -p->loss_exp);
-    if ((rc = upload(lt, &p->loss, p->device_bytes))) return rc;
   } else {
     // FP32 32x32x2 operands: [lane][mat][v] = Mat[rrow(v, h)][c]
     std::vector<float> ec(64 * 48);
     for (int lane = 0; lane < 64; ++lane) {
       int h = lane >> 5, c = lane & 31;
       for (int v = 0; v < 16; ++v) {
-        int k = rrow(v, h);
-        double ang = 2.0 * kPi * static_cast<double>((k * c) % N) / N;
-        ec[lane * 48 + v] = static_cast<float>(std::cos(ang));
-        ec[lane * 48 + 16 + v] = static_cast<float>(std::sin(ang));
-        ec[lane * 48 + 32 + v] = static_cast<float>(-std::sin(ang));
+        ec[lane * 48 + v] = static_cast<float>(emat(0, rrow(v, h), c));
+        ec[lane * 48 + 16 + v] = static_cast<float>(emat(1, rrow(v, h), c));
+        ec[lane * 48 + 32 + v] = static_cast<float>(emat(2, rrow(v, h), c));
       }
     }
     float* d = nullptr;
@@ -150,19 +148,115 @@ int build_device_2d32(qcoll_plan_s* p) {
     for (int q = 0; q < P; ++q)
       for (int lane = 0; lane < 64; ++lane)
         for (int v = 0; v < 16; ++v) {
-          int k = rrow(v, lane >> 5) * N + (lane & 31);
+          int64_t k = mode(rrow(v, lane >> 5), lane & 31);
           size_t o = (static_cast<size_t>(q) * 64 + lane) * 32 + 2 * v;
-          ft[o] = static_cast<float>(hp.packed[q][k].real());
-          ft[o + 1] = static_cast<float>(hp.packed[q][k].imag());
+          ft[o] = k < 0 ? 0.0f : static_cast<float>(hp.packed[q][k].real());
+          ft[o + 1] = k < 0 ? 0.0f : static_cast<float>(hp.packed[q][k].imag());
         }
     if ((rc = upload(ft, &p->filt32, p->device_bytes))) return rc;
     std::vector<float> lt(64 * 16);
     for (int lane = 0; lane < 64; ++lane)
-      for (int v = 0; v < 16; ++v)
-        lt[lane * 16 + v] = static_cast<float>(hp.loss_scaled[rrow(v, lane >> 5) * N + (lane & 31)]);
+      for (int v = 0; v < 16; ++v) {
+        int64_t k = mode(rrow(v, lane >> 5), lane & 31);
+        lt[lane * 16 + v] = k < 0 ? 0.0f : static_cast<float>(hp.loss_scaled[k]);
+      }
     if ((rc = upload(lt, &p->loss32, p->device_bytes))) return rc;
   }
   return QCOLL_OK;
+}
+
+// Device tables of the 2D N = 16 kernels. Lane l = 16 g + n holds, for
+// register v, the mode (k1, k2) = (4 g + v, n). DFT operands per output part
+// ([4 real rows | 4 imaginary rows] of the contraction, see kernels_2d16.hip).
+int build_device_2d16(qcoll_plan_s* p) {
+  const auto& hp = p->hp;
+  const int n = hp.N;  // grid size <= 16; rows and columns >= n of the tile are zero
+  const int P = static_cast<int>(hp.packed.size());
+  auto mode = [&](int r, int c) -> int64_t { return (r < n && c < n) ? static_cast<int64_t>(r) * n + c : -1; };
+  // set -> (matrix for the real-part rows, matrix for the imaginary-part rows);
+  // 0 Er, 1 Ei, 2 -Ei
+  const int sets[4][2] = {{0, 1}, {2, 0}, {0, 2}, {1, 0}};
+  auto mat = [&](int m, int k, int j) -> double {
+    if (k >= n || j >= n) return 0.0;
+    double ang = 2.0 * kPi * static_cast<double>((k * j) % n) / n;
+    return m == 0 ? std::cos(ang) : (m == 1 ? std::sin(ang) : -std::sin(ang));
+  };
+  int rc;
+  if (p->precision == QCOLL_MIX_FX16) {
+    std::vector<_Float16> ec(64 * 4 * 3 * 8);
+    for (int lane = 0; lane < 64; ++lane) {
+      int g = lane >> 4, n = lane & 15;
+      for (int st = 0; st < 4; ++st)
+        for (int t = 0; t < 8; ++t) {
+          double y = 512.0 * mat(sets[st][t >> 2], 4 * g + (t & 3), n);
+          double lead = std::nearbyint(y);
+          float r = static_cast<float>(y - lead);
+          _Float16 hi = static_cast<_Float16>(r);
+          _Float16 lo = static_cast<_Float16>(r - static_cast<float>(hi));
+          size_t base = ((static_cast<size_t>(lane) * 4 + st) * 3) * 8 + t;
+          ec[base] = static_cast<_Float16>(static_cast<float>(lead));
+          ec[base + 8] = hi;
+          ec[base + 16] = lo;
+        }
+    }
+    _Float16* d = nullptr;
+    rc = upload(ec, &d, p->device_bytes);
+    p->econst = d;
+    if (rc) return rc;
+    std::vector<double> ft(static_cast<size_t>(P + 1) * 64 * 8);
+    std::vector<int> fe(P + 1, 0);
+    for (int q = 0; q <= P; ++q) {
+      auto val = [&](int64_t k) -> std::complex<double> {
+        if (k < 0) return {0.0, 0.0};
+        return q < P ? hp.packed[q][k] : std::complex<double>(hp.loss_scaled[k], 0.0);
+      };
+      double mx = 0.0;
+      for (int64_t k = 0; k < static_cast<int64_t>(n) * n; ++k) mx = std::fmax(mx, std::abs(val(k)));
+      fe[q] = exp_above(mx);
+      double sc = std::ldexp(1.0, -fe[q]);
+      for (int lane = 0; lane < 64; ++lane)
+        for (int v = 0; v < 4; ++v) {
+          int64_t k = mode(4 * (lane >> 4) + v, lane & 15);
+          size_t o = (static_cast<size_t>(q) * 64 + lane) * 8 + 2 * v;
+          ft[o] = val(k).real() * sc;
+          ft[o + 1] = val(k).imag() * sc;
+        }
+    }
+    if ((rc = upload(ft, &p->filt, p->device_bytes))) return rc;
+    if ((rc = upload(fe, &p->filt_exp, p->device_bytes))) return rc;
+  } else {
+    std::vector<float> ec(64 * 32);
+    for (int lane = 0; lane < 64; ++lane) {
+      int g = lane >> 4, n = lane & 15;
+      for (int st = 0; st < 4; ++st)
+        for (int part = 0; part < 2; ++part)
+          for (int v = 0; v < 4; ++v)
+            ec[lane * 32 + st * 8 + part * 4 + v] = static_cast<float>(mat(sets[st][part], 4 * g + v, n));
+    }
+    float* d = nullptr;
+    rc = upload(ec, &d, p->device_bytes);
+    p->econst = d;
+    if (rc) return rc;
+    std::vector<float> ft(static_cast<size_t>(P) * 64 * 8), lt(64 * 4);
+    for (int lane = 0; lane < 64; ++lane)
+      for (int v = 0; v < 4; ++v) {
+        int64_t k = mode(4 * (lane >> 4) + v, lane & 15);
+        for (int q = 0; q < P; ++q) {
+          size_t o = (static_cast<size_t>(q) * 64 + lane) * 8 + 2 * v;
+          ft[o] = k < 0 ? 0.0f : static_cast<float>(hp.packed[q][k].real());
+          ft[o + 1] = k < 0 ? 0.0f : static_cast<float>(hp.packed[q][k].imag());
+        }
+        lt[lane * 4 + v] = k < 0 ? 0.0f : static_cast<float>(hp.loss_scaled[k]);
+      }
+    if ((rc = upload(ft, &p->filt32, p->device_bytes))) return rc;
+    if ((rc = upload(lt, &p->loss32, p->device_bytes))) return rc;
+  }
+  return QCOLL_OK;
+}
+
+int launch(const qcoll_plan_s* p, const qcoll::KernelArgs& a, int out_kind, hipStream_t stream) {
+  if (p->hp.N > 16) return qcoll::launch_2d32(a, p->precision, out_kind, stream);
+  return qcoll::launch_2d16(a, p->precision, out_kind, stream);
 }
 
 qcoll::KernelArgs make_args(const qcoll_plan_s* p) {
@@ -176,13 +270,15 @@ qcoll::KernelArgs make_args(const qcoll_plan_s* p) {
   a.loss32 = p->loss32;
   a.P = static_cast<int>(p->hp.packed.size());
   for (int i = 0; i < 16 && i < static_cast<int>(p->hp.gram_inv.size()); ++i) a.gram_inv[i] = p->hp.gram_inv[i];
+  a.n = p->hp.N;
   a.L = p->hp.L;
   a.dv = 2.0 * p->hp.L / p->hp.N;
   a.max_blocks = p->max_blocks;
   return a;
 }
 
-bool device_supported(const qcoll::HostPlan& hp) { return hp.d == 2 && hp.N == 32; }
+// 2D grids up to 32 points per axis run on the 16x16 (N <= 16) or 32x32 tile kernels.
+bool device_supported(const qcoll::HostPlan& hp) { return hp.d == 2 && hp.N <= 32; }
 
 }  // namespace
 
@@ -217,7 +313,7 @@ int qcoll_plan(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, do
     int cus = 256;
     if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) cus = prop.multiProcessorCount;
     p->max_blocks = static_cast<int64_t>(cus) * 8;
-    rc = build_device_2d32(p);
+    rc = p->hp.N > 16 ? build_device_2d32(p) : build_device_2d16(p);
     if (rc) {
       free_device(p);
       delete p;
@@ -241,7 +337,7 @@ int qcoll_eval(qcoll_plan_t p, const float* f, void* Q, int64_t cells, hipStream
   a.q = Q;
   a.cells = cells;
   int out_kind = (p->flags & QCOLL_CONSERVE) ? 1 : 0;
-  return qcoll::launch_2d32(a, p->precision, out_kind, stream) ? QCOLL_EDEVICE : QCOLL_OK;
+  return launch(p, a, out_kind, stream) ? QCOLL_EDEVICE : QCOLL_OK;
 }
 
 int qcoll_step(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps, int scheme,
@@ -258,7 +354,7 @@ int qcoll_step(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps, i
   a.dt_eps = dt / eps;
   a.scheme = scheme;
   a.status = status;
-  return qcoll::launch_2d32(a, p->precision, 2, stream) ? QCOLL_EDEVICE : QCOLL_OK;
+  return launch(p, a, 2, stream) ? QCOLL_EDEVICE : QCOLL_OK;
 }
 
 int qcoll_plan_info(qcoll_plan_t p, int* transforms, int* K_r, double* R, int64_t* device_bytes) {

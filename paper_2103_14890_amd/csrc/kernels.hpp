@@ -11,6 +11,7 @@ struct KernelArgs {
   const float* f = nullptr;     // [cells][N^d] (updated in place by the step kernels)
   void* q = nullptr;            // [cells][N^d] float, or double with the projection
   int64_t cells = 0;
+  int n = 0;                    // grid points per axis (<= the kernel's tile size N)
   const void* econst = nullptr; // per-lane DFT-matrix operands (layout set by the variant)
   const double* filt = nullptr; // FX16: [P][64 lanes][16 modes][re, im], scaled by 2^-filt_exp
   const int* filt_exp = nullptr;
@@ -30,5 +31,6 @@ struct KernelArgs {
 // Launch the 2D N = 32 kernel. precision: 1 FP32, 4 FX16. out_kind: 0 eval
 // (float Q), 1 eval with projection (double Q), 2 stage update of f.
 int launch_2d32(const KernelArgs& args, int precision, int out_kind, hipStream_t stream);
+int launch_2d16(const KernelArgs& args, int precision, int out_kind, hipStream_t stream);
 
 }  // namespace qcoll

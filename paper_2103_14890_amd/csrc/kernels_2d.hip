@@ -32,107 +32,17 @@
 
 #include <cstdint>
 
-#include "kernels.hpp"
+#include "kernels_common.hpp"
 
 namespace qcoll {
 namespace {
 
-typedef _Float16 half8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
 constexpr int kN = 32;
-constexpr int kWaves = 4;  // wavefronts (cells) per workgroup
 
 __device__ __forceinline__ int rrow(int v, int h) { return 8 * (v >> 2) + 4 * h + (v & 3); }
 
-__device__ __forceinline__ float wave_max(float x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o));
-  return x;
-}
 
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-  return x;
-}
-
-// Exponent e with x < 2^e for x > 0 (0 for x == 0 or non-finite input).
-__device__ __forceinline__ int exp_above(float x) {
-  if (!(x > 0.0f) || !(x <= 3.0e38f)) return 0;
-  int e;
-  frexpf(x, &e);
-  return e;
-}
-
-// ------------------------------------------------------------- epilogue
-
-// Store Q, or apply the conservation projection (FP64 moments, wave
-// reductions) and store Q as double, or apply the stage update to f.
-template <int OUT>
-__device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, double* q, int h,
-                            int c) {
-  if (OUT == 0) {
-    float* Qc = reinterpret_cast<float*>(a.q) + cell * (kN * kN);
-#pragma unroll
-    for (int v = 0; v < 16; ++v) Qc[rrow(v, h) * kN + c] = static_cast<float>(q[v]);
-    return;
-  }
-  if (OUT == 1) {
-    // moments sum_j phi(v_j) Q_j with phi = (1, v1, v2, |v|^2); lambda = G^-1 m
-    const double v2c = -a.L + a.dv * c;
-    double m0 = 0, m1 = 0, m2 = 0, m3 = 0;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const double v1 = -a.L + a.dv * rrow(v, h);
-      m0 += q[v];
-      m1 += v1 * q[v];
-      m2 += v2c * q[v];
-      m3 += (v1 * v1 + v2c * v2c) * q[v];
-    }
-    m0 = wave_sum(m0);
-    m1 = wave_sum(m1);
-    m2 = wave_sum(m2);
-    m3 = wave_sum(m3);
-    double lam[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      lam[i] = a.gram_inv[i * 4 + 0] * m0 + a.gram_inv[i * 4 + 1] * m1 + a.gram_inv[i * 4 + 2] * m2 +
-               a.gram_inv[i * 4 + 3] * m3;
-    double* Qc = reinterpret_cast<double*>(a.q) + cell * (kN * kN);
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const double v1 = -a.L + a.dv * rrow(v, h);
-      double corr = lam[0] + lam[1] * v1 + lam[2] * v2c + lam[3] * (v1 * v1 + v2c * v2c);
-      Qc[rrow(v, h) * kN + c] = q[v] - corr;
-    }
-    return;
-  }
-  // OUT == 2: stage update in place
-  double rho = 0.0;
-#pragma unroll
-  for (int v = 0; v < 16; ++v) rho += static_cast<double>(fv[v]);
-  rho = wave_sum(rho) * a.dv * a.dv;
-  const double k = a.scheme == 1 ? a.dt_eps / (1.0 + a.dt_eps * rho) : a.dt_eps;
-  float* fcell = const_cast<float*>(a.f) + cell * (kN * kN);
-  int bad = 0;
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    float nv = static_cast<float>(static_cast<double>(fv[v]) + k * q[v]);
-    bad |= !(fabsf(nv) <= 3.0e38f);
-    fcell[rrow(v, h) * kN + c] = nv;
-  }
-  if (a.status) {
-    bad = __any(bad) ? 1 : 0;
-    if ((threadIdx.x & 63) == 0) a.status[cell] = bad;
-  }
-}
-
-// ------------------------------------------------------------ FX16 helpers
-
-struct Split3 {
-  half8 l, h, o;  // fixed-point lead, FP16 hi and lo of the remainder
-};
+// ------------------------------------------------------------ FX16 (N = 32)
 
 __device__ __forceinline__ f32x16 mfma16(half8 a, half8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
@@ -148,48 +58,47 @@ __device__ __forceinline__ void mma6(const Split3& a, const Split3& b, f32x16& a
   acc1 = mfma16(a.o, b.l, acc1);
 }
 
-struct H3 {
-  _Float16 l, h, o;
-};
-
-// Split y (|y| < 512.5) into lead = rint(y) and an FP16 hi/lo remainder.
-__device__ __forceinline__ H3 split_f64(double y) {
-  double n0 = __builtin_rint(y);
-  float r = static_cast<float>(y - n0);
-  H3 s;
-  s.l = static_cast<_Float16>(static_cast<float>(n0));
-  s.h = static_cast<_Float16>(r);
-  s.o = static_cast<_Float16>(r - static_cast<float>(s.h));
-  return s;
-}
-
-// Same from an accumulator pair (a0 exact, a1 small) scaled by a power of two.
-__device__ __forceinline__ H3 split_acc(float a0, float a1, float c) {
-  float y0 = a0 * c, y1 = a1 * c;
-  float n0 = __builtin_rintf(y0 + y1);
-  float r = (y0 - n0) + y1;
-  H3 s;
-  s.l = static_cast<_Float16>(n0);
-  s.h = static_cast<_Float16>(r);
-  s.o = static_cast<_Float16>(r - static_cast<float>(s.h));
-  return s;
-}
-
-__device__ __forceinline__ void put(Split3& A, int t, const H3& s) {
-  A.l[t] = s.l;
-  A.h[t] = s.h;
-  A.o[t] = s.o;
-}
-
 // Left operand (K = 64: real part rows, then imaginary part rows) from a
 // complex result tile held as accumulator pairs.
 __device__ __forceinline__ void slice_tiles(const f32x16& r0, const f32x16& r1, const f32x16& i0,
                                             const f32x16& i1, float c, Split3 A[4]) {
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    put(A[v >> 3], v & 7, split_acc(r0[v], r1[v], c));
-    put(A[2 + (v >> 3)], v & 7, split_acc(i0[v], i1[v], c));
+  for (int v = 0; v < 16; v += 2) {
+    put2(A[v >> 3], v & 7, split2_acc(r0[v], r1[v], r0[v + 1], r1[v + 1], c));
+    put2(A[2 + (v >> 3)], v & 7, split2_acc(i0[v], i1[v], i0[v + 1], i1[v + 1], c));
   }
+}
+
+__device__ __forceinline__ void load_filter(const double* mq, double* m) {
+  const double2* src = reinterpret_cast<const double2*>(mq);
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    double2 t = src[v];
+    m[2 * v] = t.x;
+    m[2 * v + 1] = t.y;
+  }
+}
+
+// Z = m * f_hat for modes v, v+1 of one packed filter (FP64 complex product,
+// |Z| < 2^9 by the scaling of m and f_hat), split into the left operand of the
+// first inverse pass.
+__device__ __forceinline__ void split_spectrum_pair(const double* m, const double* fr, const double* fi,
+                                                    Split3 A[4], int v) {
+  double yr[2], yi[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    double mr = m[2 * (v + u)], mi = m[2 * (v + u) + 1];
+    yr[u] = mr * fr[v + u] - mi * fi[v + u];
+    yi[u] = mr * fi[v + u] + mi * fr[v + u];
+  }
+  put2(A[v >> 3], v & 7, split2_f64(yr[0], yr[1]));
+  put2(A[2 + (v >> 3)], v & 7, split2_f64(yi[0], yi[1]));
+}
+
+__device__ __forceinline__ void split_spectrum(const double* m, const double* fr, const double* fi,
+                                               Split3 A[4]) {
+#pragma unroll
+  for (int v = 0; v < 16; v += 2) split_spectrum_pair(m, fr, fi, A, v);
 }
 
 __device__ __forceinline__ float tile_absmax(const f32x16& r0, const f32x16& r1, const f32x16& i0,
@@ -245,10 +154,8 @@ __global__ __launch_bounds__(256) void fx16_kernel(KernelArgs a) {
   }
 
   for (int64_t cell = wave; cell < a.cells; cell += nwaves) {
-    const float* fc = a.f + cell * (kN * kN);
     float fv[16];
-#pragma unroll
-    for (int v = 0; v < 16; ++v) fv[v] = fc[rrow(v, h) * kN + c];
+    load_cell<Lay32>(a, cell, lane, fv);
 
     // ---- forward pass 1 (real input, contraction over the first axis)
     float fm = 0.0f;
@@ -259,8 +166,8 @@ __global__ __launch_bounds__(256) void fx16_kernel(KernelArgs a) {
     const float cf = ldexpf(1.0f, a0);
     Split3 A[4];
 #pragma unroll
-    for (int v = 0; v < 16; ++v)
-      put(A[v >> 3], v & 7, split_f64(static_cast<double>(fv[v] * cf)));
+    for (int v = 0; v < 16; v += 2)
+      put2(A[v >> 3], v & 7, split2_f64(static_cast<double>(fv[v] * cf), static_cast<double>(fv[v + 1] * cf)));
     f32x16 r0{}, r1{}, i0{}, i1{};
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -297,54 +204,56 @@ __global__ __launch_bounds__(256) void fx16_kernel(KernelArgs a) {
 #pragma unroll
     for (int v = 0; v < 16; ++v) gain[v] = 0.0;
 
+    // Packed transforms q = 0..P-1 contribute Re * Im of their inverse DFT to the
+    // gain; entry P of the table is the real loss multiplier, whose inverse DFT
+    // (real part) is the loss field. Software pipeline: the spectrum of
+    // transform q+1 is formed and split while the MFMAs of pass B of transform q
+    // run.
+    double mbuf[32];
+    load_filter(a.filt + static_cast<int64_t>(lane) * 32, mbuf);
+    split_spectrum(mbuf, fr, fi, A);
+    int sd_last = 0;
     for (int q = 0; q <= a.P; ++q) {
-      const bool loss = (q == a.P);
-      int sq;
-      if (!loss) {
-        const double* mq = a.filt + (static_cast<int64_t>(q) * 64 + lane) * 32;
-        sq = a.filt_exp[q];
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          double mr = mq[2 * v], mi = mq[2 * v + 1];
-          double yr = mr * fr[v] - mi * fi[v];
-          double yi = mr * fi[v] + mi * fr[v];
-          put(A[v >> 3], v & 7, split_f64(yr));
-          put(A[2 + (v >> 3)], v & 7, split_f64(yi));
-        }
-      } else {
-        const double* lq = a.loss + lane * 16;
-        sq = a.loss_exp;
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          double m = lq[v];
-          put(A[v >> 3], v & 7, split_f64(m * fr[v]));
-          put(A[2 + (v >> 3)], v & 7, split_f64(m * fi[v]));
-        }
-      }
+      // prefetch the next filter; its loads complete under pass A
+      const int qn = q < a.P ? q + 1 : q;
+      load_filter(a.filt + (static_cast<int64_t>(qn) * 64 + lane) * 32, mbuf);
       // inverse pass A (contraction over the first axis)
       pass64(A, E, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
-      int sd = sq + s_fh - 9;
+      int sd = a.filt_exp[q] + s_fh - 9;
       const int a2 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
-      slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a2), A);
-      // inverse pass B (second axis); the loss needs only the real part
-      pass64(A, E, kEr, kNEi, kEi, kEr, !loss, r0, r1, i0, i1);
+      Split3 B[4];
+      slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a2), B);
+      // inverse pass B (second axis) in 8 chunks of 6 MFMAs, each followed by
+      // the split of two modes of the next spectrum (independent VALU work that
+      // executes while the matrix cores run)
+      r0 = r1 = i0 = i1 = f32x16{};
+#pragma unroll
+      for (int ch = 0; ch < 8; ++ch) {
+        const int s = ch >> 2, part = (ch >> 1) & 1, im = ch & 1;
+        const Split3& Aop = B[part ? 2 + s : s];
+        const Split3& Bop = E[im ? (part ? kEr : kEi) : (part ? kNEi : kEr)][s];
+        if (im) mma6(Aop, Bop, i0, i1);
+        else mma6(Aop, Bop, r0, r1);
+        split_spectrum_pair(mbuf, fr, fi, A, 2 * ch);
+        __builtin_amdgcn_sched_barrier(0);
+      }
       sd = sd - a2 - 9;
-      if (!loss) {
+      sd_last = sd;
+      const double w = q < a.P ? ldexp(1.0, 2 * sd) : 0.0;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          double re = static_cast<double>(r0[v]) + static_cast<double>(r1[v]);
-          double im = static_cast<double>(i0[v]) + static_cast<double>(i1[v]);
-          gain[v] = fma(ldexp(re, 2 * sd), im, gain[v]);
-        }
-      } else {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          double lf = ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), sd);
-          gain[v] = gain[v] - static_cast<double>(fv[v]) * lf;  // gain now holds Q
-        }
+      for (int v = 0; v < 16; ++v) {
+        double re = static_cast<double>(r0[v]) + static_cast<double>(r1[v]);
+        double im = static_cast<double>(i0[v]) + static_cast<double>(i1[v]);
+        gain[v] = fma(re * w, im, gain[v]);
       }
     }
-    finish_cell<OUT>(a, cell, fv, gain, h, c);
+    // the last transform is the loss field: Q = gain - f * loss
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      double lf = ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), sd_last);
+      gain[v] = gain[v] - static_cast<double>(fv[v]) * lf;
+    }
+    finish_cell<OUT, Lay32>(a, cell, fv, gain, lane);
   }
 }
 
@@ -371,10 +280,8 @@ __global__ __launch_bounds__(256) void fp32_kernel(KernelArgs a) {
     }
   }
   for (int64_t cell = wave; cell < a.cells; cell += nwaves) {
-    const float* fc = a.f + cell * (kN * kN);
     float fv[16];
-#pragma unroll
-    for (int v = 0; v < 16; ++v) fv[v] = fc[rrow(v, h) * kN + c];
+    load_cell<Lay32>(a, cell, lane, fv);
     f32x16 re{}, im{};
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -438,7 +345,7 @@ __global__ __launch_bounds__(256) void fp32_kernel(KernelArgs a) {
           gain[v] = gain[v] - static_cast<double>(fv[v]) * static_cast<double>(yr[v]);
       }
     }
-    finish_cell<OUT>(a, cell, fv, gain, h, c);
+    finish_cell<OUT, Lay32>(a, cell, fv, gain, lane);
   }
 }
 

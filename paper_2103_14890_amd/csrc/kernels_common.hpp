@@ -1,0 +1,208 @@
+// Device helpers shared by the 2D collision kernels (included by each .hip file).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace qcoll {
+namespace {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kWaves = 4;  // wavefronts (cells) per workgroup
+
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Wavefront-wide max of non-negative values with DPP moves only (no LDS):
+// rotations within each row of 16 lanes, then the row broadcasts of lanes 15
+// and 31; lane 63 ends with the maximum, which is read back as a uniform value.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_max(float x) {
+  int y = __builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), CTRL, ROWS, 0xf, false);
+  return fmaxf(x, __int_as_float(y));
+}
+
+__device__ __forceinline__ float wave_max(float x) {
+  x = dpp_max<0x121, 0xf>(x);  // row_ror:1
+  x = dpp_max<0x122, 0xf>(x);  // row_ror:2
+  x = dpp_max<0x124, 0xf>(x);  // row_ror:4
+  x = dpp_max<0x128, 0xf>(x);  // row_ror:8
+  x = dpp_max<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x = dpp_max<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+// Exponent e with x < 2^e for x > 0 (0 for x == 0 or non-finite input).
+__device__ __forceinline__ int exp_above(float x) {
+  if (!(x > 0.0f) || !(x <= 3.0e38f)) return 0;
+  int e;
+  frexpf(x, &e);
+  return e;
+}
+
+// Register layouts of one cell's N x N field across a wavefront: register v
+// of lane `lane` holds element (row(v, lane), col(lane)).
+struct Lay32 {  // 32x32 MFMA result tile
+  static constexpr int N = 32, V = 16;
+  __device__ static int row(int v, int lane) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
+  __device__ static int col(int lane) { return lane & 31; }
+};
+struct Lay16 {  // 16x16 MFMA result tile
+  static constexpr int N = 16, V = 4;
+  __device__ static int row(int v, int lane) { return 4 * (lane >> 4) + v; }
+  __device__ static int col(int lane) { return lane & 15; }
+};
+
+// ------------------------------------------------------------- epilogue
+
+// Store Q, or apply the conservation projection (FP64 moments, wave
+// reductions) and store Q as double, or apply the stage update to f.
+template <int OUT, class LY>
+__device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, double* q, int lane) {
+  constexpr int kV = LY::V;
+  const int n = a.n;
+  const int c = LY::col(lane);
+  const int64_t base = cell * static_cast<int64_t>(n) * n;
+  if (OUT == 0) {
+    float* Qc = reinterpret_cast<float*>(a.q) + base;
+#pragma unroll
+    for (int v = 0; v < kV; ++v) {
+      const int r = LY::row(v, lane);
+      if (r < n && c < n) Qc[r * n + c] = static_cast<float>(q[v]);
+    }
+    return;
+  }
+  if (OUT == 1) {
+    // moments sum_j phi(v_j) Q_j with phi = (1, v1, v2, |v|^2) (Q is zero
+    // outside the n x n grid); lambda = G^-1 m; Q <- Q - lambda . phi
+    const double v2c = -a.L + a.dv * c;
+    double m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+#pragma unroll
+    for (int v = 0; v < kV; ++v) {
+      const double v1 = -a.L + a.dv * LY::row(v, lane);
+      m0 += q[v];
+      m1 += v1 * q[v];
+      m2 += v2c * q[v];
+      m3 += (v1 * v1 + v2c * v2c) * q[v];
+    }
+    m0 = wave_sum(m0);
+    m1 = wave_sum(m1);
+    m2 = wave_sum(m2);
+    m3 = wave_sum(m3);
+    double lam[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      lam[i] = a.gram_inv[i * 4 + 0] * m0 + a.gram_inv[i * 4 + 1] * m1 + a.gram_inv[i * 4 + 2] * m2 +
+               a.gram_inv[i * 4 + 3] * m3;
+    double* Qc = reinterpret_cast<double*>(a.q) + base;
+#pragma unroll
+    for (int v = 0; v < kV; ++v) {
+      const int r = LY::row(v, lane);
+      const double v1 = -a.L + a.dv * r;
+      double corr = lam[0] + lam[1] * v1 + lam[2] * v2c + lam[3] * (v1 * v1 + v2c * v2c);
+      if (r < n && c < n) Qc[r * n + c] = q[v] - corr;
+    }
+    return;
+  }
+  // OUT == 2: stage update in place
+  double rho = 0.0;
+#pragma unroll
+  for (int v = 0; v < kV; ++v) rho += static_cast<double>(fv[v]);
+  rho = wave_sum(rho) * a.dv * a.dv;
+  const double k = a.scheme == 1 ? a.dt_eps / (1.0 + a.dt_eps * rho) : a.dt_eps;
+  float* fcell = const_cast<float*>(a.f) + base;
+  int bad = 0;
+#pragma unroll
+  for (int v = 0; v < kV; ++v) {
+    const int r = LY::row(v, lane);
+    float nv = static_cast<float>(static_cast<double>(fv[v]) + k * q[v]);
+    if (r < n && c < n) {
+      bad |= !(fabsf(nv) <= 3.0e38f);
+      fcell[r * n + c] = nv;
+    }
+  }
+  if (a.status) {
+    bad = __any(bad) ? 1 : 0;
+    if ((threadIdx.x & 63) == 0) a.status[cell] = bad;
+  }
+}
+
+// Load one cell's n x n field into a register layout, zero outside the grid.
+template <class LY>
+__device__ __forceinline__ void load_cell(const KernelArgs& a, int64_t cell, int lane, float* fv) {
+  const int n = a.n, c = LY::col(lane);
+  const float* fc = a.f + cell * static_cast<int64_t>(n) * n;
+#pragma unroll
+  for (int v = 0; v < LY::V; ++v) {
+    const int r = LY::row(v, lane);
+    fv[v] = (r < n && c < n) ? fc[r * n + c] : 0.0f;
+  }
+}
+
+// ------------------------------------------------------------ FX16 splits
+
+struct Split3 {
+  half8 l, h, o;  // fixed-point lead, FP16 hi and lo of the remainder
+};
+
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+
+// Pairwise split into lead / hi / lo FP16 parts. The conversions go through
+// v_cvt_pkrtz_f16_f32 (round toward zero): the lead is an exact small integer,
+// and whatever hi loses to rounding is carried by lo, so the rounding mode of
+// the conversion does not change the accuracy of the three-part sum.
+struct P3 {
+  half2v l, h, o;
+};
+
+typedef __fp16 fp16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ half2v pk(float a, float b) {
+  fp16x2 r = __builtin_amdgcn_cvt_pkrtz(a, b);
+  return __builtin_bit_cast(half2v, r);
+}
+
+__device__ __forceinline__ P3 finish_pair(float na, float nb, float ra, float rb) {
+  P3 s;
+  s.l = pk(na, nb);
+  s.h = pk(ra, rb);
+  s.o = pk(ra - static_cast<float>(s.h.x), rb - static_cast<float>(s.h.y));
+  return s;
+}
+
+// ya, yb already scaled so that |y| < 512.5 (FP64 inputs).
+__device__ __forceinline__ P3 split2_f64(double ya, double yb) {
+  double na = __builtin_rint(ya), nb = __builtin_rint(yb);
+  return finish_pair(static_cast<float>(na), static_cast<float>(nb), static_cast<float>(ya - na),
+                     static_cast<float>(yb - nb));
+}
+
+// From accumulator pairs (a0 exact, a1 small) scaled by the power of two c.
+__device__ __forceinline__ P3 split2_acc(float a0, float a1, float b0, float b1, float c) {
+  float ya = a0 * c, yb = b0 * c;
+  float na = __builtin_rintf(ya), nb = __builtin_rintf(yb);
+  return finish_pair(na, nb, fmaf(a1, c, ya - na), fmaf(b1, c, yb - nb));
+}
+
+__device__ __forceinline__ void put2(Split3& A, int t, const P3& s) {
+  A.l[t] = s.l.x;
+  A.l[t + 1] = s.l.y;
+  A.h[t] = s.h.x;
+  A.h[t + 1] = s.h.y;
+  A.o[t] = s.o.x;
+  A.o[t + 1] = s.o.y;
+}
+
+}  // namespace
+}  // namespace qcoll

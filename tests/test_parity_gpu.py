@@ -176,3 +176,86 @@ def test_grid_stride_and_determinism(qc):
     idx = np.array([0, 1, cells // 2, cells - 1])
     assert _rel(q1.cpu().double().numpy()[idx], _ref(f[idx], "maxwell", 8)) < 1e-5
     plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fx16", "fp32"])
+@pytest.mark.parametrize("kernel,M,L", [("maxwell", 16, 8.0), ("hard_sphere", 8, 8.0), ("hard_sphere", 8, 6.0)])
+def test_parity_n16(qc, precision, kernel, M, L):
+    f = wl.mixture_cells(2, 16, L, 21, 17)
+    plan = qc.Plan(2, 16, L, kernel, M, precision=precision)
+    q = _gpu_eval(plan, f)
+    ref = _ref(f, kernel, M, N=16, L=L)
+    err = _rel(q, ref)
+    print(f"N=16 {precision} {kernel} M={M} L={L}: rel L2 {err:.3e}")
+    assert err < TOL[precision]
+    plan.close()
+
+
+def test_n16_conserve_and_step(qc):
+    f = wl.mixture_cells(2, 16, 8.0, 10, 3)
+    plan = qc.Plan(2, 16, 8.0, "hard_sphere", 8, precision="fx16", conserve=True)
+    q = plan.eval(torch.tensor(f, dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    qn = q.cpu().numpy()
+    assert (np.abs(qn.sum(axis=(1, 2))) / np.abs(qn).sum(axis=(1, 2))).max() <= 1e-12
+    assert _rel(qn, sp.project_conservative(_ref(f, "hard_sphere", 8, N=16), 2, 8.0)) < 1e-5
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fx16", "fp32"])
+def test_bkw_config1_on_gpu(qc, precision):
+    """Config 1: BKW datum on [-8,8]^2, N = 16, Maxwell, M = 16, 100 explicit Euler
+    steps of dt = 0.01 with qcoll_step; the GPU trajectory follows the FP64 oracle's
+    and its error against the closed form at t = 1 matches the oracle's."""
+    from oracle.bkw import bkw_grid, error_norms
+    N, L = 16, 8.0
+    f0 = bkw_grid(N, L, 0.0)[None]
+    plan = qc.Plan(2, N, L, "maxwell", 16, precision=precision)
+    f = torch.tensor(f0, dtype=torch.float32, device="cuda")
+    for _ in range(100):
+        plan.step(f, 0.01, 1.0, "explicit")
+    torch.cuda.synchronize()
+    s = sp.Setup(d=2, N=N, L=L, kernel="maxwell", M=16)
+    bank = sp.filter_bank(s)
+    g = f0.astype(np.float64)
+    for _ in range(100):
+        g = g + 0.01 * sp.q_fast(g, s, bank)
+    got = f.cpu().double().numpy()
+    exact = bkw_grid(N, L, 1.0)[None]
+    e_gpu, e_ora = error_norms(got, exact), error_norms(g, exact)
+    print(f"BKW {precision}: GPU L1/L2/Linf {e_gpu}, oracle {e_ora}, traj diff {_rel(got, g):.2e}")
+    assert _rel(got, g) < (2e-6 if precision == "fx16" else 2e-5)
+    assert abs(e_gpu[0] - e_ora[0]) < 1e-3 * e_ora[0]
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fx16", "fp32"])
+@pytest.mark.parametrize("N,L,kernel,M", [(8, 4.0, "maxwell", 8), (12, 5.0, "hard_sphere", 8),
+                                          (24, 8.0, "hard_sphere", 8), (24, 8.0, "maxwell", 16),
+                                          (28, 7.0, "hard_sphere", 12)])
+def test_parity_padded_grids(qc, precision, N, L, kernel, M):
+    """Grids smaller than the kernel tile (zero-padded DFT operands and filters)."""
+    f = wl.mixture_cells(2, N, L, 13, 29)
+    plan = qc.Plan(2, N, L, kernel, M, precision=precision)
+    q = _gpu_eval(plan, f)
+    ref = _ref(f, kernel, M, N=N, L=L)
+    err = _rel(q, ref)
+    print(f"N={N} {precision} {kernel} M={M}: rel L2 {err:.3e}")
+    assert err < TOL[precision]
+    plan.close()
+
+
+def test_gpu_matches_real_space_brute_force(qc):
+    """The GPU operator equals the Carleman integrals evaluated in real space on
+    the trigonometric interpolant (oracle O3), with no Fourier multiplier formula."""
+    from oracle.brute import q_brute
+    N, L = 8, 4.0
+    f = wl.mixture_cells(2, N, L, 2, 31)
+    for kernel, K in [("maxwell", None), ("hard_sphere", 32)]:
+        plan = qc.Plan(2, N, L, kernel, 8, K_r=K or 0, precision="fx16")
+        q = _gpu_eval(plan, f)
+        s = sp.Setup(d=2, N=N, L=L, kernel=kernel, M=8, K_r=K)
+        for c in range(2):
+            qb = q_brute(f[c].astype(np.float32).astype(np.float64), s).reshape(N, N)
+            assert _rel(q[c], qb) < 1e-5
+        plan.close()
