@@ -71,15 +71,18 @@ enum {
 #define QCOLL_HOST_ONLY 0x100u /* build the FP64 host tables only (no device)  */
 
 /* Build a plan (section 3.3: directions, filters, loss multiplier; section
- * 3.1: grid). d in {2,3}; n_per_dim = N (currently N = 32 for d = 2 on the
- * device); L > 0 half-width of the velocity box; kernel QCOLL_MAXWELL or
+ * 3.1: grid). d in {2,3}; n_per_dim = N (even, 4..256); L > 0 half-width of
+ * the velocity box; kernel QCOLL_MAXWELL or
  * QCOLL_HARD_SPHERE; b kernel constant (<= 0: default); M number of collision
  * directions (the paper's A; even in 2D); K_r radial rank of the 2D
  * hard-sphere expansion (0: smallest rank with eigenvalue ratio < 1e-4;
  * ignored otherwise); precision one of the QCOLL_FP32 / QCOLL_MIX_FX16 values;
  * flags a combination of QCOLL_* flags. The plan owns its host and device
- * tables; it is immutable after creation and may be used from several streams
- * at once. On error *out is set to NULL. */
+ * tables; apart from its launch shape (qcoll_plan_set_launch, set before use)
+ * it is immutable and may be used from several streams at once. On error *out
+ * is set to NULL. Device plans: d = 2 with N <= 32 (grids below 16 or 32 run
+ * zero-padded in a 16x16 or 32x32 tile); larger grids and d = 3 are
+ * QCOLL_EUNSUPPORTED on the device (their host tables build). */
 int qcoll_plan(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, double b,
                int M, int K_r, int precision, unsigned flags);
 
@@ -101,6 +104,26 @@ int qcoll_eval(qcoll_plan_t plan, const float* f, void* Q, int64_t cells, hipStr
  * dt > 0 and eps > 0 are required. */
 int qcoll_step(qcoll_plan_t plan, float* f, int64_t cells, double dt, double eps, int scheme,
                int32_t* status, hipStream_t stream);
+
+/* Batched launches (cell-locality of section 3.3: cells of different velocity
+ * grids and kernels share one launch). Slot i uses plans[i] with f[i], Q[i]
+ * (or status[i]) and cells[i] exactly as the single-plan call; each cell's
+ * result is bitwise equal to the single-plan launch. nplans <= 8, all plans on
+ * one device; slots with cells[i] == 0 are skipped. status may be NULL. */
+int qcoll_eval_multi(const qcoll_plan_t* plans, int nplans, const float* const* f, void* const* Q,
+                     const int64_t* cells, hipStream_t stream);
+int qcoll_step_multi(const qcoll_plan_t* plans, int nplans, float* const* f, const int64_t* cells, double dt,
+                     double eps, int scheme, int32_t* const* status, hipStream_t stream);
+
+/* Launch shape of single-plan calls: cells per workgroup (1, 2 or 4) and the
+ * grid cap in workgroups (each wavefront loops over cells beyond it). */
+int qcoll_plan_set_launch(qcoll_plan_t plan, int waves_per_block, int64_t max_blocks);
+int qcoll_plan_get_launch(qcoll_plan_t plan, int* waves_per_block, int64_t* max_blocks);
+
+/* Autotuner: times every launch shape on the caller's f (device, cells cells)
+ * with HIP events, `reps` launches each, and keeps the fastest in the plan.
+ * Synchronises the stream; Q (device, as for qcoll_eval) is overwritten. */
+int qcoll_plan_autotune(qcoll_plan_t plan, const float* f, void* Q, int64_t cells, int reps, hipStream_t stream);
 
 /* Plan properties: number of DFT passes per cell (packed transforms incl. the
  * loss), radial rank, Carleman radius, and the device bytes the plan holds. */

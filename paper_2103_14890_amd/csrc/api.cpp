@@ -25,8 +25,12 @@ struct qcoll_plan_s {
   int loss_exp = 0;
   float* filt32 = nullptr;
   float* loss32 = nullptr;
+  double* tw = nullptr;
+  int tile = 32;
   int64_t device_bytes = 0;
-  int64_t max_blocks = 0;
+  int64_t max_blocks = 0;    // grid cap of single-plan launches
+  int waves_per_block = 4;   // cells per workgroup
+  int cus = 256;
 };
 
 namespace {
@@ -60,6 +64,8 @@ void free_device(qcoll_plan_s* p) {
   hipFree(p->loss);
   hipFree(p->filt32);
   hipFree(p->loss32);
+  hipFree(p->tw);
+  p->tw = nullptr;
   p->econst = nullptr;
   p->filt = p->loss = nullptr;
   p->filt_exp = nullptr;
@@ -254,9 +260,76 @@ int build_device_2d16(qcoll_plan_s* p) {
   return QCOLL_OK;
 }
 
-int launch(const qcoll_plan_s* p, const qcoll::KernelArgs& a, int out_kind, hipStream_t stream) {
-  if (p->hp.N > 16) return qcoll::launch_2d32(a, p->precision, out_kind, stream);
-  return qcoll::launch_2d16(a, p->precision, out_kind, stream);
+int launch(const qcoll::KernelArgs& a, hipStream_t stream) {
+  if (a.tile == 64) return qcoll::launch_2d64(a, stream);
+  return a.tile == 32 ? qcoll::launch_2d32(a, stream) : qcoll::launch_2d16(a, stream);
+}
+
+// Device tables of the tile-64 kernel (grids n = 2 n', n' <= 32): n'-point
+// DFT operands in the 32x32-tile order, the filters split into the four mode
+// quarters k = k' + n' a (one per wavefront), and the twiddles w^(k p).
+int build_device_2d64(qcoll_plan_s* p) {
+  const auto& hp = p->hp;
+  const int n = hp.N, np = n / 2;
+  const int P = static_cast<int>(hp.packed.size());
+  std::vector<_Float16> ec(64 * 3 * 2 * 3 * 8);
+  for (int lane = 0; lane < 64; ++lane) {
+    int h = lane >> 5, c = lane & 31;
+    for (int m = 0; m < 3; ++m)
+      for (int s = 0; s < 2; ++s)
+        for (int t = 0; t < 8; ++t) {
+          int k = rrow(8 * s + t, h);
+          double val = 0.0;
+          if (k < np && c < np) {
+            double ang = 2.0 * kPi * static_cast<double>((k * c) % np) / np;
+            val = m == 0 ? std::cos(ang) : (m == 1 ? std::sin(ang) : -std::sin(ang));
+          }
+          double y = 512.0 * val;
+          double lead = std::nearbyint(y);
+          float r = static_cast<float>(y - lead);
+          _Float16 hi = static_cast<_Float16>(r);
+          _Float16 lo = static_cast<_Float16>(r - static_cast<float>(hi));
+          size_t base = ((((static_cast<size_t>(lane) * 3 + m) * 2 + s) * 3) * 8) + t;
+          ec[base] = static_cast<_Float16>(static_cast<float>(lead));
+          ec[base + 8] = hi;
+          ec[base + 16] = lo;
+        }
+  }
+  _Float16* d = nullptr;
+  int rc = upload(ec, &d, p->device_bytes);
+  p->econst = d;
+  if (rc) return rc;
+  std::vector<double> ft(static_cast<size_t>(P + 1) * 4 * 64 * 32, 0.0);
+  std::vector<int> fe(P + 1, 0);
+  for (int q = 0; q <= P; ++q) {
+    auto val = [&](int64_t k) -> std::complex<double> {
+      return q < P ? hp.packed[q][k] : std::complex<double>(hp.loss_scaled[k], 0.0);
+    };
+    double mx = 0.0;
+    for (int64_t k = 0; k < static_cast<int64_t>(n) * n; ++k) mx = std::fmax(mx, std::abs(val(k)));
+    fe[q] = exp_above(mx);
+    double sc = std::ldexp(1.0, -fe[q]);
+    for (int w = 0; w < 4; ++w)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int v = 0; v < 16; ++v) {
+          int r = rrow(v, lane >> 5), c = lane & 31;
+          if (r >= np || c >= np) continue;
+          int64_t k = static_cast<int64_t>(r + np * (w >> 1)) * n + (c + np * (w & 1));
+          size_t o = ((static_cast<size_t>(q) * 4 + w) * 64 + lane) * 32 + 2 * v;
+          ft[o] = val(k).real() * sc;
+          ft[o + 1] = val(k).imag() * sc;
+        }
+  }
+  if ((rc = upload(ft, &p->filt, p->device_bytes))) return rc;
+  if ((rc = upload(fe, &p->filt_exp, p->device_bytes))) return rc;
+  std::vector<double> tw(2 * 32 * 2, 0.0);
+  for (int par = 0; par < 2; ++par)
+    for (int k = 0; k < 32; ++k) {
+      double ang = 2.0 * kPi * static_cast<double>(k * par) / n;
+      tw[(par * 32 + k) * 2] = std::cos(ang);
+      tw[(par * 32 + k) * 2 + 1] = std::sin(ang);
+    }
+  return upload(tw, &p->tw, p->device_bytes);
 }
 
 qcoll::KernelArgs make_args(const qcoll_plan_s* p) {
@@ -274,11 +347,20 @@ qcoll::KernelArgs make_args(const qcoll_plan_s* p) {
   a.L = p->hp.L;
   a.dv = 2.0 * p->hp.L / p->hp.N;
   a.max_blocks = p->max_blocks;
+  a.waves_per_block = p->waves_per_block;
+  a.tile = p->tile;
+  a.tw = p->tw;
+  a.precision = p->precision;
   return a;
 }
 
-// 2D grids up to 32 points per axis run on the 16x16 (N <= 16) or 32x32 tile kernels.
-bool device_supported(const qcoll::HostPlan& hp) { return hp.d == 2 && hp.N <= 32; }
+// 2D grids up to 32 points per axis run on the 16x16 (N <= 16) or 32x32 tile
+// kernels; grids of 34..64 points on the tile-64 kernel (FX16 only).
+bool device_supported(const qcoll::HostPlan& hp, int precision) {
+  if (hp.d != 2) return false;
+  if (hp.N <= 32) return true;
+  return hp.N <= 64 && precision == QCOLL_MIX_FX16;
+}
 
 }  // namespace
 
@@ -300,7 +382,7 @@ int qcoll_plan(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, do
     return rc;
   }
   if (!(flags & QCOLL_HOST_ONLY)) {
-    if (!device_supported(p->hp)) {
+    if (!device_supported(p->hp, precision)) {
       delete p;
       return QCOLL_EUNSUPPORTED;
     }
@@ -312,8 +394,10 @@ int qcoll_plan(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, do
     hipDeviceProp_t prop;
     int cus = 256;
     if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) cus = prop.multiProcessorCount;
+    p->cus = cus;
     p->max_blocks = static_cast<int64_t>(cus) * 8;
-    rc = p->hp.N > 16 ? build_device_2d32(p) : build_device_2d16(p);
+    p->tile = p->hp.N > 32 ? 64 : (p->hp.N > 16 ? 32 : 16);
+    rc = p->tile == 64 ? build_device_2d64(p) : (p->tile == 32 ? build_device_2d32(p) : build_device_2d16(p));
     if (rc) {
       free_device(p);
       delete p;
@@ -336,8 +420,8 @@ int qcoll_eval(qcoll_plan_t p, const float* f, void* Q, int64_t cells, hipStream
   a.f = f;
   a.q = Q;
   a.cells = cells;
-  int out_kind = (p->flags & QCOLL_CONSERVE) ? 1 : 0;
-  return launch(p, a, out_kind, stream) ? QCOLL_EDEVICE : QCOLL_OK;
+  a.out_kind = (p->flags & QCOLL_CONSERVE) ? 1 : 0;
+  return launch(a, stream) ? QCOLL_EDEVICE : QCOLL_OK;
 }
 
 int qcoll_step(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps, int scheme,
@@ -354,7 +438,126 @@ int qcoll_step(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps, i
   a.dt_eps = dt / eps;
   a.scheme = scheme;
   a.status = status;
-  return launch(p, a, 2, stream) ? QCOLL_EDEVICE : QCOLL_OK;
+  a.out_kind = 2;
+  return launch(a, stream) ? QCOLL_EDEVICE : QCOLL_OK;
+}
+
+// Shared by qcoll_eval_multi and qcoll_step_multi: validate the slot list and
+// build the batched launch (one workgroup per waves_per_block cells of a slot).
+static int multi_launch(const qcoll_plan_t* plans, int nplans, const float* const* f, void* const* Q,
+                        const int64_t* cells, bool step, double dt, double eps, int scheme,
+                        int32_t* const* status, hipStream_t stream) {
+  if (!plans || nplans < 0 || nplans > qcoll::kMaxSlots || !f || !cells) return QCOLL_EINVAL;
+  if (!step && !Q) return QCOLL_EINVAL;
+  if (step && (!(dt > 0.0) || !(eps > 0.0) || !std::isfinite(dt) || !std::isfinite(eps))) return QCOLL_EINVAL;
+  if (step && scheme != QCOLL_EXPLICIT_EULER && scheme != QCOLL_IMEX_EULER_PENALIZED) return QCOLL_EINVAL;
+  qcoll::MultiArgs m;
+  int wpb = 4, dev = -1;
+  int64_t blocks = 0;
+  for (int i = 0; i < nplans; ++i) {
+    const qcoll_plan_s* p = plans[i];
+    if (!p || cells[i] < 0) return QCOLL_EINVAL;
+    if (!p->on_device) return QCOLL_EUNSUPPORTED;
+    if (dev >= 0 && p->device != dev) return QCOLL_EINVAL;
+    dev = p->device;
+    if (cells[i] > 0 && (!f[i] || (!step && !Q[i]))) return QCOLL_EINVAL;
+    if (p->tile == 64) return QCOLL_EUNSUPPORTED;
+  }
+  for (int i = 0; i < nplans; ++i) {
+    if (cells[i] == 0) continue;
+    const qcoll_plan_s* p = plans[i];
+    qcoll::KernelArgs a = make_args(p);
+    a.f = f[i];
+    a.cells = cells[i];
+    if (step) {
+      a.dt_eps = dt / eps;
+      a.scheme = scheme;
+      a.status = status ? status[i] : nullptr;
+      a.out_kind = 2;
+    } else {
+      a.q = Q[i];
+      a.out_kind = (p->flags & QCOLL_CONSERVE) ? 1 : 0;
+    }
+    m.slot[m.nslots] = a;
+    m.block_start[m.nslots] = blocks;
+    blocks += (cells[i] + wpb - 1) / wpb;
+    ++m.nslots;
+  }
+  m.block_start[m.nslots] = blocks;
+  if (m.nslots == 0) return QCOLL_OK;
+  return qcoll::launch_multi(m, wpb, stream) ? QCOLL_EDEVICE : QCOLL_OK;
+}
+
+int qcoll_eval_multi(const qcoll_plan_t* plans, int nplans, const float* const* f, void* const* Q,
+                     const int64_t* cells, hipStream_t stream) {
+  return multi_launch(plans, nplans, f, Q, cells, false, 0.0, 0.0, 0, nullptr, stream);
+}
+
+int qcoll_step_multi(const qcoll_plan_t* plans, int nplans, float* const* f, const int64_t* cells, double dt,
+                     double eps, int scheme, int32_t* const* status, hipStream_t stream) {
+  return multi_launch(plans, nplans, const_cast<const float* const*>(f), nullptr, cells, true, dt, eps, scheme,
+                      status, stream);
+}
+
+int qcoll_plan_set_launch(qcoll_plan_t p, int waves_per_block, int64_t max_blocks) {
+  if (!p) return QCOLL_EINVAL;
+  if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4) return QCOLL_EINVAL;
+  if (max_blocks < 1) return QCOLL_EINVAL;
+  p->waves_per_block = waves_per_block;
+  p->max_blocks = max_blocks;
+  return QCOLL_OK;
+}
+
+int qcoll_plan_get_launch(qcoll_plan_t p, int* waves_per_block, int64_t* max_blocks) {
+  if (!p) return QCOLL_EINVAL;
+  if (waves_per_block) *waves_per_block = p->waves_per_block;
+  if (max_blocks) *max_blocks = p->max_blocks;
+  return QCOLL_OK;
+}
+
+// Time every launch shape (cells per workgroup x grid cap) on the caller's
+// data with HIP events and keep the fastest in the plan. Synchronises the
+// stream. Q receives the result of the last timed launch.
+int qcoll_plan_autotune(qcoll_plan_t p, const float* f, void* Q, int64_t cells, int reps, hipStream_t stream) {
+  if (!p || !f || !Q || cells < 1 || reps < 1) return QCOLL_EINVAL;
+  if (!p->on_device) return QCOLL_EUNSUPPORTED;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return QCOLL_EDEVICE;
+  const int wpbs[3] = {1, 2, 4};
+  const int64_t caps[4] = {1, 2, 8, 1 << 30};  // multiples of the CU count; last = one wave per cell
+  float best = 1e30f;
+  int best_w = p->waves_per_block;
+  int64_t best_b = p->max_blocks;
+  int rc = QCOLL_OK;
+  for (int w : wpbs)
+    for (int64_t c : caps) {
+      qcoll::KernelArgs a = make_args(p);
+      a.f = f;
+      a.q = Q;
+      a.cells = cells;
+      a.out_kind = (p->flags & QCOLL_CONSERVE) ? 1 : 0;
+      a.waves_per_block = w;
+      a.max_blocks = c >= (1 << 30) ? (int64_t{1} << 40) : c * p->cus * (4 / w);
+      if (launch(a, stream)) { rc = QCOLL_EDEVICE; break; }  // warm-up
+      hipEventRecord(e0, stream);
+      for (int r = 0; r < reps; ++r) launch(a, stream);
+      hipEventRecord(e1, stream);
+      if (hipEventSynchronize(e1) != hipSuccess) { rc = QCOLL_EDEVICE; break; }
+      float ms = 0.0f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) {
+        best = ms;
+        best_w = w;
+        best_b = a.max_blocks;
+      }
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc == QCOLL_OK) {
+    p->waves_per_block = best_w;
+    p->max_blocks = best_b;
+  }
+  return rc;
 }
 
 int qcoll_plan_info(qcoll_plan_t p, int* transforms, int* K_r, double* R, int64_t* device_bytes) {

@@ -17,6 +17,7 @@ struct KernelArgs {
   const int* filt_exp = nullptr;
   const double* loss = nullptr; // FX16: [64 lanes][16 modes], scaled by 2^-loss_exp
   int loss_exp = 0;
+  const double* tw = nullptr;   // tile-64 kernel: w^(k p), [p in {0,1}][k < 32][re, im]
   const float* filt32 = nullptr;  // FP32: [P][64][16][re, im]
   const float* loss32 = nullptr;  // FP32: [64][16]
   int P = 0;                    // packed gain transforms
@@ -25,12 +26,27 @@ struct KernelArgs {
   double dt_eps = 0;            // dt / eps
   int scheme = 0;
   int32_t* status = nullptr;
-  int64_t max_blocks = 1 << 20;
+  int out_kind = 0;             // 0 eval (float Q), 1 eval with projection (double Q), 2 step
+  int tile = 32;                // MFMA tile of the kernel: 16 or 32
+  int precision = 4;            // 1 FP32, 4 FX16
+  int waves_per_block = 4;      // launch shape (1, 2 or 4 wavefronts, one cell each)
+  int64_t max_blocks = 1 << 20; // grid cap; waves loop over cells beyond it
 };
 
-// Launch the 2D N = 32 kernel. precision: 1 FP32, 4 FX16. out_kind: 0 eval
-// (float Q), 1 eval with projection (double Q), 2 stage update of f.
-int launch_2d32(const KernelArgs& args, int precision, int out_kind, hipStream_t stream);
-int launch_2d16(const KernelArgs& args, int precision, int out_kind, hipStream_t stream);
+// Batched launch over several plans: slot s owns workgroups
+// [block_start[s], block_start[s+1]) of the grid.
+constexpr int kMaxSlots = 8;
+struct MultiArgs {
+  int nslots = 0;
+  int64_t block_start[kMaxSlots + 1] = {};
+  KernelArgs slot[kMaxSlots];
+};
+
+// Single-plan launches (args.tile selects the 16x16 or 32x32 kernel family).
+int launch_2d16(const KernelArgs& args, hipStream_t stream);
+int launch_2d32(const KernelArgs& args, hipStream_t stream);
+int launch_2d64(const KernelArgs& args, hipStream_t stream);
+// One launch over several plans (cells of different grids in one grid).
+int launch_multi(const MultiArgs& args, int waves_per_block, hipStream_t stream);
 
 }  // namespace qcoll

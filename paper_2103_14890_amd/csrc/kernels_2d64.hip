@@ -1,0 +1,293 @@
+// Fast spectral collision operator, 2D velocity grids of n = 2 n' points per
+// axis with n' <= 32 (n = 36..64, e.g. 48 and 64), gfx950.
+//
+// One workgroup of four wavefronts evaluates one cell. The n-point DFTs are
+// split once by parity (radix 2) into n'-point DFTs that run on the
+// register-resident 32x32-tile machinery of the N <= 32 kernels:
+//
+//   forward:  f_hat[k' + n'a] = sum_p (-1)^(a.p) w^(-k'.p) F_p[k'],
+//             F_p = n'-point 2D DFT of the sub-grid f[2m + p]
+//   inverse:  y[2m + p] = n'-point 2D inverse DFT over k' of
+//             G_p[k'] = w^(k'.p) sum_a (-1)^(a.p) Z[k' + n'a]
+//
+// with w = exp(2 pi i / n), a, p in {0,1}^2 (one per axis) and k' in
+// [0, n')^2. Wavefront w = 2 w1 + w2 holds the mode quarter a = (w1, w2) of
+// the spectrum (f_hat and the filter values there) and computes the output
+// parity class p = (w1, w2) of the grid. Between the two roles the quarters
+// are exchanged through LDS in FP64 (true values), once for the forward
+// transform and once per filter. The row twiddle w^(k1' p1) comes from a small
+// broadcast table in LDS, the column twiddle w^(k2' p2) is one complex number
+// per lane.
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "body_t32.hpp"
+
+namespace qcoll {
+namespace {
+
+// LDS: four complex FP64 32x32 slots in [slot][register][lane] order (a lane's
+// 16-byte value for register v of slot s sits at (s * 16 + v) * 64 + lane), the
+// row-twiddle table [p1][k1'] and a small reduction area.
+constexpr int kZSlot = 16 * 64;                      // complex values per slot
+constexpr int kLdsBytes = (4 * kZSlot + 2 * 32 + 8 * 4) * 16;
+
+struct Cd {
+  double x, y;
+};
+
+__device__ __forceinline__ Cd cmul(Cd a, Cd b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+
+template <int OUT>
+__global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
+  extern __shared__ double lds[];
+  Cd* zs = reinterpret_cast<Cd*>(lds);                 // [4][16][64]
+  Cd* tw = zs + 4 * kZSlot;                            // [2][32]
+  double* red = reinterpret_cast<double*>(tw + 64);    // [4 waves][4]
+
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int p1 = w >> 1, p2 = w & 1;                   // parity class = mode quarter
+  const int h = lane >> 5, c = lane & 31;
+  const int n = a.n, np = n >> 1;
+
+  // row twiddles w^(k1' p1) for both parities, column twiddle of this lane
+  for (int i = threadIdx.x; i < 64; i += blockDim.x) tw[i] = {a.tw[2 * i], a.tw[2 * i + 1]};
+  const Cd c2 = {a.tw[2 * (32 * p2 + c)], a.tw[2 * (32 * p2 + c) + 1]};
+  __syncthreads();
+
+  Split3 E[3][2];
+  {
+    const half8* src = reinterpret_cast<const half8*>(a.econst) + lane * 18;
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        E[m][s].l = src[(m * 2 + s) * 3 + 0];
+        E[m][s].h = src[(m * 2 + s) * 3 + 1];
+        E[m][s].o = src[(m * 2 + s) * 3 + 2];
+      }
+  }
+  const double sgn[4] = {1.0, (p2 ? -1.0 : 1.0), (p1 ? -1.0 : 1.0), ((p1 ^ p2) ? -1.0 : 1.0)};
+
+  for (int64_t cell = blockIdx.x; cell < a.cells; cell += gridDim.x) {
+    // ---- own parity sub-grid x[m1][m2] = f[2 m1 + p1][2 m2 + p2]
+    const float* fc = a.f + cell * static_cast<int64_t>(n) * n;
+    float fv[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int r = rrow(v, h);
+      fv[v] = (r < np && c < np) ? fc[(2 * r + p1) * n + 2 * c + p2] : 0.0f;
+    }
+    // ---- n'-point 2D DFT of the sub-grid (as in the N <= 32 kernel)
+    float fm = 0.0f;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) fm = fmaxf(fm, fabsf(fv[v]));
+    fm = wave_max(fm);
+    const int a0 = 9 - exp_above(fm);
+    const float cf = ldexpf(1.0f, a0);
+    Split3 A[4];
+#pragma unroll
+    for (int v = 0; v < 16; v += 2)
+      put2(A[v >> 3], v & 7, split2_f64(static_cast<double>(fv[v] * cf), static_cast<double>(fv[v + 1] * cf)));
+    f32x16 r0{}, r1{}, i0{}, i1{};
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      mma6(A[s], E[kEr][s], r0, r1);
+      mma6(A[s], E[kNEi][s], i0, i1);
+    }
+    int sc = -(a0 + 9);
+    const int a1 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
+    slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a1), A);
+    pass64(A, E, kEr, kEi, kNEi, kEr, true, r0, r1, i0, i1);
+    sc = sc - a1 - 9;
+    // ---- twiddle w^(-k'.p) and exchange: T_p -> f_hat quarter a = w
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const Cd t1 = tw[32 * p1 + rrow(v, h)];
+      const Cd tt = cmul({t1.x, -t1.y}, {c2.x, -c2.y});
+      const Cd F = {ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), sc),
+                    ldexp(static_cast<double>(i0[v]) + static_cast<double>(i1[v]), sc)};
+      zs[(w * 16 + v) * 64 + lane] = cmul(tt, F);
+    }
+    __syncthreads();
+    double fr[16], fi[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const Cd t = zs[(s * 16 + v) * 64 + lane];
+        sr += sgn[s] * t.x;
+        si += sgn[s] * t.y;
+      }
+      fr[v] = sr;
+      fi[v] = si;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+
+    double gain[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) gain[v] = 0.0;
+    int sd_last = 0;
+    for (int q = 0; q <= a.P; ++q) {
+      // filtered quarter Z_a (true values) to LDS, with its max |component|
+      const double* mq = a.filt + ((static_cast<int64_t>(q) * 4 + w) * 64 + lane) * 32;
+      const double zsc = ldexp(1.0, a.filt_exp[q]);
+      float zm = 0.0f;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const double mr = mq[2 * v] * zsc, mi = mq[2 * v + 1] * zsc;
+        const Cd z = {mr * fr[v] - mi * fi[v], mr * fi[v] + mi * fr[v]};
+        zs[(w * 16 + v) * 64 + lane] = z;
+        zm = fmaxf(zm, fmaxf(fabsf(static_cast<float>(z.x)), fabsf(static_cast<float>(z.y))));
+      }
+      zm = wave_max(zm);
+      if (lane == 0) red[w * 4 + 3] = zm;
+      __syncthreads();
+      // |G_p| <= sum_a max |Z_a| (twiddles have modulus one): common slicing scale
+      const float gb = static_cast<float>(red[3] + red[7] + red[11] + red[15]) * 1.0000005f;
+      const int b = 9 - (exp_above(gb) + 1);
+      // G_p = w^(k'.p) sum_a (-1)^(a.p) Z_a for this wave's parity class, split
+      // into the left operand of the first inverse pass as it is formed
+#pragma unroll
+      for (int v = 0; v < 16; v += 2) {
+        double gr[2], gi[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          double sr = 0.0, si = 0.0;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const Cd t = zs[(s * 16 + v + u) * 64 + lane];
+            sr += sgn[s] * t.x;
+            si += sgn[s] * t.y;
+          }
+          const Cd g = cmul(cmul(tw[32 * p1 + rrow(v + u, h)], c2), {sr, si});
+          gr[u] = ldexp(g.x, b);
+          gi[u] = ldexp(g.y, b);
+        }
+        put2(A[v >> 3], v & 7, split2_f64(gr[0], gr[1]));
+        put2(A[2 + (v >> 3)], v & 7, split2_f64(gi[0], gi[1]));
+        __builtin_amdgcn_sched_barrier(0);  // bound the LDS reads in flight
+      }
+      __syncthreads();
+      pass64(A, E, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
+      int sd = -b - 9;
+      const int a2 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
+      slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a2), A);
+      pass64(A, E, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
+      sd = sd - a2 - 9;
+      sd_last = sd;
+      const double wq = q < a.P ? ldexp(1.0, 2 * sd) : 0.0;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        double re = static_cast<double>(r0[v]) + static_cast<double>(r1[v]);
+        double im = static_cast<double>(i0[v]) + static_cast<double>(i1[v]);
+        gain[v] = fma(re * wq, im, gain[v]);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v)
+      gain[v] -= static_cast<double>(fv[v]) * ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), sd_last);
+
+    // ---- epilogue on this wave's parity class; cell-wide sums through LDS
+    const double v2c = -a.L + a.dv * (2 * c + p2);
+    if (OUT == 0) {
+      float* Qc = reinterpret_cast<float*>(a.q) + cell * static_cast<int64_t>(n) * n;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int r = rrow(v, h);
+        if (r < np && c < np) Qc[(2 * r + p1) * n + 2 * c + p2] = static_cast<float>(gain[v]);
+      }
+    } else if (OUT == 1) {
+      double m[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const double v1 = -a.L + a.dv * (2 * rrow(v, h) + p1);
+        m[0] += gain[v];
+        m[1] += v1 * gain[v];
+        m[2] += v2c * gain[v];
+        m[3] += (v1 * v1 + v2c * v2c) * gain[v];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) m[i] = wave_sum(m[i]);
+      if (lane == 0)
+        for (int i = 0; i < 4; ++i) red[w * 4 + i] = m[i];
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 4; ++i) m[i] = red[i] + red[4 + i] + red[8 + i] + red[12 + i];
+      __syncthreads();
+      double lam[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        lam[i] = a.gram_inv[i * 4 + 0] * m[0] + a.gram_inv[i * 4 + 1] * m[1] + a.gram_inv[i * 4 + 2] * m[2] +
+                 a.gram_inv[i * 4 + 3] * m[3];
+      double* Qc = reinterpret_cast<double*>(a.q) + cell * static_cast<int64_t>(n) * n;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int r = rrow(v, h);
+        const double v1 = -a.L + a.dv * (2 * r + p1);
+        const double corr = lam[0] + lam[1] * v1 + lam[2] * v2c + lam[3] * (v1 * v1 + v2c * v2c);
+        if (r < np && c < np) Qc[(2 * r + p1) * n + 2 * c + p2] = gain[v] - corr;
+      }
+    } else {
+      double rho = 0.0;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) rho += static_cast<double>(fv[v]);
+      rho = wave_sum(rho);
+      if (lane == 0) red[w * 4] = rho;
+      __syncthreads();
+      rho = (red[0] + red[4] + red[8] + red[12]) * a.dv * a.dv;
+      __syncthreads();
+      const double k = a.scheme == 1 ? a.dt_eps / (1.0 + a.dt_eps * rho) : a.dt_eps;
+      float* fcell = const_cast<float*>(a.f) + cell * static_cast<int64_t>(n) * n;
+      int bad = 0;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int r = rrow(v, h);
+        const float nv = static_cast<float>(static_cast<double>(fv[v]) + k * gain[v]);
+        if (r < np && c < np) {
+          bad |= !(fabsf(nv) <= 3.0e38f);
+          fcell[(2 * r + p1) * n + 2 * c + p2] = nv;
+        }
+      }
+      if (a.status) {
+        bad = __any(bad) ? 1 : 0;
+        if (lane == 0) red[w * 4 + 1] = bad;
+        __syncthreads();
+        if (threadIdx.x == 0)
+          a.status[cell] = (red[1] + red[5] + red[9] + red[13]) > 0 ? 1 : 0;
+        __syncthreads();
+      }
+    }
+  }
+}
+
+}  // namespace
+
+int launch_2d64(const KernelArgs& args, hipStream_t stream) {
+  if (args.cells <= 0) return 0;
+  if (args.precision != 4) return -4;
+  int64_t blocks = args.cells;
+  if (blocks > args.max_blocks) blocks = args.max_blocks;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<0>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<1>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<2>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    attr_set = true;
+  }
+  dim3 grid(static_cast<unsigned>(blocks)), block(256);
+  if (args.out_kind == 0) hipLaunchKernelGGL(fx16_t64_kernel<0>, grid, block, kLdsBytes, stream, args);
+  else if (args.out_kind == 1) hipLaunchKernelGGL(fx16_t64_kernel<1>, grid, block, kLdsBytes, stream, args);
+  else hipLaunchKernelGGL(fx16_t64_kernel<2>, grid, block, kLdsBytes, stream, args);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+}  // namespace qcoll

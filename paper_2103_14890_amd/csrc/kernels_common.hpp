@@ -13,7 +13,6 @@ namespace {
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kWaves = 4;  // wavefronts (cells) per workgroup
 
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -70,6 +69,12 @@ struct Lay16 {  // 16x16 MFMA result tile
 // reductions) and store Q as double, or apply the stage update to f.
 template <int OUT, class LY>
 __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, double* q, int lane) {
+  if constexpr (OUT < 0) {  // epilogue chosen at run time (batched launches)
+    if (a.out_kind == 0) finish_cell<0, LY>(a, cell, fv, q, lane);
+    else if (a.out_kind == 1) finish_cell<1, LY>(a, cell, fv, q, lane);
+    else finish_cell<2, LY>(a, cell, fv, q, lane);
+    return;
+  }
   constexpr int kV = LY::V;
   const int n = a.n;
   const int c = LY::col(lane);

@@ -1,0 +1,46 @@
+// Batched launch over several plans: cells of different velocity grids (and
+// arithmetic variants) in one grid. The operator is cell-local (section 3.3),
+// so every cell runs exactly the code of its single-plan launch and the
+// results are bitwise equal to separate launches. Workgroups are assigned to
+// slots by contiguous ranges; a workgroup finds its slot with a short scan of
+// the slot table (at most kMaxSlots entries) and then walks its slot's cells.
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "body_t16.hpp"
+#include "body_t32.hpp"
+
+namespace qcoll {
+namespace {
+
+__global__ __launch_bounds__(256) void multi_kernel(MultiArgs m) {
+  const int64_t b = blockIdx.x;
+  int s = 0;
+#pragma unroll 1
+  while (s + 1 < m.nslots && b >= m.block_start[s + 1]) ++s;
+  const KernelArgs& a = m.slot[s];
+  const int wpb = blockDim.x >> 6;
+  const int64_t first = (b - m.block_start[s]) * wpb + (threadIdx.x >> 6);
+  const int64_t stride = (m.block_start[s + 1] - m.block_start[s]) * wpb;
+  if (a.tile == 32) {
+    if (a.precision == 4) fx16_t32_body<-1>(a, first, stride);
+    else fp32_t32_body<-1>(a, first, stride);
+  } else {
+    if (a.precision == 4) fx16_t16_body<-1>(a, first, stride);
+    else fp32_t16_body<-1>(a, first, stride);
+  }
+}
+
+}  // namespace
+
+int launch_multi(const MultiArgs& args, int waves_per_block, hipStream_t stream) {
+  const int64_t blocks = args.block_start[args.nslots];
+  if (blocks <= 0) return 0;
+  hipLaunchKernelGGL(multi_kernel, dim3(static_cast<unsigned>(blocks)), dim3(64 * waves_per_block), 0,
+                     stream, args);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+}  // namespace qcoll

@@ -36,6 +36,15 @@ class QcollError(RuntimeError):
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2103_14890_amd.build`")
+    # The device buffers and streams passed in come from PyTorch's HIP runtime,
+    # so the library must bind to that same runtime instance: load torch (and
+    # with it its libamdhip64) first, so that libqcoll's libamdhip64.so.7
+    # dependency resolves to the copy already in the process instead of
+    # bringing a second HIP/HSA runtime along.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp, i64, dbl, c_int = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
     lib.qcoll_plan.argtypes = [ctypes.POINTER(vp), c_int, c_int, dbl, c_int, dbl, c_int, c_int, c_int,
@@ -50,6 +59,18 @@ def _load() -> ctypes.CDLL:
     lib.qcoll_plan_info.restype = c_int
     lib.qcoll_plan_table.argtypes = [vp, c_int, c_int, ctypes.POINTER(dbl), i64]
     lib.qcoll_plan_table.restype = c_int
+    lib.qcoll_eval_multi.argtypes = [ctypes.POINTER(vp), c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                     ctypes.POINTER(i64), vp]
+    lib.qcoll_eval_multi.restype = c_int
+    lib.qcoll_step_multi.argtypes = [ctypes.POINTER(vp), c_int, ctypes.POINTER(vp), ctypes.POINTER(i64), dbl, dbl,
+                                     c_int, ctypes.POINTER(vp), vp]
+    lib.qcoll_step_multi.restype = c_int
+    lib.qcoll_plan_set_launch.argtypes = [vp, c_int, i64]
+    lib.qcoll_plan_set_launch.restype = c_int
+    lib.qcoll_plan_get_launch.argtypes = [vp, ctypes.POINTER(c_int), ctypes.POINTER(i64)]
+    lib.qcoll_plan_get_launch.restype = c_int
+    lib.qcoll_plan_autotune.argtypes = [vp, vp, vp, i64, c_int, vp]
+    lib.qcoll_plan_autotune.restype = c_int
     lib.qcoll_plan_destroy.argtypes = [vp]
     lib.qcoll_plan_destroy.restype = None
     lib.qcoll_strerror.argtypes = [c_int]
@@ -144,6 +165,50 @@ class Plan:
                               _SCHEMES[scheme], st, _stream_ptr(stream)), "qcoll_step")
         return f
 
+    @property
+    def key(self) -> str:
+        """Identity of the plan's workload shape for the autotuning cache."""
+        return f"d{self.d}_N{self.N}_{self.kernel}_M{self.M}_{self.precision}_{'c' if self.conserve else 'n'}"
+
+    def launch(self) -> tuple[int, int]:
+        w, b = ctypes.c_int(), ctypes.c_int64()
+        _check(LIB.qcoll_plan_get_launch(self._h, ctypes.byref(w), ctypes.byref(b)), "qcoll_plan_get_launch")
+        return w.value, b.value
+
+    def set_launch(self, waves_per_block: int, max_blocks: int) -> None:
+        _check(LIB.qcoll_plan_set_launch(self._h, int(waves_per_block), int(max_blocks)), "qcoll_plan_set_launch")
+
+    def autotune(self, f, reps: int = 3, cache: str | None = None, stream=None) -> tuple[int, int]:
+        """Pick the fastest launch shape on f (see qcoll_plan_autotune) and store it
+        in the JSON cache (path `cache`, or $QCOLL_TUNE_CACHE) under the plan key."""
+        import torch
+        q = torch.empty(f.shape, dtype=torch.float64 if self.conserve else torch.float32, device=f.device)
+        _check(LIB.qcoll_plan_autotune(self._h, _dev_ptr(f, torch.float32, "f"), ctypes.c_void_p(q.data_ptr()),
+                                       f.shape[0], int(reps), _stream_ptr(stream)), "qcoll_plan_autotune")
+        best = self.launch()
+        path = cache or os.environ.get("QCOLL_TUNE_CACHE")
+        if path:
+            import json
+            data = json.load(open(path)) if os.path.exists(path) else {}
+            data[self.key] = {"waves_per_block": best[0], "max_blocks": best[1]}
+            tmp = path + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(data, fh, indent=1, sort_keys=True)
+            os.replace(tmp, path)
+        return best
+
+    def load_tuning(self, cache: str | None = None) -> bool:
+        """Apply a cached launch shape for this plan's key, if any."""
+        import json
+        path = cache or os.environ.get("QCOLL_TUNE_CACHE")
+        if not path or not os.path.exists(path):
+            return False
+        ent = json.load(open(path)).get(self.key)
+        if not ent:
+            return False
+        self.set_launch(ent["waves_per_block"], ent["max_blocks"])
+        return True
+
     def close(self):
         if getattr(self, "_h", None):
             LIB.qcoll_plan_destroy(self._h)
@@ -154,3 +219,38 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _ptr_array(items):
+    arr = (ctypes.c_void_p * len(items))()
+    for i, it in enumerate(items):
+        arr[i] = it
+    return arr
+
+
+def eval_multi(plans, fs, qs, stream=None):
+    """One launch over several plans (qcoll_eval_multi); fs, qs device tensors."""
+    import torch
+    n = len(plans)
+    pl = _ptr_array([p._h.value for p in plans])
+    fp = _ptr_array([_dev_ptr(f, torch.float32, "f").value for f in fs])
+    qp = _ptr_array([_dev_ptr(q, torch.float64 if p.conserve else torch.float32, "Q").value
+                     for p, q in zip(plans, qs)])
+    cells = (ctypes.c_int64 * n)(*[f.shape[0] for f in fs])
+    _check(LIB.qcoll_eval_multi(pl, n, fp, qp, cells, _stream_ptr(stream)), "qcoll_eval_multi")
+    return qs
+
+
+def step_multi(plans, fs, dt: float, eps: float = 1.0, scheme: str = "explicit", statuses=None, stream=None):
+    """One stage update over several plans in one launch (qcoll_step_multi)."""
+    import torch
+    n = len(plans)
+    pl = _ptr_array([p._h.value for p in plans])
+    fp = _ptr_array([_dev_ptr(f, torch.float32, "f").value for f in fs])
+    cells = (ctypes.c_int64 * n)(*[f.shape[0] for f in fs])
+    st = None
+    if statuses is not None:
+        st = _ptr_array([0 if s is None else _dev_ptr(s, torch.int32, "status").value for s in statuses])
+    _check(LIB.qcoll_step_multi(pl, n, fp, cells, float(dt), float(eps), _SCHEMES[scheme], st,
+                                _stream_ptr(stream)), "qcoll_step_multi")
+    return fs

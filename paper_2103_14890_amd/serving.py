@@ -1,0 +1,240 @@
+"""Continuous-batching service for space-homogeneous relaxation problems.
+
+A request is one cell's distribution f0 on an N x N velocity grid, a
+collision kernel and a number of time steps of d f/dt = Q(f)/eps (section
+3.4; explicit Euler by default). Requests of different N and kernels run side
+by side on one GPU:
+
+  * admission: a request is admitted when the live state (4 N^2 bytes per
+    request) fits in the HBM budget and its group has a free slot; otherwise
+    it waits in a FIFO queue and is admitted as soon as memory frees up;
+  * residency: each (N, kernel) group keeps its live cells contiguous in a
+    device pool (one plan per group); f stays on the device between steps;
+  * scheduling: every tick advances every live request by one step in ONE
+    batched launch over all groups (qcoll_step_multi), then retires finished
+    requests (copy to host, compaction of the pool) and admits waiting ones;
+  * faults: a cell whose update became non-finite is flagged by the kernel
+    and evicted without affecting the others.
+
+Latency is completion time minus arrival time on the host monotonic clock.
+All device work is done by the HIP library through the binding.
+"""
+
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+
+import numpy as np
+
+from . import qcoll
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    N: int
+    kernel: str
+    steps: int
+    f0: np.ndarray           # float32 [N, N]
+    arrival: float = 0.0     # seconds on the service clock
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    f: np.ndarray | None
+    arrival: float
+    admitted: float
+    done: float
+    failed: bool = False
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class _Group:
+    def __init__(self, plan: qcoll.Plan, N: int, device):
+        import torch
+        self.plan, self.N, self.device = plan, N, device
+        self.pool = torch.empty((0, N, N), dtype=torch.float32, device=device)
+        self.status = torch.empty((0,), dtype=torch.int32, device=device)
+        self.live: list[int] = []          # request id of slot i
+        self.left: list[int] = []          # steps remaining for slot i
+
+    def ensure(self, need: int):
+        import torch
+        cap = self.pool.shape[0]
+        if need <= cap:
+            return
+        new = max(need, 2 * cap, 8)
+        pool = torch.empty((new, self.N, self.N), dtype=torch.float32, device=self.device)
+        if len(self.live):
+            pool[:len(self.live)].copy_(self.pool[:len(self.live)])
+        self.pool = pool
+        self.status = torch.empty((new,), dtype=torch.int32, device=self.device)
+
+
+class Server:
+    """Continuous-batching scheduler over qcoll_step_multi."""
+
+    def __init__(self, L: float = 8.0, M: int = 8, precision: str = "fx16", dt: float = 0.01,
+                 eps: float = 1.0, scheme: str = "explicit", budget_bytes: int = 256 << 20,
+                 max_slots: int = 1 << 16, device=None):
+        import torch
+        self.L, self.M, self.precision = L, M, precision
+        self.dt, self.eps, self.scheme = dt, eps, scheme
+        self.budget = int(budget_bytes)
+        self.max_slots = max_slots
+        self.device = device or torch.device("cuda:0")
+        self.groups: dict[tuple[int, str], _Group] = {}
+        self.queue: collections.deque[Request] = collections.deque()
+        self.results: dict[int, Result] = {}
+        self.bytes_live = 0
+        self.peak_bytes = 0
+        self.ticks = 0
+        self.cell_steps = 0
+        self._admit_time: dict[int, float] = {}
+
+    # ----------------------------------------------------------- admission
+    def _group(self, N: int, kernel: str) -> _Group:
+        key = (N, kernel)
+        if key not in self.groups:
+            plan = qcoll.Plan(2, N, self.L, kernel, self.M, precision=self.precision)
+            self.groups[key] = _Group(plan, N, self.device)
+        return self.groups[key]
+
+    def submit(self, req: Request) -> None:
+        need = 4 * req.N * req.N
+        if need > self.budget:
+            raise ValueError(f"request {req.rid} needs {need} B, more than the whole budget")
+        self.queue.append(req)
+
+    def _try_admit(self, now: float) -> None:
+        import torch
+        while self.queue:
+            req = self.queue[0]
+            need = 4 * req.N * req.N
+            g = self._group(req.N, req.kernel)
+            if self.bytes_live + need > self.budget or len(g.live) >= self.max_slots:
+                return  # FIFO: the head waits for memory to free up
+            self.queue.popleft()
+            g.ensure(len(g.live) + 1)
+            g.pool[len(g.live)].copy_(torch.from_numpy(np.ascontiguousarray(req.f0, dtype=np.float32)))
+            g.live.append(req.rid)
+            g.left.append(req.steps)
+            self.bytes_live += need
+            self.peak_bytes = max(self.peak_bytes, self.bytes_live)
+            self._admit_time[req.rid] = now
+            self.results[req.rid] = Result(req.rid, None, req.arrival, now, float("nan"))
+
+    # ---------------------------------------------------------------- tick
+    def tick(self, clock) -> int:
+        """One batched step of every live request; returns the number retired."""
+        import torch
+        groups = [g for g in self.groups.values() if g.live]
+        if not groups:
+            return 0
+        plans = [g.plan for g in groups]
+        fs = [g.pool[:len(g.live)] for g in groups]
+        st = [g.status[:len(g.live)] for g in groups]
+        qcoll.step_multi(plans, fs, self.dt, self.eps, self.scheme, st)
+        self.ticks += 1
+        self.cell_steps += sum(len(g.live) for g in groups)
+        flags = [s.cpu().numpy() for s in st]   # synchronises with the step
+        retired = 0
+        for g, fl in zip(groups, flags):
+            done = [i for i in range(len(g.live)) if g.left[i] <= 1 or fl[i] != 0]
+            for i in range(len(g.live)):
+                g.left[i] -= 1
+            if not done:
+                continue
+            host = g.pool[:len(g.live)][torch.tensor(done, device=g.pool.device)].cpu().numpy()
+            now = clock()
+            for j, i in enumerate(done):
+                r = self.results[g.live[i]]
+                r.failed = bool(fl[i] != 0)
+                r.f = None if r.failed else host[j]
+                r.done = now
+            # compaction: move the last live slots into the holes
+            for i in sorted(done, reverse=True):
+                last = len(g.live) - 1
+                if i != last:
+                    g.pool[i].copy_(g.pool[last])
+                    g.live[i], g.left[i] = g.live[last], g.left[last]
+                g.live.pop()
+                g.left.pop()
+                self.bytes_live -= 4 * g.N * g.N
+                retired += 1
+        return retired
+
+    # ----------------------------------------------------------------- run
+    def run(self, requests: list[Request], realtime: bool = True, poll: float = 2e-4) -> dict:
+        """Serve requests arriving at their `arrival` times (open loop). With
+        realtime=False the clock is virtual and advances by the measured tick
+        time (deterministic admission order for tests)."""
+        import torch
+        reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        t0 = time.monotonic()
+        vclock = [0.0]
+        clock = (lambda: time.monotonic() - t0) if realtime else (lambda: vclock[0])
+        i = 0
+        pending = len(reqs)
+        while pending:
+            now = clock()
+            while i < len(reqs) and reqs[i].arrival <= now:
+                self.submit(reqs[i])
+                i += 1
+            self._try_admit(now)
+            if any(g.live for g in self.groups.values()):
+                ts = time.monotonic()
+                pending -= self.tick(clock if realtime else (lambda: vclock[0]))
+                if not realtime:
+                    vclock[0] += time.monotonic() - ts
+            elif i < len(reqs):
+                if realtime:
+                    time.sleep(min(poll, max(0.0, reqs[i].arrival - clock())))
+                else:
+                    vclock[0] = max(vclock[0], reqs[i].arrival)
+            elif self.queue:
+                raise RuntimeError("queued requests cannot be admitted")
+        torch.cuda.synchronize()
+        return self.stats(clock())
+
+    def stats(self, wall: float) -> dict:
+        lat = np.array([r.latency for r in self.results.values() if not r.failed])
+        ok = len(lat)
+        return {
+            "requests": len(self.results),
+            "failed": sum(r.failed for r in self.results.values()),
+            "p50_latency_s": float(np.percentile(lat, 50)) if ok else None,
+            "p99_latency_s": float(np.percentile(lat, 99)) if ok else None,
+            "throughput_req_s": ok / wall if wall > 0 else None,
+            "cell_steps_s": self.cell_steps / wall if wall > 0 else None,
+            "ticks": self.ticks,
+            "peak_bytes": self.peak_bytes,
+            "wall_s": wall,
+        }
+
+    def close(self):
+        for g in self.groups.values():
+            g.plan.close()
+
+
+def poisson_requests(n: int, rate: float, seed: int, L: float = 8.0, sizes=(16, 24, 32),
+                     kernels=("maxwell", "hard_sphere"), steps=(50, 400)) -> list[Request]:
+    """Open-loop Poisson arrivals with N, kernel and step count drawn uniformly;
+    f0 is a two-Maxwellian mixture (the same generator as the batch workloads)."""
+    import workloads as wl
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    out = []
+    for k in range(n):
+        N = int(rng.choice(sizes))
+        kern = str(rng.choice(kernels))
+        st = int(rng.integers(steps[0], steps[1] + 1))
+        f0 = wl.mixture_cells(2, N, L, 1, seed * 100003 + k)[0].astype(np.float32)
+        out.append(Request(k, N, kern, st, f0, float(t[k])))
+    return out

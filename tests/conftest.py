@@ -1,6 +1,10 @@
 import os
 import sys
 
+# One HIP runtime per process: PyTorch's must be loaded before libqcoll.so
+# (see paper_2103_14890_amd/qcoll.py).
+import torch  # noqa: F401,E402
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

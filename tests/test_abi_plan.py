@@ -99,3 +99,20 @@ def test_device_plan_without_gpu_reports_device_error():
         pytest.skip("GPU present")
     rc, h = _plan(flags=0)
     assert rc == qc.EDEVICE and not h.value
+
+
+def test_multi_and_tuning_argument_checks():
+    p = qc.Plan(2, 32, 8.0, "hard_sphere", 8, host_only=True)
+    arr = (ctypes.c_void_p * 1)(p._h.value)
+    ptrs = (ctypes.c_void_p * 1)(0)
+    cells = (ctypes.c_int64 * 1)(4)
+    assert qc.LIB.qcoll_eval_multi(arr, 9, ptrs, ptrs, cells, None) == qc.EINVAL      # too many slots
+    assert qc.LIB.qcoll_eval_multi(None, 1, ptrs, ptrs, cells, None) == qc.EINVAL
+    assert qc.LIB.qcoll_eval_multi(arr, 1, ptrs, ptrs, cells, None) == qc.EUNSUPPORTED  # host-only plan
+    assert qc.LIB.qcoll_step_multi(arr, 1, ptrs, cells, -1.0, 1.0, 0, None, None) == qc.EINVAL
+    assert qc.LIB.qcoll_plan_set_launch(p._h, 3, 10) == qc.EINVAL
+    assert qc.LIB.qcoll_plan_set_launch(p._h, 2, 0) == qc.EINVAL
+    p.set_launch(2, 512)
+    assert p.launch() == (2, 512)
+    assert qc.LIB.qcoll_plan_autotune(p._h, None, None, 4, 1, None) == qc.EINVAL
+    p.close()

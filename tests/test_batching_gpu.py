@@ -1,0 +1,120 @@
+"""GPU tests of the batched paths: one launch over several plans (cells of
+different velocity grids), hipGraph capture and replay, and the launch-shape
+autotuner. The operator is cell-local, so every variant must reproduce the
+single-plan results bitwise."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qc():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2103_14890_amd import qcoll
+    return qcoll
+
+
+SLOTS = [(32, 8.0, "hard_sphere", 8, "fx16", False, 37), (16, 8.0, "maxwell", 16, "fx16", False, 9),
+         (24, 8.0, "hard_sphere", 8, "fp32", False, 13), (32, 8.0, "maxwell", 8, "fx16", True, 5),
+         (12, 5.0, "hard_sphere", 8, "fp32", True, 3)]
+
+
+def _setup(qc, seed=0):
+    plans, fs = [], []
+    for i, (N, L, kern, M, prec, cons, cells) in enumerate(SLOTS):
+        plans.append(qc.Plan(2, N, L, kern, M, precision=prec, conserve=cons))
+        fs.append(torch.tensor(wl.mixture_cells(2, N, L, cells, 100 + i + seed), dtype=torch.float32, device="cuda"))
+    return plans, fs
+
+
+def test_eval_multi_bitwise_equals_single_launches(qc):
+    plans, fs = _setup(qc)
+    singles = [p.eval(f) for p, f in zip(plans, fs)]
+    outs = [torch.full_like(s, float("nan")) for s in singles]
+    qc.eval_multi(plans, fs, outs)
+    torch.cuda.synchronize()
+    for a, b in zip(singles, outs):
+        assert torch.equal(a, b)
+    for p in plans:
+        p.close()
+
+
+@pytest.mark.parametrize("scheme", ["explicit", "imex"])
+def test_step_multi_bitwise_equals_single_launches(qc, scheme):
+    plans, fs = _setup(qc, seed=7)
+    ref = [f.clone() for f in fs]
+    for p, f in zip(plans, ref):
+        p.step(f, 0.02, 0.5, scheme)
+    st = [torch.full((f.shape[0],), -1, dtype=torch.int32, device="cuda") for f in fs]
+    qc.step_multi(plans, fs, 0.02, 0.5, scheme, st)
+    torch.cuda.synchronize()
+    for a, b, s in zip(ref, fs, st):
+        assert torch.equal(a, b)
+        assert (s == 0).all()
+    for p in plans:
+        p.close()
+
+
+def test_graph_capture_and_replay(qc):
+    """Capture single and batched launches in one graph; every replay (with eager
+    work and synchronisation in between) equals the eager result bitwise."""
+    plans, fs = _setup(qc, seed=3)
+    eager = [p.eval(f) for p, f in zip(plans, fs)]
+    torch.cuda.synchronize()
+    q_single = torch.empty_like(eager[0])
+    q_multi = [torch.empty_like(e) for e in eager]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):   # warm-up on the side stream before capture
+        plans[0].eval(fs[0], q_single)
+        qc.eval_multi(plans, fs, q_multi)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plans[0].eval(fs[0], q_single)
+        qc.eval_multi(plans, fs, q_multi)
+    for r in range(3):
+        q_single.fill_(float("nan"))
+        for q in q_multi:
+            q.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(q_single, eager[0])
+        for a, b in zip(q_multi, eager):
+            assert torch.equal(a, b)
+        other = plans[1].eval(fs[1])          # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(other, eager[1])
+    for p in plans:
+        p.close()
+
+
+def test_autotune_keeps_results_and_caches(qc, tmp_path):
+    plan = qc.Plan(2, 32, 8.0, "hard_sphere", 8, precision="fx16")
+    f = torch.tensor(wl.mixture_cells(2, 32, 8.0, 1024, 9), dtype=torch.float32, device="cuda")
+    before = plan.eval(f)
+    cache = str(tmp_path / "tune.json")
+    w, b = plan.autotune(f, reps=2, cache=cache)
+    assert w in (1, 2, 4) and b >= 1
+    after = plan.eval(f)
+    torch.cuda.synchronize()
+    assert torch.equal(before, after)
+    data = json.load(open(cache))
+    assert data[plan.key] == {"waves_per_block": w, "max_blocks": b}
+    other = qc.Plan(2, 32, 8.0, "hard_sphere", 8, precision="fx16")
+    assert other.load_tuning(cache) and other.launch() == (w, b)
+    for ws in (1, 2, 4):
+        other.set_launch(ws, 64)
+        assert torch.equal(other.eval(f), before)
+    plan.close()
+    other.close()

@@ -259,3 +259,43 @@ def test_gpu_matches_real_space_brute_force(qc):
             qb = q_brute(f[c].astype(np.float32).astype(np.float64), s).reshape(N, N)
             assert _rel(q[c], qb) < 1e-5
         plan.close()
+
+
+@pytest.mark.parametrize("N,L,kernel,M", [(64, 10.0, "hard_sphere", 16), (64, 10.0, "maxwell", 8),
+                                          (48, 8.0, "hard_sphere", 8), (40, 8.0, "maxwell", 8)])
+def test_parity_tile64(qc, N, L, kernel, M):
+    """Grids of 34..64 points: radix-2 parity split over four wavefronts."""
+    f = wl.mixture_cells(2, N, L, 6, 41)
+    plan = qc.Plan(2, N, L, kernel, M, precision="fx16")
+    q = _gpu_eval(plan, f)
+    ref = _ref(f, kernel, M, N=N, L=L)
+    err, cerr = _rel(q, ref), _cell_rel(q, ref)
+    print(f"N={N} fx16 {kernel} M={M}: rel L2 {err:.3e}, worst cell {cerr:.3e}")
+    assert err < 1e-5 and cerr < 5e-5
+    plan.close()
+
+
+def test_tile64_noisy_conserve_and_step(qc):
+    """Config-3 shape (64x64 on [-10,10]^2, hard spheres, M = 16, 1% noise): parity,
+    FP64 projection, stage update."""
+    f = wl.noisy_mixture_cells(2, 64, 10.0, 5, 1002, 0.01)
+    plan = qc.Plan(2, 64, 10.0, "hard_sphere", 16, precision="fx16", conserve=True)
+    q = plan.eval(torch.tensor(f, dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    qn = q.cpu().numpy()
+    ref = sp.project_conservative(_ref(f, "hard_sphere", 16, N=64, L=10.0), 2, 10.0)
+    err = _rel(qn, ref)
+    mass = (np.abs(qn.sum(axis=(1, 2))) / np.abs(qn).sum(axis=(1, 2))).max()
+    print(f"N=64 noisy conserve: rel L2 {err:.3e}, mass {mass:.2e}")
+    assert err < 1e-5 and mass < 1e-12
+    plan.close()
+    plan = qc.Plan(2, 64, 10.0, "hard_sphere", 16, precision="fx16")
+    ft = torch.tensor(f, dtype=torch.float32, device="cuda")
+    st = torch.full((5,), -1, dtype=torch.int32, device="cuda")
+    plan.step(ft, 0.02, 1.0, "imex", st)
+    torch.cuda.synchronize()
+    f32 = f.astype(np.float32).astype(np.float64)
+    want = stepping.imex_euler_penalized(f32, _ref(f, "hard_sphere", 16, N=64, L=10.0), 0.02, 1.0, 2, 10.0)
+    assert np.abs(ft.cpu().double().numpy() - want).max() <= 2e-6 * np.abs(want).max()
+    assert (st.cpu().numpy() == 0).all()
+    plan.close()
