@@ -80,9 +80,11 @@ enum {
  * flags a combination of QCOLL_* flags. The plan owns its host and device
  * tables; apart from its launch shape (qcoll_plan_set_launch, set before use)
  * it is immutable and may be used from several streams at once. On error *out
- * is set to NULL. Device plans: d = 2 with N <= 32 (grids below 16 or 32 run
- * zero-padded in a 16x16 or 32x32 tile); larger grids and d = 3 are
- * QCOLL_EUNSUPPORTED on the device (their host tables build). */
+ * is set to NULL. Device plans: d = 2 with N <= 32 in either precision (grids
+ * below 16 or 32 run zero-padded in a 16x16 or 32x32 tile) and 34 <= N <= 64
+ * in QCOLL_MIX_FX16 (radix-2 split into 32-point tiles, one workgroup per
+ * cell); other sizes and d = 3 are QCOLL_EUNSUPPORTED on the device (their
+ * host tables build). */
 int qcoll_plan(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, double b,
                int M, int K_r, int precision, unsigned flags);
 
@@ -109,7 +111,9 @@ int qcoll_step(qcoll_plan_t plan, float* f, int64_t cells, double dt, double eps
  * grids and kernels share one launch). Slot i uses plans[i] with f[i], Q[i]
  * (or status[i]) and cells[i] exactly as the single-plan call; each cell's
  * result is bitwise equal to the single-plan launch. nplans <= 8, all plans on
- * one device; slots with cells[i] == 0 are skipped. status may be NULL. */
+ * one device; slots with cells[i] == 0 are skipped. status may be NULL. Plans
+ * with N > 32 are QCOLL_EUNSUPPORTED here (their cells need a workgroup each;
+ * launch them with the single-plan calls). */
 int qcoll_eval_multi(const qcoll_plan_t* plans, int nplans, const float* const* f, void* const* Q,
                      const int64_t* cells, hipStream_t stream);
 int qcoll_step_multi(const qcoll_plan_t* plans, int nplans, float* const* f, const int64_t* cells, double dt,

@@ -144,6 +144,7 @@ __global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
         const Cd z = {mr * fr[v] - mi * fi[v], mr * fi[v] + mi * fr[v]};
         zs[(w * 16 + v) * 64 + lane] = z;
         zm = fmaxf(zm, fmaxf(fabsf(static_cast<float>(z.x)), fabsf(static_cast<float>(z.y))));
+        if (v & 1) __builtin_amdgcn_sched_barrier(0);
       }
       zm = wave_max(zm);
       if (lane == 0) red[w * 4 + 3] = zm;
