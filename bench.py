@@ -94,6 +94,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", default="hs2d_32", choices=sorted(WORKLOADS))
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after timing, copy a buffer of this many MiB once (a plain copy kernel of "
+                         "known size, for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -120,6 +123,14 @@ def main() -> int:
         wall, per = time_launches(lambda: plan.eval(f, q), args.steps, args.warmup, stream)
         info = plan.info()
         res[prec] = dict(plan=plan, q=q, wall=wall, per=per, info=info)
+
+    if args.calibrate_copy > 0:
+        src = torch.ones(args.calibrate_copy << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # accuracy on a sample, against the oracle (also the CPU-baseline run)
     ncpu, t_cpu, q_ref = cpu_baseline(f64.astype(np.float32).astype(np.float64), args.cpu_seconds, NN, LL, KERN, MM)

@@ -123,11 +123,13 @@ int build_device_2d32(qcoll_plan_s* p) {
       int e = exp_above(mx);
       fe[q] = e;
       double sc = std::ldexp(1.0, -e);
+      // [q][register v][lane][re, im]: one wavefront's load of a register is
+      // 1 KB contiguous
       for (int lane = 0; lane < 64; ++lane) {
         int h = lane >> 5, c = lane & 31;
         for (int v = 0; v < 16; ++v) {
           int64_t k = mode(rrow(v, h), c);
-          size_t o = (static_cast<size_t>(q) * 64 + lane) * 32 + 2 * v;
+          size_t o = ((static_cast<size_t>(q) * 16 + v) * 64 + lane) * 2;
           ft[o] = val(k).real() * sc;
           ft[o + 1] = val(k).imag() * sc;
         }

@@ -27,9 +27,10 @@ enum { kFwdRe = 0, kFwdIm = 1, kInvRe = 2, kInvIm = 3 };
 
 __device__ __forceinline__ float tile_absmax16(const f32x4& r0, const f32x4& r1, const f32x4& i0,
                                                const f32x4& i1) {
+  // max (|acc0| + |acc1|): bounds |acc0| (the next lead) and |acc0 + acc1|
   float m = 0.0f;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) m = fmaxf(m, fmaxf(fabsf(r0[v] + r1[v]), fabsf(i0[v] + i1[v])));
+  for (int v = 0; v < 4; ++v) m = fmaxf(m, fmaxf(fabsf(r0[v]) + fabsf(r1[v]), fabsf(i0[v]) + fabsf(i1[v])));
   return wave_max(m);
 }
 

@@ -40,45 +40,17 @@ __device__ __forceinline__ void slice_tiles(const f32x16& r0, const f32x16& r1, 
   }
 }
 
-__device__ __forceinline__ void load_filter(const double* mq, double* m) {
-  const double2* src = reinterpret_cast<const double2*>(mq);
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    double2 t = src[v];
-    m[2 * v] = t.x;
-    m[2 * v + 1] = t.y;
-  }
-}
-
-// Z = m * f_hat for modes v, v+1 of one packed filter (FP64 complex product,
-// |Z| < 2^9 by the scaling of m and f_hat), split into the left operand of the
-// first inverse pass.
-__device__ __forceinline__ void split_spectrum_pair(const double* m, const double* fr, const double* fi,
-                                                    Split3 A[4], int v) {
-  double yr[2], yi[2];
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    double mr = m[2 * (v + u)], mi = m[2 * (v + u) + 1];
-    yr[u] = mr * fr[v + u] - mi * fi[v + u];
-    yi[u] = mr * fi[v + u] + mi * fr[v + u];
-  }
-  put2(A[v >> 3], v & 7, split2_f64(yr[0], yr[1]));
-  put2(A[2 + (v >> 3)], v & 7, split2_f64(yi[0], yi[1]));
-}
-
-__device__ __forceinline__ void split_spectrum(const double* m, const double* fr, const double* fi,
-                                               Split3 A[4]) {
-#pragma unroll
-  for (int v = 0; v < 16; v += 2) split_spectrum_pair(m, fr, fi, A, v);
-}
-
+// Bound on the magnitudes of a complex result tile held as accumulator pairs:
+// max (|acc0| + |acc1|) bounds both |acc0| (the part that becomes the lead of
+// the next split) and |acc0 + acc1|. (The sums are canonical floats, so the
+// maxima need no NaN quieting and fold into v_max3.)
 __device__ __forceinline__ float tile_absmax(const f32x16& r0, const f32x16& r1, const f32x16& i0,
                                              const f32x16& i1) {
   float m = 0.0f;
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
-    m = fmaxf(m, fabsf(r0[v] + r1[v]));
-    m = fmaxf(m, fabsf(i0[v] + i1[v]));
+    m = fmaxf(m, fabsf(r0[v]) + fabsf(r1[v]));
+    m = fmaxf(m, fabsf(i0[v]) + fabsf(i1[v]));
   }
   return wave_max(m);
 }
@@ -103,13 +75,107 @@ __device__ __forceinline__ void pass64(const Split3 A[4], const Split3 E[3][2], 
 
 enum { kEr = 0, kEi = 1, kNEi = 2 };
 
-template <int OUT>  // OUT: 0 eval float, 1 eval double (projection), 2 step, -1 from a.out_kind
-__device__ __forceinline__ void fx16_t32_body(const KernelArgs& a, int64_t first, int64_t stride) {
-  const int lane = threadIdx.x & 63;
-  const int h = lane >> 5, c = lane & 31;
+// DFT-matrix operands with the lo parts in LDS: lead and hi stay in registers
+// (48 VGPRs), the lo part (used by one of the six products) is read from a
+// block-shared LDS table [mat][K-slice][lane] right before its product.
+struct Split2 {
+  half8 l, h;
+};
 
-  // DFT-matrix operands (Er, Ei, -Ei; two K-slices; lead/hi/lo), per lane.
-  Split3 E[3][2];
+__device__ __forceinline__ void mma6_lo_lds(const Split3& a, const Split2& b, const half8* bo, f32x16& acc0,
+                                            f32x16& acc1) {
+  const half8 b_o = *bo;
+  acc0 = mfma16(a.l, b.l, acc0);
+  acc1 = mfma16(a.l, b.h, acc1);
+  acc1 = mfma16(a.h, b.l, acc1);
+  acc1 = mfma16(a.h, b.h, acc1);
+  acc1 = mfma16(a.o, b.l, acc1);
+  acc1 = mfma16(a.l, b_o, acc1);
+}
+
+// pass64 with Split2 operands; eo is the LDS table of lo parts. An opaque lane
+// index keeps the table reads inside the caller's loops.
+__device__ __forceinline__ void pass64_lo_lds(const Split3 A[4], const Split2 E[3][2], const half8* eo, int re_a,
+                                              int re_b, int im_a, int im_b, bool want_im, f32x16& r0, f32x16& r1,
+                                              f32x16& i0, f32x16& i1) {
+  int lane = threadIdx.x & 63;
+  asm volatile("" : "+v"(lane));
+  r0 = r1 = i0 = i1 = f32x16{};
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    mma6_lo_lds(A[s], E[re_a][s], eo + (re_a * 2 + s) * 64 + lane, r0, r1);
+    mma6_lo_lds(A[2 + s], E[re_b][s], eo + (re_b * 2 + s) * 64 + lane, r0, r1);
+    if (want_im) {
+      mma6_lo_lds(A[s], E[im_a][s], eo + (im_a * 2 + s) * 64 + lane, i0, i1);
+      mma6_lo_lds(A[2 + s], E[im_b][s], eo + (im_b * 2 + s) * 64 + lane, i0, i1);
+    }
+  }
+}
+
+// Fill the block-shared LDS table of DFT-matrix lo parts (all threads of the
+// workgroup take part; ends with a workgroup barrier).
+__device__ __forceinline__ void load_eo_table(const KernelArgs& a, half8* eo) {
+  const half8* src = reinterpret_cast<const half8*>(a.econst);
+  for (int i = threadIdx.x; i < 6 * 64; i += blockDim.x) {
+    const int ms = i >> 6, ln = i & 63;
+    eo[i] = src[ln * 18 + ms * 3 + 2];
+  }
+  __syncthreads();
+}
+
+// Byte offset of this lane's entry in a [register][lane] table of 16-byte
+// values, kept opaque so that per-register addresses are formed where they are
+// used (a uniform base plus a 32-bit lane offset) instead of being hoisted into
+// sixteen 64-bit VGPR pairs.
+__device__ __forceinline__ unsigned opaque_lane16(int lane) {
+  unsigned o = static_cast<unsigned>(lane) * 16u;
+  asm volatile("" : "+v"(o));
+  return o;
+}
+
+// Filter value of transform q, register v, from the table [q][v][lane].
+__device__ __forceinline__ double2 load_filter_value(const double* filt, int q, int v, unsigned l16) {
+  const char* base = reinterpret_cast<const char*>(filt) + static_cast<size_t>(q) * (16 * 64 * 16);
+  return *reinterpret_cast<const double2*>(base + (static_cast<unsigned>(v) * 1024u + l16));
+}
+
+// Filtered spectrum Z = m * f_hat for all 16 modes of a lane (FP64, |Z| < 2^8),
+// split into the left operand of inverse pass A. The spectrum is re-read from
+// LDS for every transform: an opaque lane offset keeps the compiler from
+// hoisting the reads into 64 live VGPRs.
+__device__ __forceinline__ void filtered_split(const double2* mv, const double2* fh, int lane, Split3 A[4]) {
+  asm volatile("" : "+v"(lane));
+#pragma unroll
+  for (int v = 0; v < 16; v += 2) {
+    const double2 m0 = mv[v], m1 = mv[v + 1];
+    const double2 f0 = fh[v * 64 + lane], f1 = fh[(v + 1) * 64 + lane];
+    const double yr0 = m0.x * f0.x - m0.y * f0.y, yi0 = m0.x * f0.y + m0.y * f0.x;
+    const double yr1 = m1.x * f1.x - m1.y * f1.y, yi1 = m1.x * f1.y + m1.y * f1.x;
+    put2(A[v >> 3], v & 7, split2_f64(yr0, yr1));
+    put2(A[2 + (v >> 3)], v & 7, split2_f64(yi0, yi1));
+  }
+}
+
+// LDS of the FX16 body: per wavefront the cell's spectrum as FP64 complex
+// values in [register][lane] order, per workgroup the table of DFT-matrix lo
+// parts [mat][K-slice][lane].
+constexpr int kFhatLdsBytes = 16 * 64 * 16;
+constexpr int kEoLdsBytes = 6 * 64 * 16;
+
+// FX16 body. Register budget: at most 256 VGPRs per lane, so that two
+// wavefronts share each SIMD and the matrix-core work of one overlaps the
+// vector work (splits, FP64 filtering and gain) of the other. The spectrum
+// lives in LDS (`fh`, this wavefront's kFhatLdsBytes), the filters stream from
+// L2 in mode pairs, and per transform the phases run in order: split of the
+// filtered spectrum, inverse pass A, slicing, inverse pass B, gain.
+template <int OUT>  // OUT: 0 eval float, 1 eval double (projection), 2 step, -1 from a.out_kind
+__device__ __forceinline__ void fx16_t32_body(const KernelArgs& a, int64_t first, int64_t stride, double2* fh,
+                                              const half8* eo) {
+  const int lane = threadIdx.x & 63;
+
+  // DFT-matrix operands (Er, Ei, -Ei; two K-slices; lead and hi per lane; the
+  // lo parts in the LDS table eo).
+  Split2 E[3][2];
   {
     const half8* src = reinterpret_cast<const half8*>(a.econst) + lane * 18;
 #pragma unroll
@@ -118,56 +184,57 @@ __device__ __forceinline__ void fx16_t32_body(const KernelArgs& a, int64_t first
       for (int s = 0; s < 2; ++s) {
         E[m][s].l = src[(m * 2 + s) * 3 + 0];
         E[m][s].h = src[(m * 2 + s) * 3 + 1];
-        E[m][s].o = src[(m * 2 + s) * 3 + 2];
       }
   }
 
   for (int64_t cell = first; cell < a.cells; cell += stride) {
-    float fv[16];
-    load_cell<Lay32>(a, cell, lane, fv);
-
-    // ---- forward pass 1 (real input, contraction over the first axis)
-    float fm = 0.0f;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) fm = fmaxf(fm, fabsf(fv[v]));
-    fm = wave_max(fm);
-    const int a0 = 9 - exp_above(fm);
-    const float cf = ldexpf(1.0f, a0);
-    Split3 A[4];
-#pragma unroll
-    for (int v = 0; v < 16; v += 2)
-      put2(A[v >> 3], v & 7, split2_f64(static_cast<double>(fv[v] * cf), static_cast<double>(fv[v + 1] * cf)));
     f32x16 r0{}, r1{}, i0{}, i1{};
+    Split3 A[4];
+    int s_fh;
+    {
+      float fv[16];
+      load_cell<Lay32>(a, cell, lane, fv);
+
+      // ---- forward pass 1 (real input, contraction over the first axis)
+      float fm = 0.0f;
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      mma6(A[s], E[kEr][s], r0, r1);
-      mma6(A[s], E[kNEi][s], i0, i1);
+      for (int v = 0; v < 16; ++v) fm = fmaxf(fm, fabsf(fv[v]));
+      fm = wave_max(fm);
+      const int a0 = 9 - exp_above(fm);
+      const float cf = ldexpf(1.0f, a0);
+#pragma unroll
+      for (int v = 0; v < 16; v += 2)
+        put2(A[v >> 3], v & 7, split2_f64(static_cast<double>(fv[v] * cf), static_cast<double>(fv[v + 1] * cf)));
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        mma6_lo_lds(A[s], E[kEr][s], eo + (kEr * 2 + s) * 64 + lane, r0, r1);
+        mma6_lo_lds(A[s], E[kNEi][s], eo + (kNEi * 2 + s) * 64 + lane, i0, i1);
+      }
+      s_fh = -(a0 + 9);  // true value = accumulator * 2^s_fh
     }
-    int sc = -(a0 + 9);  // true value = accumulator * 2^sc
 
     // ---- forward pass 2 (complex, contraction over the second axis)
-    int a1 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
-    slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a1), A);
-    pass64(A, E, kEr, kEi, kNEi, kEr, true, r0, r1, i0, i1);
-    sc = sc - a1 - 9;
+    {
+      const int a1 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
+      slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a1), A);
+      pass64_lo_lds(A, E, eo, kEr, kEi, kNEi, kEr, true, r0, r1, i0, i1);
+      s_fh -= a1 + 9;
+    }
 
-    // unnormalised spectrum in FP64, rescaled so that |f_hat| < 2^9
-    double fr[16], fi[16];
-    float fhm = 0.0f;
+    // unnormalised spectrum in FP64 to LDS, rescaled so that |f_hat| < 2^8
+    {
+      float fhm = 0.0f;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      fr[v] = static_cast<double>(r0[v]) + static_cast<double>(r1[v]);
-      fi[v] = static_cast<double>(i0[v]) + static_cast<double>(i1[v]);
-      fhm = fmaxf(fhm, fmaxf(fabsf(static_cast<float>(fr[v])), fabsf(static_cast<float>(fi[v]))));
-    }
-    fhm = wave_max(fhm * 1.0000002f);
-    const int bsh = 9 - (exp_above(fhm) + 1);
+      for (int v = 0; v < 16; ++v)
+        fhm = fmaxf(fhm, fmaxf(fabsf(r0[v] + r1[v]), fabsf(i0[v] + i1[v])));
+      fhm = wave_max(fhm * 1.0000002f);
+      const int bsh = 9 - (exp_above(fhm) + 1);
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      fr[v] = ldexp(fr[v], bsh);
-      fi[v] = ldexp(fi[v], bsh);
+      for (int v = 0; v < 16; ++v)
+        fh[v * 64 + lane] = make_double2(ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), bsh),
+                                         ldexp(static_cast<double>(i0[v]) + static_cast<double>(i1[v]), bsh));
+      s_fh -= bsh;  // true f_hat = stored value * 2^s_fh
     }
-    const int s_fh = sc - bsh;  // true f_hat = fr * 2^s_fh
 
     double gain[16];
 #pragma unroll
@@ -175,51 +242,60 @@ __device__ __forceinline__ void fx16_t32_body(const KernelArgs& a, int64_t first
 
     // Packed transforms q = 0..P-1 contribute Re * Im of their inverse DFT to the
     // gain; entry P of the table is the real loss multiplier, whose inverse DFT
-    // (real part) is the loss field. Software pipeline: the spectrum of
-    // transform q+1 is formed and split while the MFMAs of pass B of transform q
-    // run.
-    double mbuf[32];
-    load_filter(a.filt + static_cast<int64_t>(lane) * 32, mbuf);
-    split_spectrum(mbuf, fr, fi, A);
-    int sd_last = 0;
+    // (real part) is the loss field.
+    // Filter values [q][mode v][lane] (complex FP64, 1 KB per wavefront and
+    // register): all 16 of a transform are loaded in one batch, those of
+    // transform q+1 as soon as the operands of pass B of transform q are dead,
+    // so that their latency overlaps the gain update. The loop is rotated so
+    // that each batch is consumed in the iteration that loads it.
+    {
+      double2 mv[16];
+      const unsigned l16 = opaque_lane16(lane);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) mv[v] = load_filter_value(a.filt, 0, v, l16);
+      filtered_split(mv, fh, lane, A);
+    }
+    int sd_loss = 0;
     for (int q = 0; q <= a.P; ++q) {
-      // prefetch the next filter; its loads complete under pass A
-      const int qn = q < a.P ? q + 1 : q;
-      load_filter(a.filt + (static_cast<int64_t>(qn) * 64 + lane) * 32, mbuf);
       // inverse pass A (contraction over the first axis)
-      pass64(A, E, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
-      int sd = a.filt_exp[q] + s_fh - 9;
+      pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
       const int a2 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
-      Split3 B[4];
-      slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a2), B);
-      // inverse pass B (second axis) in 8 chunks of 6 MFMAs, each followed by
-      // the split of two modes of the next spectrum (independent VALU work that
-      // executes while the matrix cores run)
-      r0 = r1 = i0 = i1 = f32x16{};
-#pragma unroll
-      for (int ch = 0; ch < 8; ++ch) {
-        const int s = ch >> 2, part = (ch >> 1) & 1, im = ch & 1;
-        const Split3& Aop = B[part ? 2 + s : s];
-        const Split3& Bop = E[im ? (part ? kEr : kEi) : (part ? kNEi : kEr)][s];
-        if (im) mma6(Aop, Bop, i0, i1);
-        else mma6(Aop, Bop, r0, r1);
-        split_spectrum_pair(mbuf, fr, fi, A, 2 * ch);
+      slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a2), A);
+      // inverse pass B (second axis); the loss field needs only the real part
+      const bool gain_q = q < a.P;
+      pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, gain_q, r0, r1, i0, i1);
+      const int sd = a.filt_exp[q] + s_fh - 9 - a2 - 9;  // true field = accumulator * 2^sd
+      if (gain_q) {
+        // first half of the next filter in flight during the gain update, the
+        // second half once the accumulators are consumed
         __builtin_amdgcn_sched_barrier(0);
-      }
-      sd = sd - a2 - 9;
-      sd_last = sd;
-      const double w = q < a.P ? ldexp(1.0, 2 * sd) : 0.0;
+        double2 mv[16];
+        const unsigned l16 = opaque_lane16(lane);
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        double re = static_cast<double>(r0[v]) + static_cast<double>(r1[v]);
-        double im = static_cast<double>(i0[v]) + static_cast<double>(i1[v]);
-        gain[v] = fma(re * w, im, gain[v]);
+        for (int v = 0; v < 8; ++v) mv[v] = load_filter_value(a.filt, q + 1, v, l16);
+        __builtin_amdgcn_sched_barrier(0);
+        const double w = ldexp(1.0, 2 * sd);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const double re = static_cast<double>(r0[v]) + static_cast<double>(r1[v]);
+          const double im = static_cast<double>(i0[v]) + static_cast<double>(i1[v]);
+          gain[v] = fma(re * w, im, gain[v]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int v = 8; v < 16; ++v) mv[v] = load_filter_value(a.filt, q + 1, v, l16);
+        __builtin_amdgcn_sched_barrier(0);
+        filtered_split(mv, fh, lane, A);
+      } else {
+        sd_loss = sd;
       }
     }
     // the last transform is the loss field: Q = gain - f * loss
+    float fv[16];
+    load_cell<Lay32>(a, cell, lane, fv);
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      double lf = ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), sd_last);
+      const double lf = ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), sd_loss);
       gain[v] = gain[v] - static_cast<double>(fv[v]) * lf;
     }
     finish_cell<OUT, Lay32>(a, cell, fv, gain, lane);

@@ -13,7 +13,7 @@ struct KernelArgs {
   int64_t cells = 0;
   int n = 0;                    // grid points per axis (<= the kernel's tile size N)
   const void* econst = nullptr; // per-lane DFT-matrix operands (layout set by the variant)
-  const double* filt = nullptr; // FX16: [P][64 lanes][16 modes][re, im], scaled by 2^-filt_exp
+  const double* filt = nullptr; // FX16 filters scaled by 2^-filt_exp (layout set by the tile family)
   const int* filt_exp = nullptr;
   const double* loss = nullptr; // FX16: [64 lanes][16 modes], scaled by 2^-loss_exp
   int loss_exp = 0;

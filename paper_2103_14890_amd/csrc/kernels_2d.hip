@@ -1,8 +1,9 @@
 // Fast spectral collision operator, 2D velocity grid N = 32, gfx950.
 //
 // One wavefront evaluates one cell; a 256-thread workgroup holds four cells
-// and walks the cell range in a grid-stride loop. Everything a cell needs
-// between the load of f and the store of Q stays in registers.
+// and walks the cell range in a grid-stride loop. Between the load of f and
+// the store of Q a cell stays on chip: its data tiles in registers and, in the
+// FX16 variant, its FP64 spectrum in LDS.
 //
 // Dataflow per cell (section 3.3): forward 2D DFT of f -> f_hat; for every
 // packed filter q the spectrum m_q * f_hat and its inverse 2D DFT, whose real
@@ -37,11 +38,17 @@
 namespace qcoll {
 namespace {
 
+// Two wavefronts per SIMD (at most 256 VGPRs each). Dynamic LDS: the table of
+// DFT-matrix lo parts, then one spectrum per wavefront.
 template <int OUT>
-__global__ __launch_bounds__(256) void fx16_t32_kernel(KernelArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fx16_t32_kernel(KernelArgs a) {
+  extern __shared__ double2 lds[];
+  half8* eo = reinterpret_cast<half8*>(lds);
+  load_eo_table(a, eo);
   const int wpb = blockDim.x >> 6;
-  fx16_t32_body<OUT>(a, static_cast<int64_t>(blockIdx.x) * wpb + (threadIdx.x >> 6),
-                 static_cast<int64_t>(gridDim.x) * wpb);
+  const int w = threadIdx.x >> 6;
+  fx16_t32_body<OUT>(a, static_cast<int64_t>(blockIdx.x) * wpb + w, static_cast<int64_t>(gridDim.x) * wpb,
+                     lds + (kEoLdsBytes + w * kFhatLdsBytes) / 16, eo);
 }
 
 template <int OUT>
@@ -60,9 +67,21 @@ int launch_2d32(const KernelArgs& args, hipStream_t stream) {
   if (blocks > args.max_blocks) blocks = args.max_blocks;
   dim3 grid(static_cast<unsigned>(blocks)), block(64 * wpb);
   if (args.precision == 4) {
-    if (args.out_kind == 0) hipLaunchKernelGGL(fx16_t32_kernel<0>, grid, block, 0, stream, args);
-    else if (args.out_kind == 1) hipLaunchKernelGGL(fx16_t32_kernel<1>, grid, block, 0, stream, args);
-    else hipLaunchKernelGGL(fx16_t32_kernel<2>, grid, block, 0, stream, args);
+    const unsigned lds = kEoLdsBytes + kFhatLdsBytes * wpb;
+    static const bool attr_set = [] {  // dynamic LDS above the 64 KB default (4 waves: 70 KB)
+      const int mx = kEoLdsBytes + 4 * kFhatLdsBytes;
+      hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t32_kernel<0>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+      hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t32_kernel<1>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+      hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t32_kernel<2>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+      return true;
+    }();
+    (void)attr_set;
+    if (args.out_kind == 0) hipLaunchKernelGGL(fx16_t32_kernel<0>, grid, block, lds, stream, args);
+    else if (args.out_kind == 1) hipLaunchKernelGGL(fx16_t32_kernel<1>, grid, block, lds, stream, args);
+    else hipLaunchKernelGGL(fx16_t32_kernel<2>, grid, block, lds, stream, args);
   } else {
     if (args.out_kind == 0) hipLaunchKernelGGL(fp32_t32_kernel<0>, grid, block, 0, stream, args);
     else if (args.out_kind == 1) hipLaunchKernelGGL(fp32_t32_kernel<1>, grid, block, 0, stream, args);

@@ -75,6 +75,10 @@ __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, 
     else finish_cell<2, LY>(a, cell, fv, q, lane);
     return;
   }
+  // The velocities and addresses below are the same for every cell; an opaque
+  // lane index keeps the compiler from hoisting them out of the cell loop,
+  // where they would occupy registers through the whole filter loop.
+  asm volatile("" : "+v"(lane));
   constexpr int kV = LY::V;
   const int n = a.n;
   const int c = LY::col(lane);
@@ -146,6 +150,7 @@ __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, 
 // Load one cell's n x n field into a register layout, zero outside the grid.
 template <class LY>
 __device__ __forceinline__ void load_cell(const KernelArgs& a, int64_t cell, int lane, float* fv) {
+  asm volatile("" : "+v"(lane));  // per-cell addresses, not hoisted (as in finish_cell)
   const int n = a.n, c = LY::col(lane);
   const float* fc = a.f + cell * static_cast<int64_t>(n) * n;
 #pragma unroll
@@ -178,11 +183,21 @@ __device__ __forceinline__ half2v pk(float a, float b) {
   return __builtin_bit_cast(half2v, r);
 }
 
+// -1.0f that the compiler cannot fold: r + (-1) * hi with hi an FP16 value is
+// then one v_fma_mix_f32 (FP16 operand converted inside the FMA) instead of a
+// conversion plus a subtraction.
+__device__ __forceinline__ float opaque_neg_one() {
+  float m = -1.0f;
+  asm("" : "+s"(m));
+  return m;
+}
+
 __device__ __forceinline__ P3 finish_pair(float na, float nb, float ra, float rb) {
+  const float m1 = opaque_neg_one();
   P3 s;
   s.l = pk(na, nb);
   s.h = pk(ra, rb);
-  s.o = pk(ra - static_cast<float>(s.h.x), rb - static_cast<float>(s.h.y));
+  s.o = pk(fmaf(m1, static_cast<float>(s.h.x), ra), fmaf(m1, static_cast<float>(s.h.y), rb));
   return s;
 }
 

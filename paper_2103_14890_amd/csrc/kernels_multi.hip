@@ -15,7 +15,8 @@
 namespace qcoll {
 namespace {
 
-__global__ __launch_bounds__(256) void multi_kernel(MultiArgs m) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void multi_kernel(MultiArgs m) {
+  extern __shared__ double2 lds[];
   const int64_t b = blockIdx.x;
   int s = 0;
 #pragma unroll 1
@@ -25,7 +26,11 @@ __global__ __launch_bounds__(256) void multi_kernel(MultiArgs m) {
   const int64_t first = (b - m.block_start[s]) * wpb + (threadIdx.x >> 6);
   const int64_t stride = (m.block_start[s + 1] - m.block_start[s]) * wpb;
   if (a.tile == 32) {
-    if (a.precision == 4) fx16_t32_body<-1>(a, first, stride);
+    if (a.precision == 4) {  // block-uniform branch: the table load's barrier is safe
+      half8* eo = reinterpret_cast<half8*>(lds);
+      load_eo_table(a, eo);
+      fx16_t32_body<-1>(a, first, stride, lds + (kEoLdsBytes + (threadIdx.x >> 6) * kFhatLdsBytes) / 16, eo);
+    }
     else fp32_t32_body<-1>(a, first, stride);
   } else {
     if (a.precision == 4) fx16_t16_body<-1>(a, first, stride);
@@ -38,8 +43,14 @@ __global__ __launch_bounds__(256) void multi_kernel(MultiArgs m) {
 int launch_multi(const MultiArgs& args, int waves_per_block, hipStream_t stream) {
   const int64_t blocks = args.block_start[args.nslots];
   if (blocks <= 0) return 0;
-  hipLaunchKernelGGL(multi_kernel, dim3(static_cast<unsigned>(blocks)), dim3(64 * waves_per_block), 0,
-                     stream, args);
+  static const bool attr_set = [] {  // dynamic LDS above the 64 KB default (4 waves: 70 KB)
+    hipFuncSetAttribute(reinterpret_cast<const void*>(multi_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                        kEoLdsBytes + 4 * kFhatLdsBytes);
+    return true;
+  }();
+  (void)attr_set;
+  hipLaunchKernelGGL(multi_kernel, dim3(static_cast<unsigned>(blocks)), dim3(64 * waves_per_block),
+                     kEoLdsBytes + kFhatLdsBytes * waves_per_block, stream, args);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
