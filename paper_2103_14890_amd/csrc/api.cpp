@@ -26,6 +26,10 @@ struct qcoll_plan_s {
   float* filt32 = nullptr;
   float* loss32 = nullptr;
   double* tw = nullptr;
+  float* filt3 = nullptr;    // 3D: [P+1][T^3] complex FP32
+  char* scratch = nullptr;   // 3D: per-workgroup spectrum, work field and gain
+  int64_t scratch_stride = 0;
+  int64_t scratch_blocks = 0;
   int tile = 32;
   int64_t device_bytes = 0;
   int64_t max_blocks = 0;    // grid cap of single-plan launches
@@ -65,6 +69,10 @@ void free_device(qcoll_plan_s* p) {
   hipFree(p->filt32);
   hipFree(p->loss32);
   hipFree(p->tw);
+  hipFree(p->filt3);
+  hipFree(p->scratch);
+  p->filt3 = nullptr;
+  p->scratch = nullptr;
   p->tw = nullptr;
   p->econst = nullptr;
   p->filt = p->loss = nullptr;
@@ -334,6 +342,95 @@ int build_device_2d64(qcoll_plan_s* p) {
   return upload(tw, &p->tw, p->device_bytes);
 }
 
+// Device tables of the 3D kernel: per-lane DFT-matrix values for the T^3 tile
+// (MFMA step s, lane l: x = l % T, j = (64 / T) s + l / T; cos, sin, -sin of
+// 2 pi x j / n, zero outside n x n), the packed filters and the loss multiplier
+// on the padded mode grid, and the per-workgroup scratch.
+int build_device_3d(qcoll_plan_s* p) {
+  const auto& hp = p->hp;
+  const int n = hp.N, T = p->tile, KS = 64 / T, NS = T / KS;
+  const int P = static_cast<int>(hp.packed.size());
+  std::vector<float> ec(static_cast<size_t>(64) * 3 * NS);
+  for (int lane = 0; lane < 64; ++lane) {
+    const int x = lane % T, jl = lane / T;
+    for (int st = 0; st < NS; ++st) {
+      const int j = KS * st + jl;
+      double c = 0.0, sn = 0.0;
+      if (x < n && j < n) {
+        const double ang = 2.0 * kPi * static_cast<double>((x * j) % n) / n;
+        c = std::cos(ang);
+        sn = std::sin(ang);
+      }
+      ec[(lane * 3 + 0) * NS + st] = static_cast<float>(c);
+      ec[(lane * 3 + 1) * NS + st] = static_cast<float>(sn);
+      ec[(lane * 3 + 2) * NS + st] = static_cast<float>(-sn);
+    }
+  }
+  float* d = nullptr;
+  int rc = upload(ec, &d, p->device_bytes);
+  p->econst = d;
+  if (rc) return rc;
+  const int64_t T3 = static_cast<int64_t>(T) * T * T;
+  std::vector<float> ft(static_cast<size_t>(P + 1) * T3 * 2, 0.0f);
+  for (int q = 0; q <= P; ++q)
+    for (int k0 = 0; k0 < n; ++k0)
+      for (int k1 = 0; k1 < n; ++k1)
+        for (int k2 = 0; k2 < n; ++k2) {
+          const int64_t k = (static_cast<int64_t>(k0) * n + k1) * n + k2;
+          const size_t o = (static_cast<size_t>(q) * T3 + (static_cast<int64_t>(k0) * T + k1) * T + k2) * 2;
+          if (q < P) {
+            ft[o] = static_cast<float>(hp.packed[q][k].real());
+            ft[o + 1] = static_cast<float>(hp.packed[q][k].imag());
+          } else {
+            ft[o] = static_cast<float>(hp.loss_scaled[k]);
+          }
+        }
+  if ((rc = upload(ft, &p->filt3, p->device_bytes))) return rc;
+  // scratch: complex spectrum and work field (8 T^3 bytes each) and the FP64
+  // gain (8 T^3 bytes) per workgroup; two workgroups per CU for 32^3 tiles
+  p->scratch_stride = 24 * T3;
+  p->scratch_blocks = static_cast<int64_t>(p->cus) * (T == 32 ? 2 : 4);
+  const size_t sb = static_cast<size_t>(p->scratch_stride) * p->scratch_blocks;
+  if (hipMalloc(reinterpret_cast<void**>(&p->scratch), sb) != hipSuccess) return QCOLL_ENOMEM;
+  p->device_bytes += static_cast<int64_t>(sb);
+  return QCOLL_OK;
+}
+
+qcoll::Slot3 make_slot3(const qcoll_plan_s* p) {
+  qcoll::Slot3 a;
+  a.n = p->hp.N;
+  a.T = p->tile;
+  a.P = static_cast<int>(p->hp.packed.size());
+  a.econst = static_cast<const float*>(p->econst);
+  a.filt = p->filt3;
+  for (int i = 0; i < 25 && i < static_cast<int>(p->hp.gram_inv.size()); ++i) a.gram_inv[i] = p->hp.gram_inv[i];
+  a.L = p->hp.L;
+  a.dv = 2.0 * p->hp.L / p->hp.N;
+  return a;
+}
+
+// One 3D launch over the given slots, using the scratch of the plan with the
+// largest tile.
+int launch3(const qcoll_plan_s* const* plans, const qcoll::Slot3* slots, int nslots, const int64_t* cells,
+            hipStream_t stream) {
+  qcoll::Args3 A;
+  const qcoll_plan_s* big = nullptr;
+  int64_t total = 0;
+  for (int i = 0; i < nslots; ++i) {
+    if (!big || plans[i]->tile > big->tile) big = plans[i];
+    A.slot[A.nslots] = slots[i];
+    A.cell_start[A.nslots] = total;
+    total += cells[i];
+    ++A.nslots;
+  }
+  A.cell_start[A.nslots] = total;
+  if (!big || total == 0) return 0;
+  A.scratch = big->scratch;
+  A.scratch_stride = big->scratch_stride;
+  A.blocks = big->scratch_blocks;
+  return qcoll::launch_3d(A, stream);
+}
+
 qcoll::KernelArgs make_args(const qcoll_plan_s* p) {
   qcoll::KernelArgs a;
   a.econst = p->econst;
@@ -359,6 +456,7 @@ qcoll::KernelArgs make_args(const qcoll_plan_s* p) {
 // 2D grids up to 32 points per axis run on the 16x16 (N <= 16) or 32x32 tile
 // kernels; grids of 34..64 points on the tile-64 kernel (FX16 only).
 bool device_supported(const qcoll::HostPlan& hp, int precision) {
+  if (hp.d == 3) return hp.N <= 32 && precision == QCOLL_FP32;
   if (hp.d != 2) return false;
   if (hp.N <= 32) return true;
   return hp.N <= 64 && precision == QCOLL_MIX_FX16;
@@ -399,7 +497,8 @@ int qcoll_plan(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, do
     p->cus = cus;
     p->max_blocks = static_cast<int64_t>(cus) * 8;
     p->tile = p->hp.N > 32 ? 64 : (p->hp.N > 16 ? 32 : 16);
-    rc = p->tile == 64 ? build_device_2d64(p) : (p->tile == 32 ? build_device_2d32(p) : build_device_2d16(p));
+    if (p->hp.d == 3) rc = build_device_3d(p);
+    else rc = p->tile == 64 ? build_device_2d64(p) : (p->tile == 32 ? build_device_2d32(p) : build_device_2d16(p));
     if (rc) {
       free_device(p);
       delete p;
@@ -416,8 +515,16 @@ int qcoll_eval(qcoll_plan_t p, const float* f, void* Q, int64_t cells, hipStream
   if (!p->on_device) return QCOLL_EUNSUPPORTED;
   if (cells == 0) return QCOLL_OK;
   if (!f || !Q) return QCOLL_EINVAL;
-  int64_t n = static_cast<int64_t>(p->hp.N) * p->hp.N;
+  int64_t n = static_cast<int64_t>(p->hp.N) * p->hp.N * (p->hp.d == 3 ? p->hp.N : 1);
   if (cells > (INT64_MAX / 8) / n) return QCOLL_EINVAL;
+  if (p->hp.d == 3) {
+    qcoll::Slot3 s3 = make_slot3(p);
+    s3.f = f;
+    s3.q = Q;
+    s3.out_kind = (p->flags & QCOLL_CONSERVE) ? 1 : 0;
+    const qcoll_plan_s* pl = p;
+    return launch3(&pl, &s3, 1, &cells, stream) ? QCOLL_EDEVICE : QCOLL_OK;
+  }
   qcoll::KernelArgs a = make_args(p);
   a.f = f;
   a.q = Q;
@@ -434,6 +541,16 @@ int qcoll_step(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps, i
   if (!p->on_device) return QCOLL_EUNSUPPORTED;
   if (cells == 0) return QCOLL_OK;
   if (!f) return QCOLL_EINVAL;
+  if (p->hp.d == 3) {
+    qcoll::Slot3 s3 = make_slot3(p);
+    s3.f = f;
+    s3.dt_eps = dt / eps;
+    s3.scheme = scheme;
+    s3.status = status;
+    s3.out_kind = 2;
+    const qcoll_plan_s* pl = p;
+    return launch3(&pl, &s3, 1, &cells, stream) ? QCOLL_EDEVICE : QCOLL_OK;
+  }
   qcoll::KernelArgs a = make_args(p);
   a.f = f;
   a.cells = cells;
@@ -464,6 +581,32 @@ static int multi_launch(const qcoll_plan_t* plans, int nplans, const float* cons
     dev = p->device;
     if (cells[i] > 0 && (!f[i] || (!step && !Q[i]))) return QCOLL_EINVAL;
     if (p->tile == 64) return QCOLL_EUNSUPPORTED;
+    if (p->hp.d != plans[0]->hp.d) return QCOLL_EUNSUPPORTED;  // 2D and 3D plans do not mix
+  }
+  if (nplans > 0 && plans[0]->hp.d == 3) {
+    const qcoll_plan_s* pl[qcoll::kMaxSlots];
+    qcoll::Slot3 sl[qcoll::kMaxSlots];
+    int64_t cs[qcoll::kMaxSlots];
+    int ns = 0;
+    for (int i = 0; i < nplans; ++i) {
+      if (cells[i] == 0) continue;
+      pl[ns] = plans[i];
+      sl[ns] = make_slot3(plans[i]);
+      sl[ns].f = f[i];
+      if (step) {
+        sl[ns].dt_eps = dt / eps;
+        sl[ns].scheme = scheme;
+        sl[ns].status = status ? status[i] : nullptr;
+        sl[ns].out_kind = 2;
+      } else {
+        sl[ns].q = Q[i];
+        sl[ns].out_kind = (plans[i]->flags & QCOLL_CONSERVE) ? 1 : 0;
+      }
+      cs[ns] = cells[i];
+      ++ns;
+    }
+    if (ns == 0) return QCOLL_OK;
+    return launch3(pl, sl, ns, cs, stream) ? QCOLL_EDEVICE : QCOLL_OK;
   }
   for (int i = 0; i < nplans; ++i) {
     if (cells[i] == 0) continue;
@@ -522,7 +665,7 @@ int qcoll_plan_get_launch(qcoll_plan_t p, int* waves_per_block, int64_t* max_blo
 // stream. Q receives the result of the last timed launch.
 int qcoll_plan_autotune(qcoll_plan_t p, const float* f, void* Q, int64_t cells, int reps, hipStream_t stream) {
   if (!p || !f || !Q || cells < 1 || reps < 1) return QCOLL_EINVAL;
-  if (!p->on_device) return QCOLL_EUNSUPPORTED;
+  if (!p->on_device || p->hp.d == 3) return QCOLL_EUNSUPPORTED;  // 3D: one fixed launch shape
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return QCOLL_EDEVICE;
   const int wpbs[3] = {1, 2, 4};

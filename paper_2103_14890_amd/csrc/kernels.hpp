@@ -42,6 +42,34 @@ struct MultiArgs {
   KernelArgs slot[kMaxSlots];
 };
 
+// 3D velocity grids (FP32 MFMA; one workgroup of four wavefronts per cell).
+// Slot s of a launch covers the cells [cell_start[s], cell_start[s+1]) of the
+// launch's global cell range; every slot has its own plan tables.
+struct Slot3 {
+  const float* f = nullptr;     // [cells][n^3]
+  void* q = nullptr;            // [cells][n^3] float, or double with the projection
+  int n = 0;                    // grid points per axis (<= T)
+  int T = 32;                   // tile edge: 16 or 32 (zero padding up to T)
+  int P = 0;                    // gain transforms; entry P of filt is the loss multiplier
+  const float* econst = nullptr;  // [64 lanes][cos, sin, -sin][T/(64/T) steps]
+  const float* filt = nullptr;    // [P+1][T^3][re, im], modes in FFT order per axis
+  double gram_inv[25] = {};     // inverse Gram matrix of (1, v1, v2, v3, |v|^2)
+  double L = 0, dv = 0;
+  double dt_eps = 0;
+  int scheme = 0;
+  int32_t* status = nullptr;
+  int out_kind = 0;             // 0 eval (float Q), 1 eval with projection (double Q), 2 step
+};
+struct Args3 {
+  int nslots = 0;
+  int64_t cell_start[kMaxSlots + 1] = {};
+  Slot3 slot[kMaxSlots];
+  char* scratch = nullptr;      // per workgroup: spectrum, work field (complex FP32), gain (FP64)
+  int64_t scratch_stride = 0;   // bytes per workgroup (24 T^3 for the largest T)
+  int64_t blocks = 0;           // workgroups (at most the scratch capacity)
+};
+int launch_3d(const Args3& args, hipStream_t stream);
+
 // Single-plan launches (args.tile selects the 16x16 or 32x32 kernel family).
 int launch_2d16(const KernelArgs& args, hipStream_t stream);
 int launch_2d32(const KernelArgs& args, hipStream_t stream);

@@ -1,0 +1,356 @@
+// Fast spectral collision operator on 3D velocity grids, gfx950.
+//
+// Grids of n <= 32 points per axis run zero-padded in a T^3 tile (T = 16 for
+// n <= 16, else 32); the DFT matrices are zero outside n x n, so the padding
+// never mixes into the result. One workgroup of four wavefronts evaluates one
+// cell; cells of several plans (grids) share one launch through a slot table.
+//
+// The 3D DFT is three passes, one per axis, each a batch of 1-D complex DFTs
+// done as FP32 MFMA GEMMs over tiles of T lines (section 3.3: the kernel modes
+// become A products in Fourier space, each evaluated by FFT-sized transforms).
+// A cell's complex spectrum, the work field between passes and the FP64 gain
+// live in a per-workgroup scratch area (global memory, cached in L2/MALL):
+// a 32^3 complex field is 256 KB, more than the LDS of a CU.
+//
+// Layouts: fields are [i0][i1][i2] with i2 fastest (f and Q use the same order
+// with n instead of T). Passes along axes 0 and 1 use the data as the right
+// MFMA operand (lines on the lanes: coalesced loads and stores); the pass along
+// axis 2 uses the data as the left operand, so that its output has the lines in
+// registers and the transformed index on the lanes (coalesced stores). The
+// per-lane DFT-matrix values are the same in both roles since E is symmetric.
+//
+// Per cell: forward passes axis 2, 1, 0 -> spectrum; for each packed transform q
+// the inverse passes axis 0 (multiplying the spectrum by the filter on load),
+// 1, 2 (accumulating Re * Im into the gain, FP64); the last transform is the
+// loss multiplier, whose real field gives Q = gain - f * loss. Then the FP64
+// conservation projection or the stage update, as in the 2D kernels.
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels_common.hpp"
+
+namespace qcoll {
+namespace {
+
+template <int T>
+struct Sh;
+
+// v_mfma_f32_32x32x2f32: A 32x2 (lane: row l%32, k l/32), B 2x32 (k l/32,
+// column l%32), D 32x32 with column l%32 and 16 rows per lane.
+template <>
+struct Sh<32> {
+  static constexpr int KS = 2, NS = 16, NR = 16;
+  typedef f32x16 acc;
+  __device__ static int row(int v, int l) { return 8 * (v >> 2) + 4 * (l >> 5) + (v & 3); }
+  __device__ static acc mfma(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0); }
+};
+
+// v_mfma_f32_16x16x4f32: A 16x4 (row l%16, k l/16), B 4x16 (k l/16, column
+// l%16), D 16x16 with column l%16 and rows 4 (l/16) + v.
+template <>
+struct Sh<16> {
+  static constexpr int KS = 4, NS = 4, NR = 4;
+  typedef f32x4 acc;
+  __device__ static int row(int v, int l) { return 4 * (l >> 4) + v; }
+  __device__ static acc mfma(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+
+// Per-lane DFT-matrix values: for step s, e(x, j) with x = lane % T and
+// j = KS s + lane / T, as cos, sin and -sin of 2 pi x j / n.
+template <int T>
+struct Emat {
+  float c[Sh<T>::NS], s[Sh<T>::NS], ns[Sh<T>::NS];
+};
+
+// One complex pass over a tile. Inputs xr, xi: per step, point j of line x
+// (DB: data as the right operand, D = E X; otherwise the left operand, D = X E).
+// Forward E = C - iS, inverse E = C + iS.
+template <int T, bool DB, bool INV, bool REAL_IN>
+__device__ __forceinline__ void tile_dft(const Emat<T>& E, const float* xr, const float* xi,
+                                         typename Sh<T>::acc& dr, typename Sh<T>::acc& di) {
+  using S = Sh<T>;
+  dr = typename S::acc{};
+  di = typename S::acc{};
+#pragma unroll
+  for (int s = 0; s < S::NS; ++s) {
+    const float c = E.c[s];
+    const float sr = INV ? E.ns[s] : E.s[s];  // multiplies xi in the real part
+    const float si = INV ? E.s[s] : E.ns[s];  // multiplies xr in the imaginary part
+    if (DB) {
+      dr = S::mfma(c, xr[s], dr);
+      di = S::mfma(si, xr[s], di);
+      if (!REAL_IN) {
+        dr = S::mfma(sr, xi[s], dr);
+        di = S::mfma(c, xi[s], di);
+      }
+    } else {
+      dr = S::mfma(xr[s], c, dr);
+      di = S::mfma(xr[s], si, di);
+      if (!REAL_IN) {
+        dr = S::mfma(xi[s], sr, dr);
+        di = S::mfma(xi[s], c, di);
+      }
+    }
+  }
+}
+
+// Sum over the workgroup (four wavefronts) of K values per thread.
+template <int K>
+__device__ __forceinline__ void block_sum(double* x, double* red) {
+#pragma unroll
+  for (int i = 0; i < K; ++i) x[i] = wave_sum(x[i]);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int i = 0; i < K; ++i) red[w * 8 + i] = x[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < K; ++i) x[i] = red[i] + red[8 + i] + red[16 + i] + red[24 + i];
+}
+
+// Per-lane indices are re-derived from an opaque copy of the lane id at the top
+// of every tile loop, so that per-lane addresses are formed where they are
+// used instead of being hoisted out of the transform loop into hundreds of
+// live VGPRs.
+#define OPAQUE_LANE()               \
+  int lane = threadIdx.x & 63;      \
+  asm volatile("" : "+v"(lane));    \
+  const int x = lane % T, jl = lane / T; \
+  (void)jl
+
+template <int T>
+__device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red) {
+  using S = Sh<T>;
+  constexpr int T2 = T * T, T3 = T * T * T;
+  const int w = threadIdx.x >> 6;
+  const int n = a.n;
+  float2* fh = reinterpret_cast<float2*>(scratch);
+  float2* work = fh + T3;
+  double* gain = reinterpret_cast<double*>(work + T3);
+  const float* fc = a.f + cell * static_cast<int64_t>(n) * n * n;
+
+  Emat<T> E;
+  {
+    const int lane = threadIdx.x & 63;
+    const float* src = a.econst + lane * 3 * S::NS;
+#pragma unroll
+    for (int s = 0; s < S::NS; ++s) {
+      E.c[s] = src[s];
+      E.s[s] = src[S::NS + s];
+      E.ns[s] = src[2 * S::NS + s];
+    }
+  }
+  typename S::acc dr, di;
+  float xr[S::NS], xi[S::NS];
+
+  // ---- forward pass, axis 2 (real input; data as the left operand); tile t = i0
+  double fsum = 0.0;
+#pragma unroll 1
+  for (int t = w; t < T; t += 4) {
+    OPAQUE_LANE();
+#pragma unroll
+    for (int s = 0; s < S::NS; ++s) {
+      const int j = S::KS * s + jl;
+      xr[s] = (t < n && x < n && j < n) ? fc[(t * n + x) * n + j] : 0.0f;
+      fsum += static_cast<double>(xr[s]);
+    }
+    tile_dft<T, false, false, true>(E, xr, xi, dr, di);
+#pragma unroll
+    for (int v = 0; v < S::NR; ++v) work[t * T2 + S::row(v, lane) * T + x] = make_float2(dr[v], di[v]);
+  }
+  __syncthreads();
+  // ---- forward pass, axis 1 (tile t = i0, lanes over i2)
+#pragma unroll 1
+  for (int t = w; t < T; t += 4) {
+    OPAQUE_LANE();
+#pragma unroll
+    for (int s = 0; s < S::NS; ++s) {
+      const float2 z = work[t * T2 + (S::KS * s + jl) * T + x];
+      xr[s] = z.x;
+      xi[s] = z.y;
+    }
+    tile_dft<T, true, false, false>(E, xr, xi, dr, di);
+#pragma unroll
+    for (int v = 0; v < S::NR; ++v) work[t * T2 + S::row(v, lane) * T + x] = make_float2(dr[v], di[v]);
+  }
+  __syncthreads();
+  // ---- forward pass, axis 0 (tile t = i1, lanes over i2) -> spectrum
+#pragma unroll 1
+  for (int t = w; t < T; t += 4) {
+    OPAQUE_LANE();
+#pragma unroll
+    for (int s = 0; s < S::NS; ++s) {
+      const float2 z = work[(S::KS * s + jl) * T2 + t * T + x];
+      xr[s] = z.x;
+      xi[s] = z.y;
+    }
+    tile_dft<T, true, false, false>(E, xr, xi, dr, di);
+#pragma unroll
+    for (int v = 0; v < S::NR; ++v) fh[S::row(v, lane) * T2 + t * T + x] = make_float2(dr[v], di[v]);
+  }
+  __syncthreads();
+
+  double mom[5] = {0, 0, 0, 0, 0};
+  for (int q = 0; q <= a.P; ++q) {
+    const float2* mq = reinterpret_cast<const float2*>(a.filt) + static_cast<int64_t>(q) * T3;
+    // ---- inverse pass, axis 0: filter times spectrum on load (tile t = k1)
+#pragma unroll 1
+    for (int t = w; t < T; t += 4) {
+      OPAQUE_LANE();
+#pragma unroll
+      for (int s = 0; s < S::NS; ++s) {
+        const int o = (S::KS * s + jl) * T2 + t * T + x;
+        const float2 z = fh[o], m = mq[o];
+        xr[s] = m.x * z.x - m.y * z.y;
+        xi[s] = m.x * z.y + m.y * z.x;
+      }
+      tile_dft<T, true, true, false>(E, xr, xi, dr, di);
+#pragma unroll
+      for (int v = 0; v < S::NR; ++v) work[S::row(v, lane) * T2 + t * T + x] = make_float2(dr[v], di[v]);
+    }
+    __syncthreads();
+    // ---- inverse pass, axis 1 (tile t = i0)
+#pragma unroll 1
+    for (int t = w; t < T; t += 4) {
+      OPAQUE_LANE();
+#pragma unroll
+      for (int s = 0; s < S::NS; ++s) {
+        const float2 z = work[t * T2 + (S::KS * s + jl) * T + x];
+        xr[s] = z.x;
+        xi[s] = z.y;
+      }
+      tile_dft<T, true, true, false>(E, xr, xi, dr, di);
+#pragma unroll
+      for (int v = 0; v < S::NR; ++v) work[t * T2 + S::row(v, lane) * T + x] = make_float2(dr[v], di[v]);
+    }
+    __syncthreads();
+    // ---- inverse pass, axis 2 (data as the left operand; tile t = i0, lines
+    // i1 = x on the lanes, output point (t, row, x)) and the gain
+#pragma unroll 1
+    for (int t = w; t < T; t += 4) {
+      OPAQUE_LANE();
+#pragma unroll
+      for (int s = 0; s < S::NS; ++s) {
+        const float2 z = work[t * T2 + x * T + S::KS * s + jl];
+        xr[s] = z.x;
+        xi[s] = z.y;
+      }
+      tile_dft<T, false, true, false>(E, xr, xi, dr, di);
+      if (q < a.P) {
+#pragma unroll
+        for (int v = 0; v < S::NR; ++v) {
+          const int o = t * T2 + S::row(v, lane) * T + x;
+          const double g = static_cast<double>(dr[v]) * static_cast<double>(di[v]);
+          gain[o] = q == 0 ? g : gain[o] + g;
+        }
+      } else {
+        // loss field: Q = gain - f * loss on the grid points, zero elsewhere
+#pragma unroll
+        for (int v = 0; v < S::NR; ++v) {
+          const int r = S::row(v, lane);
+          const int o = t * T2 + r * T + x;
+          double Q = 0.0;
+          if (t < n && r < n && x < n) {
+            const double fv = static_cast<double>(fc[(t * n + r) * n + x]);
+            Q = (a.P > 0 ? gain[o] : 0.0) - fv * static_cast<double>(dr[v]);
+            const double v0 = -a.L + a.dv * t, v1 = -a.L + a.dv * r, v2 = -a.L + a.dv * x;
+            mom[0] += Q;
+            mom[1] += v0 * Q;
+            mom[2] += v1 * Q;
+            mom[3] += v2 * Q;
+            mom[4] += (v0 * v0 + v1 * v1 + v2 * v2) * Q;
+          }
+          gain[o] = Q;
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- epilogue over this thread's points (those it wrote in the last pass)
+  OPAQUE_LANE();
+  const int64_t base = cell * static_cast<int64_t>(n) * n * n;
+  if (a.out_kind == 0) {
+    float* Qc = reinterpret_cast<float*>(a.q) + base;
+    for (int t = w; t < T; t += 4)
+#pragma unroll
+      for (int v = 0; v < S::NR; ++v) {
+        const int r = S::row(v, lane);
+        if (t < n && r < n && x < n) Qc[(t * n + r) * n + x] = static_cast<float>(gain[t * T2 + r * T + x]);
+      }
+  } else if (a.out_kind == 1) {
+    block_sum<5>(mom, red);
+    double lam[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      lam[i] = 0.0;
+#pragma unroll
+      for (int j = 0; j < 5; ++j) lam[i] += a.gram_inv[i * 5 + j] * mom[j];
+    }
+    double* Qc = reinterpret_cast<double*>(a.q) + base;
+    for (int t = w; t < T; t += 4)
+#pragma unroll
+      for (int v = 0; v < S::NR; ++v) {
+        const int r = S::row(v, lane);
+        if (t < n && r < n && x < n) {
+          const double v0 = -a.L + a.dv * t, v1 = -a.L + a.dv * r, v2 = -a.L + a.dv * x;
+          const double corr = lam[0] + lam[1] * v0 + lam[2] * v1 + lam[3] * v2 + lam[4] * (v0 * v0 + v1 * v1 + v2 * v2);
+          Qc[(t * n + r) * n + x] = gain[t * T2 + r * T + x] - corr;
+        }
+      }
+  } else {
+    double rs[1] = {fsum};
+    block_sum<1>(rs, red);
+    const double rho = rs[0] * a.dv * a.dv * a.dv;
+    const double k = a.scheme == 1 ? a.dt_eps / (1.0 + a.dt_eps * rho) : a.dt_eps;
+    float* fw = const_cast<float*>(a.f) + base;
+    int bad = 0;
+    for (int t = w; t < T; t += 4)
+#pragma unroll
+      for (int v = 0; v < S::NR; ++v) {
+        const int r = S::row(v, lane);
+        if (t < n && r < n && x < n) {
+          const int o = (t * n + r) * n + x;
+          const float nv = static_cast<float>(static_cast<double>(fw[o]) + k * gain[t * T2 + r * T + x]);
+          bad |= !(fabsf(nv) <= 3.0e38f);
+          fw[o] = nv;
+        }
+      }
+    if (a.status) {
+      double b[1] = {static_cast<double>(__any(bad) ? 1 : 0)};
+      block_sum<1>(b, red);
+      if (threadIdx.x == 0) a.status[cell] = b[0] > 0.0 ? 1 : 0;
+    }
+  }
+  __syncthreads();  // scratch and red are reused by the next cell
+}
+
+__global__ __launch_bounds__(256) void fp32_3d_kernel(Args3 A) {
+  __shared__ double red[32];
+  char* scratch = A.scratch + static_cast<int64_t>(blockIdx.x) * A.scratch_stride;
+  const int64_t total = A.cell_start[A.nslots];
+  for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    int s = 0;
+#pragma unroll 1
+    while (s + 1 < A.nslots && g >= A.cell_start[s + 1]) ++s;
+    const Slot3& a = A.slot[s];
+    const int64_t cell = g - A.cell_start[s];
+    if (a.T == 32) cell_3d<32>(a, cell, scratch, red);
+    else cell_3d<16>(a, cell, scratch, red);
+  }
+}
+
+}  // namespace
+
+int launch_3d(const Args3& args, hipStream_t stream) {
+  const int64_t total = args.cell_start[args.nslots];
+  if (total <= 0) return 0;
+  int64_t blocks = total < args.blocks ? total : args.blocks;
+  hipLaunchKernelGGL(fp32_3d_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, args);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+}  // namespace qcoll

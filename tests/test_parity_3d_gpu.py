@@ -1,0 +1,166 @@
+"""GPU parity of the 3D path (FP32 MFMA, through the C ABI) against the FP64
+oracle: hard spheres on 3D grids (16^3 and 32^3 tiles, zero-padded sizes),
+the FP64 conservation projection, the stage updates, and the two-resolution
+batched launch of the 3D workload (32^3 and 16^3 cells in one launch).
+
+Tolerance: the plain-FP32 bound of the 2D tests (relative L2 2e-4 over the
+batch, 1e-3 per cell); the projection leaves mass, momentum and energy at FP64
+rounding (1e-12 relative).
+"""
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import spectral as sp
+from oracle import stepping
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL, CELL_TOL = 2e-4, 1e-3
+
+
+@pytest.fixture(scope="module")
+def qc():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2103_14890_amd import qcoll
+    return qcoll
+
+
+def _ref(f64, N, L, M):
+    s = sp.Setup(d=3, N=N, L=L, kernel="hard_sphere", M=M)
+    return sp.q_fast(f64.astype(np.float32).astype(np.float64), s, sp.filter_bank(s))
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _cell_rel(a, b):
+    n = a.shape[0]
+    return (np.linalg.norm((a - b).reshape(n, -1), axis=1) / np.linalg.norm(b.reshape(n, -1), axis=1)).max()
+
+
+def _eval(plan, f64, conserve=False):
+    f = torch.tensor(f64, dtype=torch.float32, device="cuda")
+    q = plan.eval(f)
+    torch.cuda.synchronize()
+    return q.cpu().double().numpy()
+
+
+@pytest.mark.parametrize("N,L,M,cells", [(16, 8.0, 8, 6), (16, 8.0, 32, 5), (12, 6.0, 8, 5), (8, 4.0, 8, 7),
+                                         (32, 8.0, 8, 3), (24, 8.0, 8, 3)])
+def test_parity_3d(qc, N, L, M, cells):
+    f = wl.mixture_cells(3, N, L, cells, 40 + N)
+    plan = qc.Plan(3, N, L, "hard_sphere", M, precision="fp32")
+    q = _eval(plan, f)
+    ref = _ref(f, N, L, M)
+    err, cerr = _rel(q, ref), _cell_rel(q, ref)
+    print(f"3D N={N} M={M}: rel L2 {err:.3e}, worst cell {cerr:.3e}")
+    assert err < TOL and cerr < CELL_TOL
+    plan.close()
+
+
+@pytest.mark.parametrize("N", [16, 32])
+def test_conservation_3d(qc, N):
+    cells = 4
+    f = wl.mixture_cells(3, N, 8.0, cells, 7)
+    plan = qc.Plan(3, N, 8.0, "hard_sphere", 8, precision="fp32", conserve=True)
+    qd = torch.empty((cells, N, N, N), dtype=torch.float64, device="cuda")
+    plan.eval(torch.tensor(f, dtype=torch.float32, device="cuda"), qd)
+    torch.cuda.synchronize()
+    q = qd.cpu().numpy()
+    mom = sp.moments(q, 3, 8.0)
+    scale = sp.moments(np.abs(q), 3, 8.0)
+    print(f"3D N={N} conserve: worst |moment| / scale {(np.abs(mom) / scale[:, [0, 0, 0, 0, 4]]).max():.3e}")
+    assert (np.abs(mom) <= 1e-12 * scale[:, [0, 0, 0, 0, 4]] + 1e-14).all()
+    ref = sp.project_conservative(_ref(f, N, 8.0, 8), 3, 8.0)
+    assert _rel(q, ref) < TOL
+    plan.close()
+
+
+@pytest.mark.parametrize("scheme", ["explicit", "imex"])
+def test_step_3d(qc, scheme):
+    N, L, cells = 16, 8.0, 5
+    f0 = wl.mixture_cells(3, N, L, cells, 9)
+    plan = qc.Plan(3, N, L, "hard_sphere", 8, precision="fp32")
+    f = torch.tensor(f0, dtype=torch.float32, device="cuda")
+    status = torch.full((cells,), -1, dtype=torch.int32, device="cuda")
+    dt, eps = 0.05, 0.5
+    plan.step(f, dt, eps, scheme, status)
+    torch.cuda.synchronize()
+    f32 = f0.astype(np.float32).astype(np.float64)
+    q = _ref(f0, N, L, 8)
+    want = (stepping.explicit_euler(f32, q, dt, eps) if scheme == "explicit"
+            else stepping.imex_euler_penalized(f32, q, dt, eps, 3, L))
+    got = f.cpu().double().numpy()
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print(f"3D step {scheme}: max rel {err:.3e}")
+    assert err <= 1e-5
+    assert (status.cpu().numpy() == 0).all()
+    plan.close()
+
+
+def test_step_3d_flags_nonfinite_cell_only(qc):
+    f0 = wl.mixture_cells(3, 16, 8.0, 4, 10)
+    f0[2, 3, 4, 5] = np.nan
+    plan = qc.Plan(3, 16, 8.0, "hard_sphere", 8, precision="fp32")
+    f = torch.tensor(f0, dtype=torch.float32, device="cuda")
+    status = torch.full((4,), -1, dtype=torch.int32, device="cuda")
+    plan.step(f, 0.01, 1.0, "explicit", status)
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    assert st[2] == 1 and (np.delete(st, 2) == 0).all()
+    assert np.isfinite(f.cpu().numpy()[[0, 1, 3]]).all()
+    plan.close()
+
+
+def test_two_resolutions_one_launch(qc):
+    """32^3 and 16^3 cells in one batched call equal the single-plan calls
+    bitwise, for eval with the projection and for the step."""
+    f32c = wl.mixture_cells(3, 32, 8.0, 3, 21)
+    f16c = wl.mixture_cells(3, 16, 8.0, 7, 22)
+    p32 = qc.Plan(3, 32, 8.0, "hard_sphere", 32, precision="fp32", conserve=True)
+    p16 = qc.Plan(3, 16, 8.0, "hard_sphere", 32, precision="fp32", conserve=True)
+    a = torch.tensor(f32c, dtype=torch.float32, device="cuda")
+    b = torch.tensor(f16c, dtype=torch.float32, device="cuda")
+    qa = torch.empty(a.shape, dtype=torch.float64, device="cuda")
+    qb = torch.empty(b.shape, dtype=torch.float64, device="cuda")
+    qc.eval_multi([p32, p16], [a, b], [qa, qb])
+    sa, sb = p32.eval(a), p16.eval(b)
+    torch.cuda.synchronize()
+    assert torch.equal(qa, sa) and torch.equal(qb, sb)
+    fa, fb = a.clone(), b.clone()
+    qc.step_multi([p32, p16], [a, b], 0.01, 1.0, "imex")
+    p32.step(fa, 0.01, 1.0, "imex")
+    p16.step(fb, 0.01, 1.0, "imex")
+    torch.cuda.synchronize()
+    assert torch.equal(a, fa) and torch.equal(b, fb)
+    ref = sp.project_conservative(_ref(f16c, 16, 8.0, 32), 3, 8.0)
+    err = _rel(qb.cpu().numpy(), ref)
+    print(f"two resolutions: 16^3 rel L2 {err:.3e}")
+    assert err < TOL
+    p32.close()
+    p16.close()
+
+
+def test_3d_workload_sampled_cells(qc):
+    """The 32^3 half of the 3D workload at 1024 cells in the launch shape of the
+    benchmark; 3 sampled cells against the oracle, and the projection's moments
+    on all cells."""
+    f = wl.config_inputs("hs3d_32", cells=1024)
+    plan = qc.Plan(3, 32, 8.0, "hard_sphere", 32, precision="fp32", conserve=True)
+    ft = torch.tensor(f, dtype=torch.float32, device="cuda")
+    q = plan.eval(ft)
+    torch.cuda.synchronize()
+    idx = np.array([0, 511, 1023])
+    got = q[idx].cpu().numpy()
+    ref = sp.project_conservative(_ref(f[idx], 32, 8.0, 32), 3, 8.0)
+    err = _rel(got, ref)
+    print(f"hs3d_32 1024 cells: sampled rel L2 {err:.3e}")
+    assert err < TOL
+    qa = q.cpu().numpy()
+    mass = np.abs(qa.sum(axis=(1, 2, 3))) / np.abs(qa).sum(axis=(1, 2, 3))
+    assert mass.max() <= 1e-12
+    plan.close()
