@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -29,6 +30,13 @@ WORKLOADS = {
                 "M=8 directions x K_r=5 radial ranks (21 transforms), FP64 conservation projection"),
     "hs2d_64_noisy": (64, 10.0, "hard_sphere", 16, "20000 cells, 2D 64x64 velocity grid on [-10,10]^2, hard "
                       "spheres, M=16 x K_r=5 (41 transforms), mixtures + 1% noise, FP64 conservation projection"),
+}
+# 3D workload: two resolutions in one launch (FP32 MFMA, FP64 projection)
+WORKLOADS_3D = {
+    "hs3d": (("hs3d_32", 32), ("hs3d_16", 16), 8.0, "hard_sphere", 32,
+             "8192 cells on a 32^3 grid + 8192 cells on a 16^3 grid, [-8,8]^3, hard spheres, M=32 "
+             "hemisphere directions (33 transforms), FP32 DFT-GEMMs, FP64 conservation projection, "
+             "both resolutions in one launch"),
 }
 HBM_PEAK = 8.0e12          # B/s
 FP16_MFMA_PEAK = 2.5e15    # dense FLOP/s
@@ -50,6 +58,14 @@ def mfma_flops_per_cell(precision: str, transforms: int, N: int = 32) -> float:
     if N > 32:                            # tile-64: four 32-point sub-transforms per cell
         per_cell *= 4
     return per_cell * (6 if precision == "fx16" else 1)
+
+
+def mfma_flops_per_cell_3d(T: int, transforms: int) -> float:
+    """FP32 MFMA flops of one 3D cell on a T^3 tile: every axis pass is T tiles of
+    (T/K) MFMA steps x 4 real products (2 for the real-input first forward pass)."""
+    per_mfma = 2 * (32 * 32 * 2 if T == 32 else 16 * 16 * 4)
+    per_pass = T * (T * T // 64) * 4 * per_mfma
+    return (2.5 + 3 * transforms) * per_pass
 
 
 def time_launches(fn, steps: int, warmup: int, stream):
@@ -87,13 +103,105 @@ def cpu_baseline(f64: np.ndarray, target_s: float, N: int, L: float, kernel: str
     return done, t_used, np.concatenate(outs)
 
 
+def serve_run(seconds: float, rate: float = 200.0, warm: float = 2.0) -> dict:
+    """Open-loop serving of homogeneous relaxation requests (continuous batching):
+    Poisson arrivals, N in {16, 24, 32, 48, 64}, Maxwell or hard spheres, 50-400
+    explicit Euler steps of dt = 0.01; latencies of requests arriving in the
+    first `warm` seconds are discarded."""
+    from paper_2103_14890_amd import serving as sv
+    reqs = sv.poisson_requests(int(seconds * rate), rate=rate, seed=1003, L=8.0)
+    server = sv.Server(L=8.0, M=8, precision="fx16", dt=0.01, eps=1.0, scheme="explicit")
+    stats = server.run(reqs, realtime=True)
+    lat = np.array([r.latency for r in server.results.values() if not r.failed and r.arrival >= warm])
+    server.close()
+    return {"requests": stats["requests"], "failed": stats["failed"], "rate_req_s": rate,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "throughput_req_s": stats["throughput_req_s"], "cell_steps_s": stats["cell_steps_s"],
+            "ticks": stats["ticks"], "wall_s": stats["wall_s"],
+            "mix": "N in {16,24,32,48,64}, Maxwell/hard spheres, 50-400 steps, M=8, FX16"}
+
+
+def bench_3d(args) -> int:
+    import torch
+    import workloads as wl
+    from oracle import spectral as sp
+    from paper_2103_14890_amd import qcoll
+
+    (name_a, Na), (name_b, Nb), L, kern, M, desc = WORKLOADS_3D[args.workload]
+    dev = torch.device("cuda:0")
+    fa64, fb64 = wl.config_inputs(name_a), wl.config_inputs(name_b)
+    fa = torch.tensor(fa64, dtype=torch.float32, device=dev)
+    fb = torch.tensor(fb64, dtype=torch.float32, device=dev)
+    pa = qcoll.Plan(3, Na, L, kern, M, precision="fp32", conserve=True)
+    pb = qcoll.Plan(3, Nb, L, kern, M, precision="fp32", conserve=True)
+    qa = torch.empty(fa.shape, dtype=torch.float64, device=dev)
+    qb = torch.empty(fb.shape, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    wall, per = time_launches(lambda: qcoll.eval_multi([pa, pb], [fa, fb], [qa, qb]), args.steps, args.warmup,
+                              stream)
+    T_ = float(np.mean(per))
+    cells = fa.shape[0] + fb.shape[0]
+    tr = pa.info()["transforms"]
+    flops = (mfma_flops_per_cell_3d(32, tr) * fa.shape[0] + mfma_flops_per_cell_3d(16, tr) * fb.shape[0])
+
+    # oracle on a bounded sample: equal numbers of cells of both resolutions
+    sa, sb = sp.Setup(d=3, N=Na, L=L, kernel=kern, M=M), sp.Setup(d=3, N=Nb, L=L, kernel=kern, M=M)
+    ba, bb = sp.filter_bank(sa), sp.filter_bank(sb)
+    done, t_cpu, errs = 0, 0.0, []
+    while t_cpu < args.cpu_seconds and done < 64:
+        i = done
+        t0 = time.perf_counter()
+        ra = sp.project_conservative(sp.q_fast(fa64[i:i + 1].astype(np.float32).astype(np.float64), sa, ba), 3, L)
+        rb = sp.project_conservative(sp.q_fast(fb64[i:i + 1].astype(np.float32).astype(np.float64), sb, bb), 3, L)
+        t_cpu += time.perf_counter() - t0
+        done += 1
+        errs.append((qa[i:i + 1].cpu().numpy(), ra, qb[i:i + 1].cpu().numpy(), rb))
+    num = sum(np.linalg.norm(x - y) ** 2 + np.linalg.norm(z - w) ** 2 for x, y, z, w in errs)
+    den = sum(np.linalg.norm(y) ** 2 + np.linalg.norm(w) ** 2 for x, y, z, w in errs)
+    qa_h = qa.cpu().numpy()
+    mass = float((np.abs(qa_h.sum(axis=(1, 2, 3))) / np.abs(qa_h).sum(axis=(1, 2, 3))).max())
+    out = {
+        "metric": "cell Q(f,f) evals/s, 3D hard spheres, 32^3 and 16^3 cells in one launch",
+        "value": cells / T_,
+        "unit": "cell-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": T_ * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "cells": cells, "N_v": [f"{Na}^3", f"{Nb}^3"],
+                   "kernel": kern, "M": M},
+        "roofline": {"bound": "mfma", "achieved": flops / T_ / 1e12, "peak": FP32_MFMA_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": flops / T_ / FP32_MFMA_PEAK, "traffic": None},
+        "cpu_baseline": {"value": 2 * done / t_cpu, "unit": "cell-evals/s", "cores": 1, "kind": "oracle",
+                         "sample": f"first {done} cells of each resolution, FP64 numpy FFT oracle + projection, "
+                                   f"{t_cpu:.1f} s"},
+        "rel_err_l2": float(math.sqrt(num / den)),
+        "mass_defect_max": mass,
+        "launch_ms": {"p5": float(np.percentile(per, 5) * 1e3), "p50": float(np.median(per) * 1e3),
+                      "p95": float(np.percentile(per, 95) * 1e3)},
+        "p99_latency_ms": None,
+    }
+    print(json.dumps(out))
+    pa.close()
+    pb.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", default="hs2d_32", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="hs2d_32", choices=sorted(WORKLOADS) + sorted(WORKLOADS_3D))
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the open-loop serving run (Poisson arrivals at 200 requests/s) "
+                         "behind p99_latency_ms; 0 skips it")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, copy a buffer of this many MiB once (a plain copy kernel of "
                          "known size, for scaling hardware byte counters)")
@@ -108,6 +216,8 @@ def main() -> int:
     from paper_2103_14890_amd import qcoll
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload in WORKLOADS_3D:
+        return bench_3d(args)
     dev = torch.device("cuda:0")
     NN, LL, KERN, MM, DESC = WORKLOADS[args.workload]
     f64 = wl.config_inputs(args.workload)
@@ -139,6 +249,8 @@ def main() -> int:
         res[prec]["rel_err"] = float(np.linalg.norm(qg - q_ref) / np.linalg.norm(q_ref))
         qa = res[prec]["q"].cpu().numpy()
         res[prec]["mass"] = float((np.abs(qa.sum(axis=(1, 2))) / np.abs(qa).sum(axis=(1, 2))).max())
+
+    serve = serve_run(args.serve_seconds) if args.serve_seconds > 0 else None
 
     mix = res["fx16"]
     T = float(np.mean(mix["per"]))
@@ -181,7 +293,8 @@ def main() -> int:
         "launch_ms": {"p5": float(np.percentile(mix["per"], 5) * 1e3),
                       "p50": float(np.median(mix["per"]) * 1e3),
                       "p95": float(np.percentile(mix["per"], 95) * 1e3)},
-        "p99_latency_ms": None,
+        "p99_latency_ms": None if serve is None else serve["p99_ms"],
+        "serving": serve,
     }
     print(json.dumps(out))
     for prec in res:

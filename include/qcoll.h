@@ -83,8 +83,10 @@ enum {
  * is set to NULL. Device plans: d = 2 with N <= 32 in either precision (grids
  * below 16 or 32 run zero-padded in a 16x16 or 32x32 tile) and 34 <= N <= 64
  * in QCOLL_MIX_FX16 (radix-2 split into 32-point tiles, one workgroup per
- * cell); other sizes and d = 3 are QCOLL_EUNSUPPORTED on the device (their
- * host tables build). */
+ * cell); d = 3 hard spheres with N <= 32 in QCOLL_FP32 (zero-padded 16^3 or
+ * 32^3 tiles, one workgroup per cell, a scratch area of 24 T^3 bytes per
+ * resident workgroup held by the plan). Other sizes and precisions are
+ * QCOLL_EUNSUPPORTED on the device (their host tables build). */
 int qcoll_plan(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, double b,
                int M, int K_r, int precision, unsigned flags);
 
@@ -110,10 +112,14 @@ int qcoll_step(qcoll_plan_t plan, float* f, int64_t cells, double dt, double eps
 /* Batched launches (cell-locality of section 3.3: cells of different velocity
  * grids and kernels share one launch). Slot i uses plans[i] with f[i], Q[i]
  * (or status[i]) and cells[i] exactly as the single-plan call; each cell's
- * result is bitwise equal to the single-plan launch. nplans <= 8, all plans on
- * one device; slots with cells[i] == 0 are skipped. status may be NULL. Plans
- * with N > 32 are QCOLL_EUNSUPPORTED here (their cells need a workgroup each;
- * launch them with the single-plan calls). */
+ * result is bitwise equal to the single-plan launch. nplans <= 64, all plans
+ * on one device; slots with cells[i] == 0 are skipped. status may be NULL.
+ * 2D plans with N <= 32 share one launch per 8 such slots; 2D plans with
+ * N > 32 (a workgroup per cell) get one launch each; 3D plans (all slots 3D)
+ * share one launch per 8 slots; all launches of a call are queued on the same
+ * stream. 2D and 3D plans cannot be mixed in
+ * one call (QCOLL_EUNSUPPORTED). 3D plans hold a scratch area: calls that use
+ * the same 3D plan must not run concurrently on different streams. */
 int qcoll_eval_multi(const qcoll_plan_t* plans, int nplans, const float* const* f, void* const* Q,
                      const int64_t* cells, hipStream_t stream);
 int qcoll_step_multi(const qcoll_plan_t* plans, int nplans, float* const* f, const int64_t* cells, double dt,

@@ -566,7 +566,7 @@ int qcoll_step(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps, i
 static int multi_launch(const qcoll_plan_t* plans, int nplans, const float* const* f, void* const* Q,
                         const int64_t* cells, bool step, double dt, double eps, int scheme,
                         int32_t* const* status, hipStream_t stream) {
-  if (!plans || nplans < 0 || nplans > qcoll::kMaxSlots || !f || !cells) return QCOLL_EINVAL;
+  if (!plans || nplans < 0 || nplans > 64 || !f || !cells) return QCOLL_EINVAL;
   if (!step && !Q) return QCOLL_EINVAL;
   if (step && (!(dt > 0.0) || !(eps > 0.0) || !std::isfinite(dt) || !std::isfinite(eps))) return QCOLL_EINVAL;
   if (step && scheme != QCOLL_EXPLICIT_EULER && scheme != QCOLL_IMEX_EULER_PENALIZED) return QCOLL_EINVAL;
@@ -580,7 +580,6 @@ static int multi_launch(const qcoll_plan_t* plans, int nplans, const float* cons
     if (dev >= 0 && p->device != dev) return QCOLL_EINVAL;
     dev = p->device;
     if (cells[i] > 0 && (!f[i] || (!step && !Q[i]))) return QCOLL_EINVAL;
-    if (p->tile == 64) return QCOLL_EUNSUPPORTED;
     if (p->hp.d != plans[0]->hp.d) return QCOLL_EUNSUPPORTED;  // 2D and 3D plans do not mix
   }
   if (nplans > 0 && plans[0]->hp.d == 3) {
@@ -590,6 +589,10 @@ static int multi_launch(const qcoll_plan_t* plans, int nplans, const float* cons
     int ns = 0;
     for (int i = 0; i < nplans; ++i) {
       if (cells[i] == 0) continue;
+      if (ns == qcoll::kMaxSlots) {  // slot table full: launch it and start the next
+        if (launch3(pl, sl, ns, cs, stream)) return QCOLL_EDEVICE;
+        ns = 0;
+      }
       pl[ns] = plans[i];
       sl[ns] = make_slot3(plans[i]);
       sl[ns].f = f[i];
@@ -622,6 +625,16 @@ static int multi_launch(const qcoll_plan_t* plans, int nplans, const float* cons
     } else {
       a.q = Q[i];
       a.out_kind = (p->flags & QCOLL_CONSERVE) ? 1 : 0;
+    }
+    if (p->tile == 64) {  // one workgroup per cell: a launch of its own on the same stream
+      if (qcoll::launch_2d64(a, stream)) return QCOLL_EDEVICE;
+      continue;
+    }
+    if (m.nslots == qcoll::kMaxSlots) {  // slot table full: launch it and start the next
+      m.block_start[m.nslots] = blocks;
+      if (qcoll::launch_multi(m, wpb, stream)) return QCOLL_EDEVICE;
+      m = qcoll::MultiArgs();
+      blocks = 0;
     }
     m.slot[m.nslots] = a;
     m.block_start[m.nslots] = blocks;

@@ -223,7 +223,7 @@ class Server:
             g.plan.close()
 
 
-def poisson_requests(n: int, rate: float, seed: int, L: float = 8.0, sizes=(16, 24, 32),
+def poisson_requests(n: int, rate: float, seed: int, L: float = 8.0, sizes=(16, 24, 32, 48, 64),
                      kernels=("maxwell", "hard_sphere"), steps=(50, 400)) -> list[Request]:
     """Open-loop Poisson arrivals with N, kernel and step count drawn uniformly;
     f0 is a two-Maxwellian mixture (the same generator as the batch workloads)."""

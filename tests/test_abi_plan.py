@@ -109,7 +109,8 @@ def test_multi_and_tuning_argument_checks():
     arr = (ctypes.c_void_p * 1)(p._h.value)
     ptrs = (ctypes.c_void_p * 1)(0)
     cells = (ctypes.c_int64 * 1)(4)
-    assert qc.LIB.qcoll_eval_multi(arr, 9, ptrs, ptrs, cells, None) == qc.EINVAL      # too many slots
+    assert qc.LIB.qcoll_eval_multi(arr, 65, ptrs, ptrs, cells, None) == qc.EINVAL     # too many slots
+    assert qc.LIB.qcoll_eval_multi(arr, -1, ptrs, ptrs, cells, None) == qc.EINVAL
     assert qc.LIB.qcoll_eval_multi(None, 1, ptrs, ptrs, cells, None) == qc.EINVAL
     assert qc.LIB.qcoll_eval_multi(arr, 1, ptrs, ptrs, cells, None) == qc.EUNSUPPORTED  # host-only plan
     assert qc.LIB.qcoll_step_multi(arr, 1, ptrs, cells, -1.0, 1.0, 0, None, None) == qc.EINVAL

@@ -24,7 +24,8 @@ def qc():
 
 SLOTS = [(32, 8.0, "hard_sphere", 8, "fx16", False, 37), (16, 8.0, "maxwell", 16, "fx16", False, 9),
          (24, 8.0, "hard_sphere", 8, "fp32", False, 13), (32, 8.0, "maxwell", 8, "fx16", True, 5),
-         (12, 5.0, "hard_sphere", 8, "fp32", True, 3)]
+         (12, 5.0, "hard_sphere", 8, "fp32", True, 3), (48, 8.0, "hard_sphere", 8, "fx16", False, 4),
+         (64, 8.0, "maxwell", 8, "fx16", True, 3)]
 
 
 def _setup(qc, seed=0):
@@ -118,3 +119,26 @@ def test_autotune_keeps_results_and_caches(qc, tmp_path):
         assert torch.equal(other.eval(f), before)
     plan.close()
     other.close()
+
+
+def test_more_slots_than_one_table(qc):
+    """Ten plans in one call (the slot table holds eight; the call spreads them
+    over several launches on the same stream) still match the single launches."""
+    specs = [(N, kern) for N in (16, 24, 32, 20, 48) for kern in ("maxwell", "hard_sphere")]
+    plans = [qc.Plan(2, N, 8.0, kern, 8, precision="fx16") for N, kern in specs]
+    fs = [torch.tensor(wl.mixture_cells(2, N, 8.0, 3 + i, 300 + i), dtype=torch.float32, device="cuda")
+          for i, (N, _) in enumerate(specs)]
+    singles = [p.eval(f) for p, f in zip(plans, fs)]
+    outs = [torch.full_like(s, float("nan")) for s in singles]
+    qc.eval_multi(plans, fs, outs)
+    ref = [f.clone() for f in fs]
+    for p, f in zip(plans, ref):
+        p.step(f, 0.01, 1.0, "explicit")
+    qc.step_multi(plans, fs, 0.01, 1.0, "explicit")
+    torch.cuda.synchronize()
+    for a, b in zip(singles, outs):
+        assert torch.equal(a, b)
+    for a, b in zip(ref, fs):
+        assert torch.equal(a, b)
+    for p in plans:
+        p.close()

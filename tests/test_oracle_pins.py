@@ -353,3 +353,77 @@ def test_p12_imex_euler():
     a = stepping.imex_euler_penalized(f, q, 1e-9, 1.0, d, L)
     e = stepping.explicit_euler(f, q, 1e-9, 1.0)
     assert np.abs(a - e).max() < 1e-15 * np.abs(f).max() + 1e-20
+
+
+# ------------------------------------------------ P13: multi-stage IMEX RK
+
+@pytest.mark.parametrize("scheme", ["ars222", "bpr343"])
+def test_p13_tableau_order_conditions(scheme):
+    """The tableaux of section 3.4 satisfy the IMEX order conditions of their
+    order (2 for ARS(2,2,2), 3 for BPR(3,4,3), with the coupling conditions),
+    share the abscissae c = At 1 = A 1, and are stiffly accurate."""
+    at, a, wt, w = stepping.TABLEAUX[scheme]
+    c = at.sum(axis=1)
+    assert np.allclose(c, a.sum(axis=1), atol=1e-15)
+    assert np.allclose(wt, at[-1]) and np.allclose(w, a[-1])
+    for b in (wt, w):
+        assert abs(b.sum() - 1) < 1e-14 and abs(b @ c - 0.5) < 1e-14
+    if scheme == "bpr343":
+        for b, A1 in ((wt, at), (wt, a), (w, at), (w, a)):
+            assert abs(b @ (A1 @ c) - 1 / 6) < 1e-14
+        for b in (wt, w):
+            assert abs(b @ c ** 2 - 1 / 3) < 1e-14
+    assert (np.diag(at) == 0).all() and np.allclose(np.triu(a, 1), 0) and np.allclose(np.triu(at), 0)
+
+
+@pytest.mark.parametrize("scheme,order", [("ars222", 2), ("bpr343", 3)])
+def test_p13_convergence_order_on_split_linear_problem(scheme, order):
+    """y' = (kappa - nu)(m - y) [explicit part] + nu (m - y) [implicit part]:
+    exact y(t) = m + (y0 - m) exp(-kappa t); the observed order matches."""
+    y0, m = np.array([2.0, -1.0, 0.3]), np.array([0.5, 0.1, -0.2])
+    nu, kappa = 3.0, 5.0
+    errs = []
+    for n in (32, 64, 128):
+        y = y0.copy()
+        for _ in range(n):
+            y = stepping.imex_rk_core(y, lambda F: kappa * (m - F), 1.0 / n, m, nu, scheme)
+        errs.append(np.abs(y - (m + (y0 - m) * math.exp(-kappa))).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert (rates > order - 0.3).all(), rates
+
+
+@pytest.mark.parametrize("scheme", ["ars222", "bpr343"])
+@pytest.mark.parametrize("kappa", [1.0, 0.8])
+def test_p13_asymptotic_preservation(scheme, kappa):
+    """eps -> 0 with well-prepared data f = M + eps g: one step stays within
+    O(eps) of the Maxwellian for a relaxation operator Q = kappa nu (M - f)
+    (kappa = 1 is the penalisation itself, so the explicit part vanishes);
+    ARS(2,2,2) (first implicit column zero) also projects arbitrary data onto M
+    when Q is the penalisation."""
+    f = wl.mixture_cells(2, 16, 8.0, 3, 17)
+    M0 = stepping.maxwellian_of(f, 2, 8.0)
+    eps = 1e-6
+    fw = M0 + eps * (f - M0)
+    M = stepping.maxwellian_of(fw, 2, 8.0)
+    nu = stepping.density(fw, 2, 8.0).reshape(-1, 1, 1)
+    out = stepping.imex_rk_penalized(fw, lambda F: kappa * nu * (M - F), 0.1, eps, 2, 8.0, scheme)
+    assert np.abs(out - M).max() <= 1e-6 * np.abs(M).max()
+    if scheme == "ars222" and kappa == 1.0:
+        nu0 = stepping.density(f, 2, 8.0).reshape(-1, 1, 1)
+        out = stepping.imex_rk_penalized(f, lambda F: nu0 * (M0 - F), 0.1, 1e-8, 2, 8.0, scheme)
+        assert np.abs(out - M0).max() <= 1e-4 * np.abs(M0).max()
+
+
+def test_p13_maxwellian_moments_and_equilibrium():
+    """maxwellian_of reproduces the discrete moments of a resolved Maxwellian,
+    and a Maxwellian is a fixed point of the step with the true operator up to
+    the spectral equilibrium floor."""
+    rho, u, T = np.array([1.3]), np.array([[0.2, -0.1]]), np.array([0.9])
+    f = wl.maxwellian(2, 32, 8.0, rho, u, T)
+    r2, u2, T2 = stepping.discrete_moments(f, 2, 8.0)
+    assert abs(r2[0] - 1.3) < 1e-12 and np.abs(u2 - u).max() < 1e-12 and abs(T2[0] - 0.9) < 1e-12
+    assert np.abs(stepping.maxwellian_of(f, 2, 8.0) - f).max() < 1e-12
+    s = sp.Setup(d=2, N=32, L=8.0, kernel="maxwell", M=8)
+    bank = sp.filter_bank(s)
+    out = stepping.imex_rk_penalized(f, lambda F: sp.q_fast(F, s, bank), 0.05, 1.0, 2, 8.0, "bpr343")
+    assert np.abs(out - f).max() < 1e-6 * f.max()
