@@ -54,8 +54,15 @@ enum { QCOLL_MAXWELL = 0, QCOLL_HARD_SPHERE = 1 };
  *                  filters and all elementwise work in FP64. */
 enum { QCOLL_FP32 = 1, QCOLL_MIX_FX16 = 4 };
 
-/* Stage update of qcoll_step (section 3.4, homogeneous case). */
-enum { QCOLL_EXPLICIT_EULER = 0, QCOLL_IMEX_EULER_PENALIZED = 1 };
+/* Time schemes (section 3.4, homogeneous case): the single-stage updates of
+ * qcoll_step and the multi-stage penalised IMEX Runge-Kutta steps of
+ * qcoll_step_rk (tableaux ARS(2,2,2) and BPR(3,4,3) of section 3.4). */
+enum {
+  QCOLL_EXPLICIT_EULER = 0,
+  QCOLL_IMEX_EULER_PENALIZED = 1,
+  QCOLL_IMEX_ARS222 = 2,
+  QCOLL_IMEX_BPR343 = 3
+};
 
 enum {
   QCOLL_OK = 0,
@@ -108,6 +115,25 @@ int qcoll_eval(qcoll_plan_t plan, const float* f, void* Q, int64_t cells, hipStr
  * dt > 0 and eps > 0 are required. */
 int qcoll_step(qcoll_plan_t plan, float* f, int64_t cells, double dt, double eps, int scheme,
                int32_t* status, hipStream_t stream);
+
+/* One multi-stage penalised IMEX Runge-Kutta step of d f/dt = Q(f)/eps in
+ * place (eqs. (GIMEXb), (GIMEX1b) without transport, section 3.4). The
+ * Boltzmann operator is split as Q = G_P + Q_BGK with Q_BGK(F) = nu (M - F)
+ * implicit and G_P = Q - Q_BGK explicit; since the moments are conserved, every
+ * stage uses the Maxwellian M of the discrete moments of f^n (FP64) and
+ * nu = rho(f^n). Stage l (l = 2..S; stage 1 is f^n):
+ *   F_l = [f^n + (dt/eps) sum_{m<l} (At_lm G_m + A_lm S_m) + A_ll (dt/eps) nu M]
+ *         / (1 + A_ll dt nu / eps),   S_m = nu (M - F_m), G_m = Q(F_m) - S_m,
+ * and f^{n+1} = F_S (both tableaux are stiffly accurate). Each stage l is one
+ * launch that evaluates Q(F_{l-1}) and forms F_l. scheme: QCOLL_IMEX_ARS222
+ * (S = 3, two launches) or QCOLL_IMEX_BPR343 (S = 5, four launches). work:
+ * device float buffer owned by the caller, at least qcoll_step_rk_work_bytes()
+ * bytes, holding the stage values and Q of earlier stages (FP32); its content
+ * is scratch. status as in qcoll_step (set by the last stage). 2D plans with
+ * N <= 32 only (otherwise QCOLL_EUNSUPPORTED). */
+int64_t qcoll_step_rk_work_bytes(qcoll_plan_t plan, int scheme, int64_t cells);
+int qcoll_step_rk(qcoll_plan_t plan, float* f, int64_t cells, double dt, double eps, int scheme, float* work,
+                  int64_t work_bytes, int32_t* status, hipStream_t stream);
 
 /* Batched launches (cell-locality of section 3.3: cells of different velocity
  * grids and kernels share one launch). Slot i uses plans[i] with f[i], Q[i]

@@ -561,6 +561,44 @@ int qcoll_step(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps, i
   return launch(a, stream) ? QCOLL_EDEVICE : QCOLL_OK;
 }
 
+namespace {
+int rk_stages(int scheme) { return scheme == QCOLL_IMEX_ARS222 ? 3 : (scheme == QCOLL_IMEX_BPR343 ? 5 : 0); }
+}  // namespace
+
+int64_t qcoll_step_rk_work_bytes(qcoll_plan_t p, int scheme, int64_t cells) {
+  const int S = rk_stages(scheme);
+  if (!p || S == 0 || cells < 0) return -1;
+  const int64_t n = static_cast<int64_t>(p->hp.N) * p->hp.N;
+  return static_cast<int64_t>(2 * S - 3) * cells * n * static_cast<int64_t>(sizeof(float));
+}
+
+int qcoll_step_rk(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps, int scheme, float* work,
+                  int64_t work_bytes, int32_t* status, hipStream_t stream) {
+  if (!p || cells < 0) return QCOLL_EINVAL;
+  if (!(dt > 0.0) || !(eps > 0.0) || !std::isfinite(dt) || !std::isfinite(eps)) return QCOLL_EINVAL;
+  const int S = rk_stages(scheme);
+  if (S == 0) return QCOLL_EINVAL;
+  if (!p->on_device || p->hp.d != 2 || p->tile == 64) return QCOLL_EUNSUPPORTED;
+  if (cells == 0) return QCOLL_OK;
+  if (!f || !work || work_bytes < qcoll_step_rk_work_bytes(p, scheme, cells)) return QCOLL_EINVAL;
+  const int64_t stride = cells * static_cast<int64_t>(p->hp.N) * p->hp.N;
+  for (int l = 2; l <= S; ++l) {
+    qcoll::KernelArgs a = make_args(p);
+    a.f = l == 2 ? f : work + static_cast<int64_t>(l - 3) * stride;  // stage input F_{l-1}
+    a.cells = cells;
+    a.dt_eps = dt / eps;
+    a.out_kind = 3;
+    a.rk_fn = f;
+    a.rk_work = work;
+    a.rk_stride = stride;
+    a.rk_scheme = scheme == QCOLL_IMEX_ARS222 ? 1 : 2;
+    a.rk_stage = l;
+    a.status = status;
+    if (launch(a, stream)) return QCOLL_EDEVICE;
+  }
+  return QCOLL_OK;
+}
+
 // Shared by qcoll_eval_multi and qcoll_step_multi: validate the slot list and
 // build the batched launch (one workgroup per waves_per_block cells of a slot).
 static int multi_launch(const qcoll_plan_t* plans, int nplans, const float* const* f, void* const* Q,

@@ -26,7 +26,18 @@ struct KernelArgs {
   double dt_eps = 0;            // dt / eps
   int scheme = 0;
   int32_t* status = nullptr;
-  int out_kind = 0;             // 0 eval (float Q), 1 eval with projection (double Q), 2 step
+  int out_kind = 0;             // 0 eval (float Q), 1 eval with projection (double Q), 2 step,
+                                // 3 stage of a multi-stage IMEX step
+  // out_kind 3: stage rk_stage (2..S) of scheme rk_scheme (1 ARS(2,2,2), 2
+  // BPR(3,4,3)); f holds the stage input F_{l-1}, rk_fn the step's start value
+  // f^n (overwritten with the result by the last stage), rk_work the stage
+  // slots (F_m, m = 2..S-1, at slot m-2; Q(F_m), m = 1..S-1, at slot S-3+m),
+  // rk_stride floats apart.
+  float* rk_fn = nullptr;
+  float* rk_work = nullptr;
+  int64_t rk_stride = 0;
+  int rk_scheme = 0;
+  int rk_stage = 0;
   int tile = 32;                // MFMA tile of the kernel: 16 or 32
   int precision = 4;            // 1 FP32, 4 FX16
   int waves_per_block = 4;      // launch shape (1, 2 or 4 wavefronts, one cell each)
@@ -58,7 +69,18 @@ struct Slot3 {
   double dt_eps = 0;
   int scheme = 0;
   int32_t* status = nullptr;
-  int out_kind = 0;             // 0 eval (float Q), 1 eval with projection (double Q), 2 step
+  int out_kind = 0;             // 0 eval (float Q), 1 eval with projection (double Q), 2 step,
+                                // 3 stage of a multi-stage IMEX step
+  // out_kind 3: stage rk_stage (2..S) of scheme rk_scheme (1 ARS(2,2,2), 2
+  // BPR(3,4,3)); f holds the stage input F_{l-1}, rk_fn the step's start value
+  // f^n (overwritten with the result by the last stage), rk_work the stage
+  // slots (F_m, m = 2..S-1, at slot m-2; Q(F_m), m = 1..S-1, at slot S-3+m),
+  // rk_stride floats apart.
+  float* rk_fn = nullptr;
+  float* rk_work = nullptr;
+  int64_t rk_stride = 0;
+  int rk_scheme = 0;
+  int rk_stage = 0;
 };
 struct Args3 {
   int nslots = 0;

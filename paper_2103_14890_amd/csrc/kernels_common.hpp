@@ -65,6 +65,21 @@ struct Lay16 {  // 16x16 MFMA result tile
 
 // ------------------------------------------------------------- epilogue
 
+// Butcher tableaux of the multi-stage IMEX steps (section 3.4): explicit At
+// and implicit A, rows = stages. [0] ARS(2,2,2) with gamma = 1 - 1/sqrt 2 and
+// delta = 1 - 1/(2 gamma); [1] BPR(3,4,3). Both are stiffly accurate, so the
+// step's result is the last stage.
+constexpr double kRsqrt2 = 0.70710678118654752440084436210485;
+constexpr double kGam = 1.0 - kRsqrt2;
+constexpr double kDel = 1.0 - 1.0 / (2.0 * kGam);
+__constant__ double kRkAt[2][5][5] = {
+    {{0, 0, 0, 0, 0}, {kGam, 0, 0, 0, 0}, {kDel, 1.0 - kDel, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}},
+    {{0, 0, 0, 0, 0}, {1, 0, 0, 0, 0}, {4.0 / 9, 2.0 / 9, 0, 0, 0}, {0.25, 0, 0.75, 0, 0}, {0.25, 0, 0.75, 0, 0}}};
+__constant__ double kRkA[2][5][5] = {
+    {{0, 0, 0, 0, 0}, {0, kGam, 0, 0, 0}, {0, 1.0 - kGam, kGam, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}},
+    {{0, 0, 0, 0, 0}, {0.5, 0.5, 0, 0, 0}, {5.0 / 18, -1.0 / 9, 0.5, 0, 0}, {0.5, 0, 0, 0.5, 0},
+     {0.25, 0, 0.75, -0.5, 0.5}}};
+
 // Store Q, or apply the conservation projection (FP64 moments, wave
 // reductions) and store Q as double, or apply the stage update to f.
 template <int OUT, class LY>
@@ -72,7 +87,8 @@ __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, 
   if constexpr (OUT < 0) {  // epilogue chosen at run time (batched launches)
     if (a.out_kind == 0) finish_cell<0, LY>(a, cell, fv, q, lane);
     else if (a.out_kind == 1) finish_cell<1, LY>(a, cell, fv, q, lane);
-    else finish_cell<2, LY>(a, cell, fv, q, lane);
+    else if (a.out_kind == 2) finish_cell<2, LY>(a, cell, fv, q, lane);
+    else finish_cell<3, LY>(a, cell, fv, q, lane);
     return;
   }
   // The velocities and addresses below are the same for every cell; an opaque
@@ -121,6 +137,76 @@ __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, 
       const double v1 = -a.L + a.dv * r;
       double corr = lam[0] + lam[1] * v1 + lam[2] * v2c + lam[3] * (v1 * v1 + v2c * v2c);
       if (r < n && c < n) Qc[r * n + c] = q[v] - corr;
+    }
+    return;
+  }
+  if (OUT == 3) {
+    // Stage l of the penalised IMEX RK step (eqs. (GIMEXb), (GIMEX1b), space
+    // homogeneous): with M the Maxwellian of the discrete moments of f^n and
+    // nu = rho(f^n), S_m = nu (M - F_m), G_m = Q(F_m) - S_m,
+    //   F_l = [f^n + k sum_{m<l} (At_lm G_m + A_lm S_m) + A_ll k nu M] / (1 + A_ll k nu).
+    // q holds Q(F_{l-1}) of this launch (FP64), fv the input F_{l-1}.
+    const int sch = a.rk_scheme - 1;
+    const int S = sch == 0 ? 3 : 5;
+    const int l = a.rk_stage;
+    const double* At = kRkAt[sch][l - 1];
+    const double* Ai = kRkA[sch][l - 1];
+    float* fnp = a.rk_fn + base;
+    double fn[kV];
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    const double v2c = -a.L + a.dv * c;
+#pragma unroll
+    for (int v = 0; v < kV; ++v) {
+      const int r = LY::row(v, lane);
+      fn[v] = (r < n && c < n) ? static_cast<double>(fnp[r * n + c]) : 0.0;
+      const double v1 = -a.L + a.dv * r;
+      s0 += fn[v];
+      s1 += v1 * fn[v];
+      s2 += v2c * fn[v];
+      s3 += (v1 * v1 + v2c * v2c) * fn[v];
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    s3 = wave_sum(s3);
+    const double rho = s0 * a.dv * a.dv, u1 = s1 / s0, u2 = s2 / s0;
+    const double T = 0.5 * (s3 / s0 - u1 * u1 - u2 * u2);
+    const double nu = rho, k = a.dt_eps;
+    const double cM = rho / (2.0 * 3.14159265358979323846 * T);
+    const double den = 1.0 + Ai[l - 1] * k * nu;
+    int bad = 0;
+#pragma unroll
+    for (int v = 0; v < kV; ++v) {
+      const int r = LY::row(v, lane);
+      if (!(r < n && c < n)) continue;
+      const int o = r * n + c;
+      const double v1 = -a.L + a.dv * r;
+      const double M = cM * exp(-((v1 - u1) * (v1 - u1) + (v2c - u2) * (v2c - u2)) / (2.0 * T));
+      double rhs = fn[v] + Ai[l - 1] * k * nu * M;
+      for (int m = 1; m < l; ++m) {
+        const double Fm = m == 1 ? fn[v]
+                          : (m == l - 1 ? static_cast<double>(fv[v])
+                                        : static_cast<double>(a.rk_work[(m - 2) * a.rk_stride + base + o]));
+        const double Sm = nu * (M - Fm);
+        double acc = Ai[m - 1] * Sm;
+        if (At[m - 1] != 0.0) {
+          const double Qm = m == l - 1 ? q[v] : static_cast<double>(a.rk_work[(S - 3 + m) * a.rk_stride + base + o]);
+          acc += At[m - 1] * (Qm - Sm);
+        }
+        rhs += k * acc;
+      }
+      const float Fl = static_cast<float>(rhs / den);
+      if (l == S) {
+        bad |= !(fabsf(Fl) <= 3.0e38f);
+        fnp[o] = Fl;
+      } else {
+        a.rk_work[(l - 2) * a.rk_stride + base + o] = Fl;
+        a.rk_work[(S - 3 + (l - 1)) * a.rk_stride + base + o] = static_cast<float>(q[v]);
+      }
+    }
+    if (l == S && a.status) {
+      bad = __any(bad) ? 1 : 0;
+      if ((threadIdx.x & 63) == 0) a.status[cell] = bad;
     }
     return;
   }

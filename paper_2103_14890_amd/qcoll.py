@@ -18,13 +18,14 @@ HEADER = os.path.join(os.path.dirname(_PKG), "include", "qcoll.h")
 
 MAXWELL, HARD_SPHERE = 0, 1
 FP32, MIX_FX16 = 1, 4
-EXPLICIT_EULER, IMEX_EULER_PENALIZED = 0, 1
+EXPLICIT_EULER, IMEX_EULER_PENALIZED, IMEX_ARS222, IMEX_BPR343 = 0, 1, 2, 3
 CONSERVE, R_LITERAL, HOST_ONLY = 0x1, 0x2, 0x100
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
 
 _KERNELS = {"maxwell": MAXWELL, "hard_sphere": HARD_SPHERE}
 _PRECISIONS = {"fp32": FP32, "fx16": MIX_FX16}
 _SCHEMES = {"explicit": EXPLICIT_EULER, "imex": IMEX_EULER_PENALIZED}
+_RK_SCHEMES = {"ars222": IMEX_ARS222, "bpr343": IMEX_BPR343}
 
 
 class QcollError(RuntimeError):
@@ -54,6 +55,10 @@ def _load() -> ctypes.CDLL:
     lib.qcoll_eval.restype = c_int
     lib.qcoll_step.argtypes = [vp, vp, i64, dbl, dbl, c_int, vp, vp]
     lib.qcoll_step.restype = c_int
+    lib.qcoll_step_rk_work_bytes.argtypes = [vp, c_int, i64]
+    lib.qcoll_step_rk_work_bytes.restype = i64
+    lib.qcoll_step_rk.argtypes = [vp, vp, i64, dbl, dbl, c_int, vp, i64, vp, vp]
+    lib.qcoll_step_rk.restype = c_int
     lib.qcoll_plan_info.argtypes = [vp, ctypes.POINTER(c_int), ctypes.POINTER(c_int), ctypes.POINTER(dbl),
                                     ctypes.POINTER(i64)]
     lib.qcoll_plan_info.restype = c_int
@@ -126,6 +131,22 @@ class Plan:
         self._h = h
         self.d, self.N, self.L, self.kernel, self.M = d, N, float(L), kernel, M
         self.precision, self.conserve = precision, conserve
+
+    def step_rk(self, f, dt: float, eps: float = 1.0, scheme: str = "ars222", status=None, work=None,
+                stream=None):
+        """One multi-stage penalised IMEX step of f in place (qcoll_step_rk);
+        work is a float32 device tensor of at least work_bytes() bytes (allocated
+        here when not given)."""
+        import torch
+        code = _RK_SCHEMES[scheme]
+        need = int(LIB.qcoll_step_rk_work_bytes(self._h, code, f.shape[0]))
+        if work is None:
+            work = torch.empty(max(need // 4, 1), dtype=torch.float32, device=f.device)
+        st = ctypes.c_void_p(0) if status is None else _dev_ptr(status, torch.int32, "status")
+        _check(LIB.qcoll_step_rk(self._h, _dev_ptr(f, torch.float32, "f"), f.shape[0], float(dt), float(eps), code,
+                                 _dev_ptr(work, torch.float32, "work"), work.numel() * 4, st,
+                                 _stream_ptr(stream)), "qcoll_step_rk")
+        return f
 
     @property
     def n(self) -> int:

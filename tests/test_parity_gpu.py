@@ -299,3 +299,43 @@ def test_tile64_noisy_conserve_and_step(qc):
     assert np.abs(ft.cpu().double().numpy() - want).max() <= 2e-6 * np.abs(want).max()
     assert (st.cpu().numpy() == 0).all()
     plan.close()
+
+
+@pytest.mark.parametrize("scheme", ["ars222", "bpr343"])
+@pytest.mark.parametrize("N,precision", [(32, "fx16"), (16, "fx16"), (24, "fp32")])
+def test_step_rk_matches_oracle(qc, scheme, N, precision):
+    """Multi-stage penalised IMEX step (one launch per stage) against the oracle's
+    stage recursion with the FP64 operator; three steps in a row."""
+    cells, L, dt, eps = 7, 8.0, 0.05, 0.5
+    f0 = wl.mixture_cells(2, N, L, cells, 31 + N)
+    plan = qc.Plan(2, N, L, "hard_sphere", 8, precision=precision)
+    f = torch.tensor(f0, dtype=torch.float32, device="cuda")
+    status = torch.full((cells,), -1, dtype=torch.int32, device="cuda")
+    s = sp.Setup(d=2, N=N, L=L, kernel="hard_sphere", M=8)
+    bank = sp.filter_bank(s)
+    want = f0.astype(np.float32).astype(np.float64)
+    for _ in range(3):
+        plan.step_rk(f, dt, eps, scheme, status)
+        want = stepping.imex_rk_penalized(want, lambda F: sp.q_fast(F, s, bank), dt, eps, 2, L, scheme)
+    torch.cuda.synchronize()
+    got = f.cpu().double().numpy()
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print(f"step_rk {scheme} N={N} {precision}: max rel {err:.3e}")
+    assert err <= (3e-6 if precision == "fx16" else 3e-5)
+    assert (status.cpu().numpy() == 0).all()
+    plan.close()
+
+
+def test_step_rk_argument_checks(qc):
+    plan = qc.Plan(2, 32, 8.0, "maxwell", 8, precision="fx16")
+    f = torch.tensor(wl.mixture_cells(2, 32, 8.0, 4, 1), dtype=torch.float32, device="cuda")
+    need = qc.LIB.qcoll_step_rk_work_bytes(plan._h, qc.IMEX_BPR343, 4)
+    assert need == 7 * 4 * 32 * 32 * 4
+    small = torch.empty(need // 4 - 1, dtype=torch.float32, device="cuda")
+    with pytest.raises(qc.QcollError):
+        plan.step_rk(f, 0.01, 1.0, "bpr343", work=small)
+    p64 = qc.Plan(2, 48, 8.0, "maxwell", 8, precision="fx16")
+    with pytest.raises(qc.QcollError):
+        p64.step_rk(torch.zeros((2, 48, 48), dtype=torch.float32, device="cuda"), 0.01, 1.0, "ars222")
+    plan.close()
+    p64.close()
