@@ -48,13 +48,13 @@ def mfma_flops_per_cell(precision: str, transforms: int, N: int = 32) -> float:
 
     A complex 32-point DFT pass over a 32 x 32 tile is a real GEMM with
     M = 32, K = 64, N = 64 (2 * 32 * 64 * 64 flops); the real-input first
-    forward pass has K = 32; the loss transform's second pass needs only the
+    forward pass has K = 32; the loss transform's second pass computes only the
     real half. FX16 issues 6 FP16 products per GEMM, FP32 one.
     """
     full = 2 * 32 * 64 * 64
     per_cell = full / 2 + full            # forward: real-input pass + complex pass
     per_cell += (transforms - 1) * 2 * full  # packed gain transforms, two passes each
-    per_cell += 2 * full                  # loss transform (both passes computed)
+    per_cell += full + full / 2           # loss transform (second pass: real part only)
     if N > 32:                            # tile-64: four 32-point sub-transforms per cell
         per_cell *= 4
     return per_cell * (6 if precision == "fx16" else 1)
@@ -66,6 +66,43 @@ def mfma_flops_per_cell_3d(T: int, transforms: int) -> float:
     per_mfma = 2 * (32 * 32 * 2 if T == 32 else 16 * 16 * 4)
     per_pass = T * (T * T // 64) * 4 * per_mfma
     return (2.5 + 3 * transforms) * per_pass
+
+
+def kernel_source_hash() -> str:
+    """SHA-256 over the device sources (csrc/*.hip, *.hpp): identifies the kernel
+    build that a stored hardware-counter profile belongs to."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2103_14890_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".hpp")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the dominant kernel from the committed PMC summary
+    profiles/traffic_<workload>.md (FETCH_SIZE + WRITE_SIZE, scaled by a copy
+    kernel of known size), or None when there is none or the kernel sources have
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip().strip("`").lstrip("- ")
+            if ":" in line:
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def time_launches(fn, steps: int, warmup: int, stream):
@@ -148,7 +185,7 @@ def bench_3d(args) -> int:
     sa, sb = sp.Setup(d=3, N=Na, L=L, kernel=kern, M=M), sp.Setup(d=3, N=Nb, L=L, kernel=kern, M=M)
     ba, bb = sp.filter_bank(sa), sp.filter_bank(sb)
     done, t_cpu, errs = 0, 0.0, []
-    while t_cpu < args.cpu_seconds and done < 64:
+    while t_cpu < args.cpu_seconds and done < 512:
         i = done
         t0 = time.perf_counter()
         ra = sp.project_conservative(sp.q_fast(fa64[i:i + 1].astype(np.float32).astype(np.float64), sa, ba), 3, L)
@@ -176,7 +213,8 @@ def bench_3d(args) -> int:
         "config": {"workload": f"{args.workload}: {desc}", "cells": cells, "N_v": [f"{Na}^3", f"{Nb}^3"],
                    "kernel": kern, "M": M},
         "roofline": {"bound": "mfma", "achieved": flops / T_ / 1e12, "peak": FP32_MFMA_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": flops / T_ / FP32_MFMA_PEAK, "traffic": None},
+                     "unit": "TFLOP/s", "frac": flops / T_ / FP32_MFMA_PEAK,
+                     "traffic": measured_traffic(args.workload)},
         "cpu_baseline": {"value": 2 * done / t_cpu, "unit": "cell-evals/s", "cores": 1, "kind": "oracle",
                          "sample": f"first {done} cells of each resolution, FP64 numpy FFT oracle + projection, "
                                    f"{t_cpu:.1f} s"},
@@ -279,7 +317,8 @@ def main() -> int:
                    "cells": cells, "N_v": f"{NN}x{NN}", "kernel": KERN, "M": MM,
                    "K_r": mix["info"]["K_r"]},
         "roofline": {"bound": "mfma", "achieved": flops / T / 1e12, "peak": FP16_MFMA_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": flops / T / FP16_MFMA_PEAK, "traffic": None},
+                     "unit": "TFLOP/s", "frac": flops / T / FP16_MFMA_PEAK,
+                     "traffic": measured_traffic(args.workload)},
         "cpu_baseline": {"value": ncpu / t_cpu, "unit": "cell-evals/s", "cores": threads, "kind": "oracle",
                          "sample": f"first {ncpu} cells of the same workload, FP64 numpy FFT oracle "
                                    f"+ projection, {t_cpu:.1f} s"},

@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
       int sd = -b - 9;
       const int a2 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
       slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a2), A);
-      pass64(A, E, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
+      pass64(A, E, kEr, kNEi, kEi, kEr, q < a.P, r0, r1, i0, i1);  // loss field: real part only
       sd = sd - a2 - 9;
       sd_last = sd;
       const double wq = q < a.P ? ldexp(1.0, 2 * sd) : 0.0;
