@@ -178,6 +178,21 @@ def bench_3d(args) -> int:
                               stream)
     T_ = float(np.mean(per))
     cells = fa.shape[0] + fb.shape[0]
+
+    # one IMEX Euler stage (Q plus the update) over both resolutions, captured in
+    # a graph and replayed (on copies of the inputs)
+    ga, gb = fa.clone(), fb.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        qcoll.step_multi([pa, pb], [ga, gb], 0.01, 1.0, "imex")
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        qcoll.step_multi([pa, pb], [ga, gb], 0.01, 1.0, "imex")
+    _, per_stage = time_launches(graph.replay, max(2, args.steps // 2), 1, stream)
+    del ga, gb
     tr = pa.info()["transforms"]
     flops = (mfma_flops_per_cell_3d(32, tr) * fa.shape[0] + mfma_flops_per_cell_3d(16, tr) * fb.shape[0])
 
@@ -222,6 +237,7 @@ def bench_3d(args) -> int:
         "mass_defect_max": mass,
         "launch_ms": {"p5": float(np.percentile(per, 5) * 1e3), "p50": float(np.median(per) * 1e3),
                       "p95": float(np.percentile(per, 95) * 1e3)},
+        "imex_stage_graph_ms": float(np.median(per_stage) * 1e3),
         "p99_latency_ms": None,
     }
     print(json.dumps(out))

@@ -121,6 +121,29 @@ __device__ __forceinline__ void block_sum(double* x, double* red) {
   const int x = lane % T, jl = lane / T; \
   (void)jl
 
+// All tiles t = w, w+4, ... of one axis pass for this wavefront, with the next
+// tile's inputs loaded while the current tile's MFMAs run. load(t, xr, xi)
+// fetches a tile's inputs, store(t, dr, di) disposes of its outputs; tiles of
+// one wavefront touch disjoint lines, so prefetching ahead of the stores is safe.
+template <int T, bool DB, bool INV, bool REAL_IN, class Load, class Store>
+__device__ __forceinline__ void pass_tiles(const Emat<T>& E, int w, Load load, Store store) {
+  using S = Sh<T>;
+  float ar[S::NS], ai[S::NS], br[S::NS], bi[S::NS];
+  load(w, ar, ai);
+#pragma unroll 1
+  for (int t = w; t < T; t += 4) {
+    if (t + 4 < T) load(t + 4, br, bi);
+    typename S::acc dr, di;
+    tile_dft<T, DB, INV, REAL_IN>(E, ar, ai, dr, di);
+    store(t, dr, di);
+#pragma unroll
+    for (int s = 0; s < S::NS; ++s) {
+      ar[s] = br[s];
+      ai[s] = bi[s];
+    }
+  }
+}
+
 template <int T>
 __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red) {
   using S = Sh<T>;
@@ -143,28 +166,28 @@ __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red
       E.ns[s] = src[2 * S::NS + s];
     }
   }
-  typename S::acc dr, di;
-  float xr[S::NS], xi[S::NS];
-
   // ---- forward pass, axis 2 (real input; data as the left operand); tile t = i0
   double fsum = 0.0;
-#pragma unroll 1
-  for (int t = w; t < T; t += 4) {
-    OPAQUE_LANE();
+  pass_tiles<T, false, false, true>(
+      E, w,
+      [&](int t, float* xr, float* xi) {
+        OPAQUE_LANE();
 #pragma unroll
-    for (int s = 0; s < S::NS; ++s) {
-      const int j = S::KS * s + jl;
-      xr[s] = (t < n && x < n && j < n) ? fc[(t * n + x) * n + j] : 0.0f;
-      fsum += static_cast<double>(xr[s]);
-    }
-    tile_dft<T, false, false, true>(E, xr, xi, dr, di);
+        for (int s = 0; s < S::NS; ++s) {
+          const int j = S::KS * s + jl;
+          xr[s] = (t < n && x < n && j < n) ? fc[(t * n + x) * n + j] : 0.0f;
+          xi[s] = 0.0f;
+          fsum += static_cast<double>(xr[s]);
+        }
+      },
+      [&](int t, const typename S::acc& dr, const typename S::acc& di) {
+        OPAQUE_LANE();
 #pragma unroll
-    for (int v = 0; v < S::NR; ++v) work[t * T2 + S::row(v, lane) * T + x] = make_float2(dr[v], di[v]);
-  }
+        for (int v = 0; v < S::NR; ++v) work[t * T2 + S::row(v, lane) * T + x] = make_float2(dr[v], di[v]);
+      });
   __syncthreads();
-  // ---- forward pass, axis 1 (tile t = i0, lanes over i2)
-#pragma unroll 1
-  for (int t = w; t < T; t += 4) {
+  // ---- forward pass, axis 1 (tile t = i0, lanes over i2), in place
+  auto load_axis1 = [&](int t, float* xr, float* xi) {
     OPAQUE_LANE();
 #pragma unroll
     for (int s = 0; s < S::NS; ++s) {
@@ -172,101 +195,101 @@ __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red
       xr[s] = z.x;
       xi[s] = z.y;
     }
-    tile_dft<T, true, false, false>(E, xr, xi, dr, di);
-#pragma unroll
-    for (int v = 0; v < S::NR; ++v) work[t * T2 + S::row(v, lane) * T + x] = make_float2(dr[v], di[v]);
-  }
-  __syncthreads();
-  // ---- forward pass, axis 0 (tile t = i1, lanes over i2) -> spectrum
-#pragma unroll 1
-  for (int t = w; t < T; t += 4) {
+  };
+  auto store_axis1 = [&](int t, const typename S::acc& dr, const typename S::acc& di) {
     OPAQUE_LANE();
 #pragma unroll
-    for (int s = 0; s < S::NS; ++s) {
-      const float2 z = work[(S::KS * s + jl) * T2 + t * T + x];
-      xr[s] = z.x;
-      xi[s] = z.y;
-    }
-    tile_dft<T, true, false, false>(E, xr, xi, dr, di);
+    for (int v = 0; v < S::NR; ++v) work[t * T2 + S::row(v, lane) * T + x] = make_float2(dr[v], di[v]);
+  };
+  pass_tiles<T, true, false, false>(E, w, load_axis1, store_axis1);
+  __syncthreads();
+  // ---- forward pass, axis 0 (tile t = i1, lanes over i2) -> spectrum
+  pass_tiles<T, true, false, false>(
+      E, w,
+      [&](int t, float* xr, float* xi) {
+        OPAQUE_LANE();
 #pragma unroll
-    for (int v = 0; v < S::NR; ++v) fh[S::row(v, lane) * T2 + t * T + x] = make_float2(dr[v], di[v]);
-  }
+        for (int s = 0; s < S::NS; ++s) {
+          const float2 z = work[(S::KS * s + jl) * T2 + t * T + x];
+          xr[s] = z.x;
+          xi[s] = z.y;
+        }
+      },
+      [&](int t, const typename S::acc& dr, const typename S::acc& di) {
+        OPAQUE_LANE();
+#pragma unroll
+        for (int v = 0; v < S::NR; ++v) fh[S::row(v, lane) * T2 + t * T + x] = make_float2(dr[v], di[v]);
+      });
   __syncthreads();
 
   double mom[5] = {0, 0, 0, 0, 0};
   for (int q = 0; q <= a.P; ++q) {
     const float2* mq = reinterpret_cast<const float2*>(a.filt) + static_cast<int64_t>(q) * T3;
     // ---- inverse pass, axis 0: filter times spectrum on load (tile t = k1)
-#pragma unroll 1
-    for (int t = w; t < T; t += 4) {
-      OPAQUE_LANE();
+    pass_tiles<T, true, true, false>(
+        E, w,
+        [&](int t, float* xr, float* xi) {
+          OPAQUE_LANE();
 #pragma unroll
-      for (int s = 0; s < S::NS; ++s) {
-        const int o = (S::KS * s + jl) * T2 + t * T + x;
-        const float2 z = fh[o], m = mq[o];
-        xr[s] = m.x * z.x - m.y * z.y;
-        xi[s] = m.x * z.y + m.y * z.x;
-      }
-      tile_dft<T, true, true, false>(E, xr, xi, dr, di);
+          for (int s = 0; s < S::NS; ++s) {
+            const int o = (S::KS * s + jl) * T2 + t * T + x;
+            const float2 z = fh[o], m = mq[o];
+            xr[s] = m.x * z.x - m.y * z.y;
+            xi[s] = m.x * z.y + m.y * z.x;
+          }
+        },
+        [&](int t, const typename S::acc& dr, const typename S::acc& di) {
+          OPAQUE_LANE();
 #pragma unroll
-      for (int v = 0; v < S::NR; ++v) work[S::row(v, lane) * T2 + t * T + x] = make_float2(dr[v], di[v]);
-    }
+          for (int v = 0; v < S::NR; ++v) work[S::row(v, lane) * T2 + t * T + x] = make_float2(dr[v], di[v]);
+        });
     __syncthreads();
-    // ---- inverse pass, axis 1 (tile t = i0)
-#pragma unroll 1
-    for (int t = w; t < T; t += 4) {
-      OPAQUE_LANE();
-#pragma unroll
-      for (int s = 0; s < S::NS; ++s) {
-        const float2 z = work[t * T2 + (S::KS * s + jl) * T + x];
-        xr[s] = z.x;
-        xi[s] = z.y;
-      }
-      tile_dft<T, true, true, false>(E, xr, xi, dr, di);
-#pragma unroll
-      for (int v = 0; v < S::NR; ++v) work[t * T2 + S::row(v, lane) * T + x] = make_float2(dr[v], di[v]);
-    }
+    // ---- inverse pass, axis 1 (tile t = i0), in place
+    pass_tiles<T, true, true, false>(E, w, load_axis1, store_axis1);
     __syncthreads();
     // ---- inverse pass, axis 2 (data as the left operand; tile t = i0, lines
     // i1 = x on the lanes, output point (t, row, x)) and the gain
-#pragma unroll 1
-    for (int t = w; t < T; t += 4) {
-      OPAQUE_LANE();
+    pass_tiles<T, false, true, false>(
+        E, w,
+        [&](int t, float* xr, float* xi) {
+          OPAQUE_LANE();
 #pragma unroll
-      for (int s = 0; s < S::NS; ++s) {
-        const float2 z = work[t * T2 + x * T + S::KS * s + jl];
-        xr[s] = z.x;
-        xi[s] = z.y;
-      }
-      tile_dft<T, false, true, false>(E, xr, xi, dr, di);
-      if (q < a.P) {
-#pragma unroll
-        for (int v = 0; v < S::NR; ++v) {
-          const int o = t * T2 + S::row(v, lane) * T + x;
-          const double g = static_cast<double>(dr[v]) * static_cast<double>(di[v]);
-          gain[o] = q == 0 ? g : gain[o] + g;
-        }
-      } else {
-        // loss field: Q = gain - f * loss on the grid points, zero elsewhere
-#pragma unroll
-        for (int v = 0; v < S::NR; ++v) {
-          const int r = S::row(v, lane);
-          const int o = t * T2 + r * T + x;
-          double Q = 0.0;
-          if (t < n && r < n && x < n) {
-            const double fv = static_cast<double>(fc[(t * n + r) * n + x]);
-            Q = (a.P > 0 ? gain[o] : 0.0) - fv * static_cast<double>(dr[v]);
-            const double v0 = -a.L + a.dv * t, v1 = -a.L + a.dv * r, v2 = -a.L + a.dv * x;
-            mom[0] += Q;
-            mom[1] += v0 * Q;
-            mom[2] += v1 * Q;
-            mom[3] += v2 * Q;
-            mom[4] += (v0 * v0 + v1 * v1 + v2 * v2) * Q;
+          for (int s = 0; s < S::NS; ++s) {
+            const float2 z = work[t * T2 + x * T + S::KS * s + jl];
+            xr[s] = z.x;
+            xi[s] = z.y;
           }
-          gain[o] = Q;
-        }
-      }
-    }
+        },
+        [&](int t, const typename S::acc& dr, const typename S::acc& di) {
+          OPAQUE_LANE();
+          if (q < a.P) {
+#pragma unroll
+            for (int v = 0; v < S::NR; ++v) {
+              const int o = t * T2 + S::row(v, lane) * T + x;
+              const double g = static_cast<double>(dr[v]) * static_cast<double>(di[v]);
+              gain[o] = q == 0 ? g : gain[o] + g;
+            }
+          } else {
+            // loss field: Q = gain - f * loss on the grid points, zero elsewhere
+#pragma unroll
+            for (int v = 0; v < S::NR; ++v) {
+              const int r = S::row(v, lane);
+              const int o = t * T2 + r * T + x;
+              double Q = 0.0;
+              if (t < n && r < n && x < n) {
+                const double fv = static_cast<double>(fc[(t * n + r) * n + x]);
+                Q = (a.P > 0 ? gain[o] : 0.0) - fv * static_cast<double>(dr[v]);
+                const double v0 = -a.L + a.dv * t, v1 = -a.L + a.dv * r, v2 = -a.L + a.dv * x;
+                mom[0] += Q;
+                mom[1] += v0 * Q;
+                mom[2] += v1 * Q;
+                mom[3] += v2 * Q;
+                mom[4] += (v0 * v0 + v1 * v1 + v2 * v2) * Q;
+              }
+              gain[o] = Q;
+            }
+          }
+        });
     __syncthreads();
   }
 

@@ -164,3 +164,33 @@ def test_3d_workload_sampled_cells(qc):
     mass = np.abs(qa.sum(axis=(1, 2, 3))) / np.abs(qa).sum(axis=(1, 2, 3))
     assert mass.max() <= 1e-12
     plan.close()
+
+
+def test_3d_stage_graph_replay(qc):
+    """One hipGraph-captured launch per stage over both resolutions (32^3 and
+    16^3): every replay advances the state exactly like the eager batched step."""
+    a0 = torch.tensor(wl.mixture_cells(3, 32, 8.0, 2, 61), dtype=torch.float32, device="cuda")
+    b0 = torch.tensor(wl.mixture_cells(3, 16, 8.0, 5, 62), dtype=torch.float32, device="cuda")
+    p32 = qc.Plan(3, 32, 8.0, "hard_sphere", 8, precision="fp32")
+    p16 = qc.Plan(3, 16, 8.0, "hard_sphere", 8, precision="fp32")
+    ea, eb = a0.clone(), b0.clone()          # eager reference trajectory
+    ga, gb = a0.clone(), b0.clone()          # graph-owned state
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):               # warm-up on the side stream
+        wa, wb = a0.clone(), b0.clone()
+        qc.step_multi([p32, p16], [wa, wb], 0.01, 1.0, "imex")
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        qc.step_multi([p32, p16], [ga, gb], 0.01, 1.0, "imex")
+    ga.copy_(a0)
+    gb.copy_(b0)
+    for _ in range(3):
+        g.replay()
+        qc.step_multi([p32, p16], [ea, eb], 0.01, 1.0, "imex")
+        torch.cuda.synchronize()
+        assert torch.equal(ga, ea) and torch.equal(gb, eb)
+    p32.close()
+    p16.close()
