@@ -568,7 +568,7 @@ int rk_stages(int scheme) { return scheme == QCOLL_IMEX_ARS222 ? 3 : (scheme == 
 int64_t qcoll_step_rk_work_bytes(qcoll_plan_t p, int scheme, int64_t cells) {
   const int S = rk_stages(scheme);
   if (!p || S == 0 || cells < 0) return -1;
-  const int64_t n = static_cast<int64_t>(p->hp.N) * p->hp.N;
+  const int64_t n = static_cast<int64_t>(p->hp.N) * p->hp.N * (p->hp.d == 3 ? p->hp.N : 1);
   return static_cast<int64_t>(2 * S - 3) * cells * n * static_cast<int64_t>(sizeof(float));
 }
 
@@ -578,10 +578,27 @@ int qcoll_step_rk(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps
   if (!(dt > 0.0) || !(eps > 0.0) || !std::isfinite(dt) || !std::isfinite(eps)) return QCOLL_EINVAL;
   const int S = rk_stages(scheme);
   if (S == 0) return QCOLL_EINVAL;
-  if (!p->on_device || p->hp.d != 2 || p->tile == 64) return QCOLL_EUNSUPPORTED;
+  if (!p->on_device || p->tile == 64) return QCOLL_EUNSUPPORTED;
   if (cells == 0) return QCOLL_OK;
   if (!f || !work || work_bytes < qcoll_step_rk_work_bytes(p, scheme, cells)) return QCOLL_EINVAL;
-  const int64_t stride = cells * static_cast<int64_t>(p->hp.N) * p->hp.N;
+  const int64_t stride = cells * static_cast<int64_t>(p->hp.N) * p->hp.N * (p->hp.d == 3 ? p->hp.N : 1);
+  if (p->hp.d == 3) {
+    for (int l = 2; l <= S; ++l) {
+      qcoll::Slot3 s3 = make_slot3(p);
+      s3.f = l == 2 ? f : work + static_cast<int64_t>(l - 3) * stride;  // stage input F_{l-1}
+      s3.dt_eps = dt / eps;
+      s3.out_kind = 3;
+      s3.rk_fn = f;
+      s3.rk_work = work;
+      s3.rk_stride = stride;
+      s3.rk_scheme = scheme == QCOLL_IMEX_ARS222 ? 1 : 2;
+      s3.rk_stage = l;
+      s3.status = status;
+      const qcoll_plan_s* pl = p;
+      if (launch3(&pl, &s3, 1, &cells, stream)) return QCOLL_EDEVICE;
+    }
+    return QCOLL_OK;
+  }
   for (int l = 2; l <= S; ++l) {
     qcoll::KernelArgs a = make_args(p);
     a.f = l == 2 ? f : work + static_cast<int64_t>(l - 3) * stride;  // stage input F_{l-1}

@@ -324,6 +324,78 @@ __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red
           Qc[(t * n + r) * n + x] = gain[t * T2 + r * T + x] - corr;
         }
       }
+  } else if (a.out_kind == 3) {
+    // stage l of the penalised IMEX RK step (as finish_cell<3> of the 2D
+    // kernels): M from the discrete moments of f^n, nu = rho(f^n); gain holds
+    // Q(F_{l-1}) in FP64 and fc the input F_{l-1}
+    const int sch = a.rk_scheme - 1;
+    const int S = sch == 0 ? 3 : 5;
+    const int l = a.rk_stage;
+    const double* At = kRkAt[sch][l - 1];
+    const double* Ai = kRkA[sch][l - 1];
+    float* fnp = a.rk_fn + base;
+    double sm[5] = {0, 0, 0, 0, 0};
+    for (int t = w; t < T; t += 4)
+#pragma unroll
+      for (int v = 0; v < S::NR; ++v) {
+        const int r = S::row(v, lane);
+        if (t < n && r < n && x < n) {
+          const double fv = static_cast<double>(fnp[(t * n + r) * n + x]);
+          const double v0 = -a.L + a.dv * t, v1 = -a.L + a.dv * r, v2 = -a.L + a.dv * x;
+          sm[0] += fv;
+          sm[1] += v0 * fv;
+          sm[2] += v1 * fv;
+          sm[3] += v2 * fv;
+          sm[4] += (v0 * v0 + v1 * v1 + v2 * v2) * fv;
+        }
+      }
+    block_sum<5>(sm, red);
+    const double rho = sm[0] * a.dv * a.dv * a.dv;
+    const double u0 = sm[1] / sm[0], u1 = sm[2] / sm[0], u2 = sm[3] / sm[0];
+    const double Tm = (sm[4] / sm[0] - u0 * u0 - u1 * u1 - u2 * u2) / 3.0;
+    const double nu = rho, k = a.dt_eps;
+    const double tp = 2.0 * 3.14159265358979323846 * Tm;
+    const double cM = rho / (tp * sqrt(tp));
+    const double den = 1.0 + Ai[l - 1] * k * nu;
+    int bad = 0;
+    for (int t = w; t < T; t += 4)
+#pragma unroll
+      for (int v = 0; v < S::NR; ++v) {
+        const int r = S::row(v, lane);
+        if (!(t < n && r < n && x < n)) continue;
+        const int o = (t * n + r) * n + x;
+        const double v0 = -a.L + a.dv * t, v1 = -a.L + a.dv * r, v2 = -a.L + a.dv * x;
+        const double c2 = (v0 - u0) * (v0 - u0) + (v1 - u1) * (v1 - u1) + (v2 - u2) * (v2 - u2);
+        const double M = cM * exp(-c2 / (2.0 * Tm));
+        const double fn = static_cast<double>(fnp[o]);
+        double rhs = fn + Ai[l - 1] * k * nu * M;
+        for (int m = 1; m < l; ++m) {
+          const double Fm = m == 1 ? fn
+                            : (m == l - 1 ? static_cast<double>(fc[o])
+                                          : static_cast<double>(a.rk_work[(m - 2) * a.rk_stride + base + o]));
+          const double Sm = nu * (M - Fm);
+          double acc = Ai[m - 1] * Sm;
+          if (At[m - 1] != 0.0) {
+            const double Qm = m == l - 1 ? gain[t * T2 + r * T + x]
+                                         : static_cast<double>(a.rk_work[(S - 3 + m) * a.rk_stride + base + o]);
+            acc += At[m - 1] * (Qm - Sm);
+          }
+          rhs += k * acc;
+        }
+        const float Fl = static_cast<float>(rhs / den);
+        if (l == S) {
+          bad |= !(fabsf(Fl) <= 3.0e38f);
+          fnp[o] = Fl;
+        } else {
+          a.rk_work[(l - 2) * a.rk_stride + base + o] = Fl;
+          a.rk_work[(S - 3 + (l - 1)) * a.rk_stride + base + o] = static_cast<float>(gain[t * T2 + r * T + x]);
+        }
+      }
+    if (l == S && a.status) {
+      double b[1] = {static_cast<double>(__any(bad) ? 1 : 0)};
+      block_sum<1>(b, red);
+      if (threadIdx.x == 0) a.status[cell] = b[0] > 0.0 ? 1 : 0;
+    }
   } else {
     double rs[1] = {fsum};
     block_sum<1>(rs, red);

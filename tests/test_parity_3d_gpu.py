@@ -194,3 +194,26 @@ def test_3d_stage_graph_replay(qc):
         assert torch.equal(ga, ea) and torch.equal(gb, eb)
     p32.close()
     p16.close()
+
+
+@pytest.mark.parametrize("scheme", ["ars222", "bpr343"])
+def test_step_rk_3d(qc, scheme):
+    """Multi-stage penalised IMEX step on a 16^3 grid against the oracle's stage
+    recursion with the FP64 operator."""
+    N, L, cells, dt, eps = 16, 8.0, 3, 0.05, 0.5
+    f0 = wl.mixture_cells(3, N, L, cells, 71)
+    plan = qc.Plan(3, N, L, "hard_sphere", 8, precision="fp32")
+    f = torch.tensor(f0, dtype=torch.float32, device="cuda")
+    status = torch.full((cells,), -1, dtype=torch.int32, device="cuda")
+    plan.step_rk(f, dt, eps, scheme, status)
+    torch.cuda.synchronize()
+    s = sp.Setup(d=3, N=N, L=L, kernel="hard_sphere", M=8)
+    bank = sp.filter_bank(s)
+    want = stepping.imex_rk_penalized(f0.astype(np.float32).astype(np.float64),
+                                      lambda F: sp.q_fast(F, s, bank), dt, eps, 3, L, scheme)
+    got = f.cpu().double().numpy()
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print(f"3D step_rk {scheme}: max rel {err:.3e}")
+    assert err <= 3e-5
+    assert (status.cpu().numpy() == 0).all()
+    plan.close()
