@@ -129,9 +129,8 @@ int qcoll_step(qcoll_plan_t plan, float* f, int64_t cells, double dt, double eps
  * (S = 3, two launches) or QCOLL_IMEX_BPR343 (S = 5, four launches). work:
  * device float buffer owned by the caller, at least qcoll_step_rk_work_bytes()
  * bytes, holding the stage values and Q of earlier stages (FP32); its content
- * is scratch. status as in qcoll_step (set by the last stage). 2D plans with
- * N <= 32 and 3D plans (2D plans with N > 32: QCOLL_EUNSUPPORTED). 3D plans
- * hold a scratch area: see qcoll_eval_multi. */
+ * is scratch. status as in qcoll_step (set by the last stage). Every device
+ * plan (2D and 3D); 3D plans hold a scratch area (see qcoll_eval_multi). */
 int64_t qcoll_step_rk_work_bytes(qcoll_plan_t plan, int scheme, int64_t cells);
 int qcoll_step_rk(qcoll_plan_t plan, float* f, int64_t cells, double dt, double eps, int scheme, float* work,
                   int64_t work_bytes, int32_t* status, hipStream_t stream);

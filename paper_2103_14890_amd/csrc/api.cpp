@@ -578,7 +578,7 @@ int qcoll_step_rk(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps
   if (!(dt > 0.0) || !(eps > 0.0) || !std::isfinite(dt) || !std::isfinite(eps)) return QCOLL_EINVAL;
   const int S = rk_stages(scheme);
   if (S == 0) return QCOLL_EINVAL;
-  if (!p->on_device || p->tile == 64) return QCOLL_EUNSUPPORTED;
+  if (!p->on_device) return QCOLL_EUNSUPPORTED;
   if (cells == 0) return QCOLL_OK;
   if (!f || !work || work_bytes < qcoll_step_rk_work_bytes(p, scheme, cells)) return QCOLL_EINVAL;
   const int64_t stride = cells * static_cast<int64_t>(p->hp.N) * p->hp.N * (p->hp.d == 3 ? p->hp.N : 1);

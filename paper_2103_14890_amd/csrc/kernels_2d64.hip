@@ -234,6 +234,79 @@ __global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
         const double corr = lam[0] + lam[1] * v1 + lam[2] * v2c + lam[3] * (v1 * v1 + v2c * v2c);
         if (r < np && c < np) Qc[(2 * r + p1) * n + 2 * c + p2] = gain[v] - corr;
       }
+    } else if (OUT == 3) {
+      // stage l of the penalised IMEX RK step (as finish_cell<3> of the 32x32
+      // kernels); fv holds the input F_{l-1}, gain its Q (FP64)
+      const int sch = a.rk_scheme - 1;
+      const int S = sch == 0 ? 3 : 5;
+      const int l = a.rk_stage;
+      const double* At = kRkAt[sch][l - 1];
+      const double* Ai = kRkA[sch][l - 1];
+      const int64_t base = cell * static_cast<int64_t>(n) * n;
+      float* fnp = a.rk_fn + base;
+      double fn[16];
+      double sm[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int r = rrow(v, h);
+        const double v1 = -a.L + a.dv * (2 * r + p1);
+        fn[v] = (r < np && c < np) ? static_cast<double>(fnp[(2 * r + p1) * n + 2 * c + p2]) : 0.0;
+        sm[0] += fn[v];
+        sm[1] += v1 * fn[v];
+        sm[2] += v2c * fn[v];
+        sm[3] += (v1 * v1 + v2c * v2c) * fn[v];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sm[i] = wave_sum(sm[i]);
+      if (lane == 0)
+        for (int i = 0; i < 4; ++i) red[w * 4 + i] = sm[i];
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sm[i] = red[i] + red[4 + i] + red[8 + i] + red[12 + i];
+      __syncthreads();
+      const double rho = sm[0] * a.dv * a.dv, u1 = sm[1] / sm[0], u2 = sm[2] / sm[0];
+      const double Tm = 0.5 * (sm[3] / sm[0] - u1 * u1 - u2 * u2);
+      const double nu = rho, k = a.dt_eps;
+      const double cM = rho / (2.0 * 3.14159265358979323846 * Tm);
+      const double den = 1.0 + Ai[l - 1] * k * nu;
+      int bad = 0;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int r = rrow(v, h);
+        if (!(r < np && c < np)) continue;
+        const int o = (2 * r + p1) * n + 2 * c + p2;
+        const double v1 = -a.L + a.dv * (2 * r + p1);
+        const double M = cM * exp(-((v1 - u1) * (v1 - u1) + (v2c - u2) * (v2c - u2)) / (2.0 * Tm));
+        double rhs = fn[v] + Ai[l - 1] * k * nu * M;
+        for (int m = 1; m < l; ++m) {
+          const double Fm = m == 1 ? fn[v]
+                            : (m == l - 1 ? static_cast<double>(fv[v])
+                                          : static_cast<double>(a.rk_work[(m - 2) * a.rk_stride + base + o]));
+          const double Sm = nu * (M - Fm);
+          double acc = Ai[m - 1] * Sm;
+          if (At[m - 1] != 0.0) {
+            const double Qm =
+                m == l - 1 ? gain[v] : static_cast<double>(a.rk_work[(S - 3 + m) * a.rk_stride + base + o]);
+            acc += At[m - 1] * (Qm - Sm);
+          }
+          rhs += k * acc;
+        }
+        const float Fl = static_cast<float>(rhs / den);
+        if (l == S) {
+          bad |= !(fabsf(Fl) <= 3.0e38f);
+          fnp[o] = Fl;
+        } else {
+          a.rk_work[(l - 2) * a.rk_stride + base + o] = Fl;
+          a.rk_work[(S - 3 + (l - 1)) * a.rk_stride + base + o] = static_cast<float>(gain[v]);
+        }
+      }
+      if (l == S && a.status) {
+        bad = __any(bad) ? 1 : 0;
+        if (lane == 0) red[w * 4 + 1] = bad;
+        __syncthreads();
+        if (threadIdx.x == 0) a.status[cell] = (red[1] + red[5] + red[9] + red[13]) > 0 ? 1 : 0;
+        __syncthreads();
+      }
     } else {
       double rho = 0.0;
 #pragma unroll
@@ -282,12 +355,15 @@ int launch_2d64(const KernelArgs& args, hipStream_t stream) {
                         hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<2>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<3>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     attr_set = true;
   }
   dim3 grid(static_cast<unsigned>(blocks)), block(256);
   if (args.out_kind == 0) hipLaunchKernelGGL(fx16_t64_kernel<0>, grid, block, kLdsBytes, stream, args);
   else if (args.out_kind == 1) hipLaunchKernelGGL(fx16_t64_kernel<1>, grid, block, kLdsBytes, stream, args);
-  else hipLaunchKernelGGL(fx16_t64_kernel<2>, grid, block, kLdsBytes, stream, args);
+  else if (args.out_kind == 2) hipLaunchKernelGGL(fx16_t64_kernel<2>, grid, block, kLdsBytes, stream, args);
+  else hipLaunchKernelGGL(fx16_t64_kernel<3>, grid, block, kLdsBytes, stream, args);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
