@@ -325,7 +325,8 @@ int build_device_2d64(qcoll_plan_s* p) {
           int r = rrow(v, lane >> 5), c = lane & 31;
           if (r >= np || c >= np) continue;
           int64_t k = static_cast<int64_t>(r + np * (w >> 1)) * n + (c + np * (w & 1));
-          size_t o = ((static_cast<size_t>(q) * 4 + w) * 64 + lane) * 32 + 2 * v;
+          // [q][quarter w][register v][lane][re, im]: 1 KB per wavefront load
+          size_t o = (((static_cast<size_t>(q) * 4 + w) * 16 + v) * 64 + lane) * 2;
           ft[o] = val(k).real() * sc;
           ft[o + 1] = val(k).imag() * sc;
         }

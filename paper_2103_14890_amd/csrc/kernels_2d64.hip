@@ -30,9 +30,11 @@ namespace {
 
 // LDS: four complex FP64 32x32 slots in [slot][register][lane] order (a lane's
 // 16-byte value for register v of slot s sits at (s * 16 + v) * 64 + lane), the
-// row-twiddle table [p1][k1'] and a small reduction area.
+// row-twiddle table [p1][k1'], a small reduction area, and per wavefront the
+// combined twiddle w^(k'.p) of each of its lane's modes (same [register][lane]
+// order), which is the same for every cell and filter.
 constexpr int kZSlot = 16 * 64;                      // complex values per slot
-constexpr int kLdsBytes = (4 * kZSlot + 2 * 32 + 8 * 4) * 16;
+constexpr int kLdsBytes = (4 * kZSlot + 2 * 32 + 8 * 4 + 4 * kZSlot) * 16 + kEoLdsBytes;
 
 struct Cd {
   double x, y;
@@ -40,12 +42,30 @@ struct Cd {
 
 __device__ __forceinline__ Cd cmul(Cd a, Cd b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 
+// Parity sub-grid x[m1][m2] = f[2 m1 + p1][2 m2 + p2] of one cell in the 32x32
+// result-tile layout, zero outside n' x n'. The lane index is opaque so that the
+// addresses are formed here rather than hoisted out of the cell loop.
+__device__ __forceinline__ void load_subgrid(const KernelArgs& a, int64_t cell, int p1, int p2, float* fv) {
+  int lane = threadIdx.x & 63;
+  asm volatile("" : "+v"(lane));
+  const int h = lane >> 5, c = lane & 31;
+  const int n = a.n, np = n >> 1;
+  const float* fc = a.f + cell * static_cast<int64_t>(n) * n;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int r = rrow(v, h);
+    fv[v] = (r < np && c < np) ? fc[(2 * r + p1) * n + 2 * c + p2] : 0.0f;
+  }
+}
+
 template <int OUT>
 __global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
   extern __shared__ double lds[];
   Cd* zs = reinterpret_cast<Cd*>(lds);                 // [4][16][64]
   Cd* tw = zs + 4 * kZSlot;                            // [2][32]
   double* red = reinterpret_cast<double*>(tw + 64);    // [4 waves][4]
+  Cd* twp = reinterpret_cast<Cd*>(red + 32) + (threadIdx.x >> 6) * kZSlot;  // this wave's [16][64]
+  half8* eo = reinterpret_cast<half8*>(reinterpret_cast<Cd*>(red + 32) + 4 * kZSlot);  // DFT lo parts
 
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
@@ -57,8 +77,11 @@ __global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
   for (int i = threadIdx.x; i < 64; i += blockDim.x) tw[i] = {a.tw[2 * i], a.tw[2 * i + 1]};
   const Cd c2 = {a.tw[2 * (32 * p2 + c)], a.tw[2 * (32 * p2 + c) + 1]};
   __syncthreads();
+#pragma unroll
+  for (int v = 0; v < 16; ++v) twp[v * 64 + lane] = cmul(tw[32 * p1 + rrow(v, h)], c2);
 
-  Split3 E[3][2];
+  load_eo_table(a, eo);
+  Split2 E[3][2];
   {
     const half8* src = reinterpret_cast<const half8*>(a.econst) + lane * 18;
 #pragma unroll
@@ -67,20 +90,14 @@ __global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
       for (int s = 0; s < 2; ++s) {
         E[m][s].l = src[(m * 2 + s) * 3 + 0];
         E[m][s].h = src[(m * 2 + s) * 3 + 1];
-        E[m][s].o = src[(m * 2 + s) * 3 + 2];
       }
   }
   const double sgn[4] = {1.0, (p2 ? -1.0 : 1.0), (p1 ? -1.0 : 1.0), ((p1 ^ p2) ? -1.0 : 1.0)};
 
   for (int64_t cell = blockIdx.x; cell < a.cells; cell += gridDim.x) {
     // ---- own parity sub-grid x[m1][m2] = f[2 m1 + p1][2 m2 + p2]
-    const float* fc = a.f + cell * static_cast<int64_t>(n) * n;
     float fv[16];
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int r = rrow(v, h);
-      fv[v] = (r < np && c < np) ? fc[(2 * r + p1) * n + 2 * c + p2] : 0.0f;
-    }
+    load_subgrid(a, cell, p1, p2, fv);
     // ---- n'-point 2D DFT of the sub-grid (as in the N <= 32 kernel)
     float fm = 0.0f;
 #pragma unroll
@@ -95,22 +112,21 @@ __global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
     f32x16 r0{}, r1{}, i0{}, i1{};
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      mma6(A[s], E[kEr][s], r0, r1);
-      mma6(A[s], E[kNEi][s], i0, i1);
+      mma6_lo_lds(A[s], E[kEr][s], eo + (kEr * 2 + s) * 64 + lane, r0, r1);
+      mma6_lo_lds(A[s], E[kNEi][s], eo + (kNEi * 2 + s) * 64 + lane, i0, i1);
     }
     int sc = -(a0 + 9);
     const int a1 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
     slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a1), A);
-    pass64(A, E, kEr, kEi, kNEi, kEr, true, r0, r1, i0, i1);
+    pass64_lo_lds(A, E, eo, kEr, kEi, kNEi, kEr, true, r0, r1, i0, i1);
     sc = sc - a1 - 9;
     // ---- twiddle w^(-k'.p) and exchange: T_p -> f_hat quarter a = w
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const Cd t1 = tw[32 * p1 + rrow(v, h)];
-      const Cd tt = cmul({t1.x, -t1.y}, {c2.x, -c2.y});
+      const Cd t = twp[v * 64 + lane];
       const Cd F = {ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), sc),
                     ldexp(static_cast<double>(i0[v]) + static_cast<double>(i1[v]), sc)};
-      zs[(w * 16 + v) * 64 + lane] = cmul(tt, F);
+      zs[(w * 16 + v) * 64 + lane] = cmul({t.x, -t.y}, F);
     }
     __syncthreads();
     double fr[16], fi[16];
@@ -135,12 +151,20 @@ __global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
     int sd_last = 0;
     for (int q = 0; q <= a.P; ++q) {
       // filtered quarter Z_a (true values) to LDS, with its max |component|
-      const double* mq = a.filt + ((static_cast<int64_t>(q) * 4 + w) * 64 + lane) * 32;
+      // filter values of this quarter: [q][quarter][register v][lane] complex
+      // (all 16 loads issued together: one exposed L2 latency per filter)
+      const double2* mq = reinterpret_cast<const double2*>(a.filt) + (static_cast<int64_t>(q) * 4 + w) * kZSlot;
+      int ml = lane;
+      asm volatile("" : "+v"(ml));
+      double2 mvv[16];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) mvv[v] = mq[v * 64 + ml];
+      __builtin_amdgcn_sched_barrier(0);
       const double zsc = ldexp(1.0, a.filt_exp[q]);
       float zm = 0.0f;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const double mr = mq[2 * v] * zsc, mi = mq[2 * v + 1] * zsc;
+        const double mr = mvv[v].x * zsc, mi = mvv[v].y * zsc;
         const Cd z = {mr * fr[v] - mi * fi[v], mr * fi[v] + mi * fr[v]};
         zs[(w * 16 + v) * 64 + lane] = z;
         zm = fmaxf(zm, fmaxf(fabsf(static_cast<float>(z.x)), fabsf(static_cast<float>(z.y))));
@@ -166,7 +190,7 @@ __global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
             sr += sgn[s] * t.x;
             si += sgn[s] * t.y;
           }
-          const Cd g = cmul(cmul(tw[32 * p1 + rrow(v + u, h)], c2), {sr, si});
+          const Cd g = cmul(twp[(v + u) * 64 + lane], {sr, si});
           gr[u] = ldexp(g.x, b);
           gi[u] = ldexp(g.y, b);
         }
@@ -175,11 +199,11 @@ __global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
         __builtin_amdgcn_sched_barrier(0);  // bound the LDS reads in flight
       }
       __syncthreads();
-      pass64(A, E, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
+      pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
       int sd = -b - 9;
       const int a2 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
       slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a2), A);
-      pass64(A, E, kEr, kNEi, kEi, kEr, q < a.P, r0, r1, i0, i1);  // loss field: real part only
+      pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, q < a.P, r0, r1, i0, i1);  // loss: real part only
       sd = sd - a2 - 9;
       sd_last = sd;
       const double wq = q < a.P ? ldexp(1.0, 2 * sd) : 0.0;
@@ -190,11 +214,17 @@ __global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
         gain[v] = fma(re * wq, im, gain[v]);
       }
     }
+load_subgrid(a, cell, p1, p2, fv);  // re-read: not kept live through the filter loop
 #pragma unroll
     for (int v = 0; v < 16; ++v)
       gain[v] -= static_cast<double>(fv[v]) * ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), sd_last);
 
-    // ---- epilogue on this wave's parity class; cell-wide sums through LDS
+    // ---- epilogue on this wave's parity class; cell-wide sums through LDS. The
+    // lane indices are re-derived from an opaque copy so that the per-point
+    // velocities and addresses are not hoisted out of the cell loop.
+    int elane = lane;
+    asm volatile("" : "+v"(elane));
+    const int h = elane >> 5, c = elane & 31;
     const double v2c = -a.L + a.dv * (2 * c + p2);
     if (OUT == 0) {
       float* Qc = reinterpret_cast<float*>(a.q) + cell * static_cast<int64_t>(n) * n;
