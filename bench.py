@@ -140,6 +140,20 @@ def cpu_baseline(f64: np.ndarray, target_s: float, N: int, L: float, kernel: str
     return done, t_used, np.concatenate(outs)
 
 
+def copy_calibration(mib: int, dev) -> None:
+    """One device-to-device copy of `mib` MiB (a plain copy kernel of known size)
+    after the timed region, for scaling hardware byte counters."""
+    if mib <= 0:
+        return
+    import torch
+    src = torch.ones(mib << 18, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def serve_run(seconds: float, rate: float = 200.0, warm: float = 2.0) -> dict:
     """Open-loop serving of homogeneous relaxation requests (continuous batching):
     Poisson arrivals, N in {16, 24, 32, 48, 64}, Maxwell or hard spheres, 50-400
@@ -193,6 +207,7 @@ def bench_3d(args) -> int:
         qcoll.step_multi([pa, pb], [ga, gb], 0.01, 1.0, "imex")
     _, per_stage = time_launches(graph.replay, max(2, args.steps // 2), 1, stream)
     del ga, gb
+    copy_calibration(args.calibrate_copy, dev)
     tr = pa.info()["transforms"]
     flops = (mfma_flops_per_cell_3d(32, tr) * fa.shape[0] + mfma_flops_per_cell_3d(16, tr) * fb.shape[0])
 
@@ -288,13 +303,7 @@ def main() -> int:
         info = plan.info()
         res[prec] = dict(plan=plan, q=q, wall=wall, per=per, info=info)
 
-    if args.calibrate_copy > 0:
-        src = torch.ones(args.calibrate_copy << 18, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    copy_calibration(args.calibrate_copy, dev)
 
     # accuracy on a sample, against the oracle (also the CPU-baseline run)
     ncpu, t_cpu, q_ref = cpu_baseline(f64.astype(np.float32).astype(np.float64), args.cpu_seconds, NN, LL, KERN, MM)
