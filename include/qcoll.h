@@ -76,6 +76,7 @@ enum {
 #define QCOLL_CONSERVE 0x1u   /* FP64 moment projection; Q written as double   */
 #define QCOLL_R_LITERAL 0x2u  /* Carleman radius 2L/(3+sqrt 2)                  */
 #define QCOLL_HOST_ONLY 0x100u /* build the FP64 host tables only (no device)  */
+#define QCOLL_GALERKIN 0x4u   /* dealiased variant (qcoll_eval_galerkin), 2D   */
 
 /* Build a plan (section 3.3: directions, filters, loss multiplier; section
  * 3.1: grid). d in {2,3}; n_per_dim = N (even, 4..256); L > 0 half-width of
@@ -115,6 +116,23 @@ int qcoll_eval(qcoll_plan_t plan, const float* f, void* Q, int64_t cells, hipStr
  * dt > 0 and eps > 0 are required. */
 int qcoll_step(qcoll_plan_t plan, float* f, int64_t cells, double dt, double eps, int scheme,
                int32_t* status, hipStream_t stream);
+
+/* Dealiased (Galerkin) variant of Q_h (eqs. (VAR), (ode): the sum over l + m = k
+ * without wrap-around, k restricted to the modes of f). Plans created with
+ * QCOLL_GALERKIN (d = 2, N a multiple of 4) evaluate the operator on the grid of
+ * Nf = 3N/2 points per axis with the filters restricted to the active N-grid
+ * modes (no component equal to -N/2), between a trigonometric interpolation of f
+ * onto that grid and a restriction of Q back to the active N-grid modes; products
+ * on the finer grid are exact non-wrapping convolutions for the kept modes. The
+ * device kernels need Nf within the device sizes (N <= 40 in QCOLL_MIX_FX16,
+ * N <= 20 in QCOLL_FP32). f: device float[cells][N][N]; Q: device
+ * float[cells][N][N], or double with QCOLL_CONSERVE (FP64 projection on the N
+ * grid). work: device buffer owned by the caller of at least
+ * qcoll_galerkin_work_bytes() bytes (fine-grid f and Q); its content is scratch.
+ * Galerkin plans accept no other evaluation or step call (QCOLL_EUNSUPPORTED). */
+int64_t qcoll_galerkin_work_bytes(qcoll_plan_t plan, int64_t cells);
+int qcoll_eval_galerkin(qcoll_plan_t plan, const float* f, void* Q, int64_t cells, void* work, int64_t work_bytes,
+                        hipStream_t stream);
 
 /* One multi-stage penalised IMEX Runge-Kutta step of d f/dt = Q(f)/eps in
  * place (eqs. (GIMEXb), (GIMEX1b) without transport, section 3.4). The
@@ -172,6 +190,8 @@ int qcoll_plan_info(qcoll_plan_t plan, int* transforms, int* K_r, double* R, int
  *   3 loss multiplier l(k) = sum_t W_t alpha_t alpha'_t (out[N^d])
  *   4 radial eigenvalues lambda_j (out[K_r]; {1} for separable kernels)
  *   5 inverse Gram matrix of phi = (1, v, |v|^2) on the grid (out[(d+2)^2])
+ * A Galerkin plan returns tables 0-4 of its Nf grid (0, 1 and 3 zero outside the
+ * active N-grid modes) and table 5 of the N grid.
  * n is the capacity of out; returns the number of values written or QCOLL_EINVAL. */
 int qcoll_plan_table(qcoll_plan_t plan, int which, int index, double* out, int64_t n);
 

@@ -12,7 +12,11 @@
 #include "qcoll.h"
 
 struct qcoll_plan_s {
-  qcoll::HostPlan hp;
+  qcoll::HostPlan hp;          // the grid the kernels run on (the fine grid of a Galerkin plan)
+  qcoll::HostPlan hp_coarse;   // Galerkin plans: the N grid of f and Q
+  bool galerkin = false;
+  double* gal_interp = nullptr;    // [Nf][N]
+  double* gal_restrict = nullptr;  // [N][Nf]
   int precision = 0;
   unsigned flags = 0;
   int device = -1;
@@ -71,6 +75,9 @@ void free_device(qcoll_plan_s* p) {
   hipFree(p->tw);
   hipFree(p->filt3);
   hipFree(p->scratch);
+  hipFree(p->gal_interp);
+  hipFree(p->gal_restrict);
+  p->gal_interp = p->gal_restrict = nullptr;
   p->filt3 = nullptr;
   p->scratch = nullptr;
   p->tw = nullptr;
@@ -472,12 +479,25 @@ int qcoll_plan(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, do
   if (!out) return QCOLL_EINVAL;
   *out = nullptr;
   if (precision != QCOLL_FP32 && precision != QCOLL_MIX_FX16) return QCOLL_EINVAL;
-  if (flags & ~(QCOLL_CONSERVE | QCOLL_R_LITERAL | QCOLL_HOST_ONLY)) return QCOLL_EINVAL;
+  if (flags & ~(QCOLL_CONSERVE | QCOLL_R_LITERAL | QCOLL_HOST_ONLY | QCOLL_GALERKIN)) return QCOLL_EINVAL;
   qcoll_plan_s* p = new (std::nothrow) qcoll_plan_s;
   if (!p) return QCOLL_ENOMEM;
   p->precision = precision;
   p->flags = flags;
-  int rc = qcoll::build_host_plan(p->hp, d, n_per_dim, L, kernel, b, M, K_r, flags);
+  int rc;
+  if (flags & QCOLL_GALERKIN) {
+    if (n_per_dim % 4) {
+      delete p;
+      return QCOLL_EINVAL;
+    }
+    p->galerkin = true;
+    rc = qcoll::build_host_plan(p->hp_coarse, d, n_per_dim, L, kernel, b, M, K_r, flags);
+    if (!rc && d != 2) rc = QCOLL_EUNSUPPORTED;
+    if (!rc) rc = qcoll::build_host_plan(p->hp, d, 3 * n_per_dim / 2, L, kernel, b, M, K_r, flags);
+    if (!rc) qcoll::restrict_to_coarse_modes(p->hp, n_per_dim);
+  } else {
+    rc = qcoll::build_host_plan(p->hp, d, n_per_dim, L, kernel, b, M, K_r, flags);
+  }
   if (rc) {
     delete p;
     return rc;
@@ -500,6 +520,11 @@ int qcoll_plan(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, do
     p->tile = p->hp.N > 32 ? 64 : (p->hp.N > 16 ? 32 : 16);
     if (p->hp.d == 3) rc = build_device_3d(p);
     else rc = p->tile == 64 ? build_device_2d64(p) : (p->tile == 32 ? build_device_2d32(p) : build_device_2d16(p));
+    if (!rc && p->galerkin) {
+      std::vector<double> gi, gr;
+      qcoll::galerkin_operators(p->hp_coarse.N, p->hp.N, gi, gr);
+      if (!(rc = upload(gi, &p->gal_interp, p->device_bytes))) rc = upload(gr, &p->gal_restrict, p->device_bytes);
+    }
     if (rc) {
       free_device(p);
       delete p;
@@ -513,7 +538,7 @@ int qcoll_plan(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, do
 
 int qcoll_eval(qcoll_plan_t p, const float* f, void* Q, int64_t cells, hipStream_t stream) {
   if (!p || cells < 0) return QCOLL_EINVAL;
-  if (!p->on_device) return QCOLL_EUNSUPPORTED;
+  if (!p->on_device || p->galerkin) return QCOLL_EUNSUPPORTED;
   if (cells == 0) return QCOLL_OK;
   if (!f || !Q) return QCOLL_EINVAL;
   int64_t n = static_cast<int64_t>(p->hp.N) * p->hp.N * (p->hp.d == 3 ? p->hp.N : 1);
@@ -539,7 +564,7 @@ int qcoll_step(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps, i
   if (!p || cells < 0) return QCOLL_EINVAL;
   if (!(dt > 0.0) || !(eps > 0.0) || !std::isfinite(dt) || !std::isfinite(eps)) return QCOLL_EINVAL;
   if (scheme != QCOLL_EXPLICIT_EULER && scheme != QCOLL_IMEX_EULER_PENALIZED) return QCOLL_EINVAL;
-  if (!p->on_device) return QCOLL_EUNSUPPORTED;
+  if (!p->on_device || p->galerkin) return QCOLL_EUNSUPPORTED;
   if (cells == 0) return QCOLL_OK;
   if (!f) return QCOLL_EINVAL;
   if (p->hp.d == 3) {
@@ -566,6 +591,46 @@ namespace {
 int rk_stages(int scheme) { return scheme == QCOLL_IMEX_ARS222 ? 3 : (scheme == QCOLL_IMEX_BPR343 ? 5 : 0); }
 }  // namespace
 
+int64_t qcoll_galerkin_work_bytes(qcoll_plan_t p, int64_t cells) {
+  if (!p || !p->galerkin || cells < 0) return -1;
+  const int64_t nf2 = static_cast<int64_t>(p->hp.N) * p->hp.N;
+  return cells * nf2 * static_cast<int64_t>(sizeof(float) + sizeof(double));
+}
+
+int qcoll_eval_galerkin(qcoll_plan_t p, const float* f, void* Q, int64_t cells, void* work, int64_t work_bytes,
+                        hipStream_t stream) {
+  if (!p || cells < 0) return QCOLL_EINVAL;
+  if (!p->galerkin || !p->on_device) return QCOLL_EUNSUPPORTED;
+  if (cells == 0) return QCOLL_OK;
+  if (!f || !Q || !work || work_bytes < qcoll_galerkin_work_bytes(p, cells)) return QCOLL_EINVAL;
+  const int n = p->hp_coarse.N, nf = p->hp.N;
+  const int64_t nf2 = static_cast<int64_t>(nf) * nf;
+  double* q_fine = static_cast<double*>(work);                      // [cells][nf][nf] double
+  float* f_fine = reinterpret_cast<float*>(q_fine + cells * nf2);    // [cells][nf][nf] float
+  qcoll::GalerkinArgs g;
+  g.f = f;
+  g.f_fine = f_fine;
+  g.q_fine = q_fine;
+  g.q = Q;
+  g.cells = cells;
+  g.n = n;
+  g.nf = nf;
+  g.interp = p->gal_interp;
+  g.restrict_ = p->gal_restrict;
+  g.conserve = (p->flags & QCOLL_CONSERVE) ? 1 : 0;
+  for (int i = 0; i < 16; ++i) g.gram_inv[i] = p->hp_coarse.gram_inv[i];
+  g.L = p->hp_coarse.L;
+  g.dv = 2.0 * p->hp_coarse.L / n;
+  if (qcoll::launch_galerkin_interp(g, stream)) return QCOLL_EDEVICE;
+  qcoll::KernelArgs a = make_args(p);
+  a.f = f_fine;
+  a.q = q_fine;
+  a.cells = cells;
+  a.out_kind = 4;
+  if (launch(a, stream)) return QCOLL_EDEVICE;
+  return qcoll::launch_galerkin_restrict(g, stream) ? QCOLL_EDEVICE : QCOLL_OK;
+}
+
 int64_t qcoll_step_rk_work_bytes(qcoll_plan_t p, int scheme, int64_t cells) {
   const int S = rk_stages(scheme);
   if (!p || S == 0 || cells < 0) return -1;
@@ -579,7 +644,7 @@ int qcoll_step_rk(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps
   if (!(dt > 0.0) || !(eps > 0.0) || !std::isfinite(dt) || !std::isfinite(eps)) return QCOLL_EINVAL;
   const int S = rk_stages(scheme);
   if (S == 0) return QCOLL_EINVAL;
-  if (!p->on_device) return QCOLL_EUNSUPPORTED;
+  if (!p->on_device || p->galerkin) return QCOLL_EUNSUPPORTED;
   if (cells == 0) return QCOLL_OK;
   if (!f || !work || work_bytes < qcoll_step_rk_work_bytes(p, scheme, cells)) return QCOLL_EINVAL;
   const int64_t stride = cells * static_cast<int64_t>(p->hp.N) * p->hp.N * (p->hp.d == 3 ? p->hp.N : 1);
@@ -632,7 +697,7 @@ static int multi_launch(const qcoll_plan_t* plans, int nplans, const float* cons
   for (int i = 0; i < nplans; ++i) {
     const qcoll_plan_s* p = plans[i];
     if (!p || cells[i] < 0) return QCOLL_EINVAL;
-    if (!p->on_device) return QCOLL_EUNSUPPORTED;
+    if (!p->on_device || p->galerkin) return QCOLL_EUNSUPPORTED;
     if (dev >= 0 && p->device != dev) return QCOLL_EINVAL;
     dev = p->device;
     if (cells[i] > 0 && (!f[i] || (!step && !Q[i]))) return QCOLL_EINVAL;
@@ -734,7 +799,7 @@ int qcoll_plan_get_launch(qcoll_plan_t p, int* waves_per_block, int64_t* max_blo
 // stream. Q receives the result of the last timed launch.
 int qcoll_plan_autotune(qcoll_plan_t p, const float* f, void* Q, int64_t cells, int reps, hipStream_t stream) {
   if (!p || !f || !Q || cells < 1 || reps < 1) return QCOLL_EINVAL;
-  if (!p->on_device || p->hp.d == 3) return QCOLL_EUNSUPPORTED;  // 3D: one fixed launch shape
+  if (!p->on_device || p->hp.d == 3 || p->galerkin) return QCOLL_EUNSUPPORTED;  // one fixed launch shape
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return QCOLL_EDEVICE;
   const int wpbs[3] = {1, 2, 4};
@@ -796,7 +861,7 @@ int qcoll_plan_table(qcoll_plan_t p, int which, int index, double* out, int64_t 
     case 2: src = &hp.W; break;
     case 3: src = &hp.loss; break;
     case 4: src = &hp.lambda; break;
-    case 5: src = &hp.gram_inv; break;
+    case 5: src = p->galerkin ? &p->hp_coarse.gram_inv : &hp.gram_inv; break;
     default: return QCOLL_EINVAL;
   }
   if (static_cast<int64_t>(src->size()) > n) return QCOLL_EINVAL;

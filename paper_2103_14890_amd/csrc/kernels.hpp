@@ -27,7 +27,7 @@ struct KernelArgs {
   int scheme = 0;
   int32_t* status = nullptr;
   int out_kind = 0;             // 0 eval (float Q), 1 eval with projection (double Q), 2 step,
-                                // 3 stage of a multi-stage IMEX step
+                                // 3 stage of a multi-stage IMEX step, 4 double Q without projection
   // out_kind 3: stage rk_stage (2..S) of scheme rk_scheme (1 ARS(2,2,2), 2
   // BPR(3,4,3)); f holds the stage input F_{l-1}, rk_fn the step's start value
   // f^n (overwritten with the result by the last stage), rk_work the stage
@@ -91,6 +91,26 @@ struct Args3 {
   int64_t blocks = 0;           // workgroups (at most the scratch capacity)
 };
 int launch_3d(const Args3& args, hipStream_t stream);
+
+// Dealiased (Galerkin) variant, 2D: trigonometric interpolation of f from the
+// n grid to the nf grid (interp [nf][n] FP64) and restriction of the fine-grid
+// Q back (restrict_ [n][nf]), with the FP64 projection (gram_inv, 4x4) when
+// conserve is set (Q stored as double), else Q as float.
+struct GalerkinArgs {
+  const float* f = nullptr;       // [cells][n][n]
+  float* f_fine = nullptr;        // [cells][nf][nf]
+  const double* q_fine = nullptr; // [cells][nf][nf]
+  void* q = nullptr;              // [cells][n][n] float, or double with the projection
+  int64_t cells = 0;
+  int n = 0, nf = 0;
+  const double* interp = nullptr;     // [nf][n]
+  const double* restrict_ = nullptr;  // [n][nf]
+  int conserve = 0;
+  double gram_inv[16] = {};       // inverse Gram matrix of (1, v1, v2, |v|^2) on the n grid
+  double L = 0, dv = 0;
+};
+int launch_galerkin_interp(const GalerkinArgs& args, hipStream_t stream);
+int launch_galerkin_restrict(const GalerkinArgs& args, hipStream_t stream);
 
 // Single-plan launches (args.tile selects the 16x16 or 32x32 kernel family).
 int launch_2d16(const KernelArgs& args, hipStream_t stream);

@@ -78,18 +78,22 @@ int launch_2d32(const KernelArgs& args, hipStream_t stream) {
                           hipFuncAttributeMaxDynamicSharedMemorySize, mx);
       hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t32_kernel<3>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+      hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t32_kernel<4>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, mx);
       return true;
     }();
     (void)attr_set;
     if (args.out_kind == 0) hipLaunchKernelGGL(fx16_t32_kernel<0>, grid, block, lds, stream, args);
     else if (args.out_kind == 1) hipLaunchKernelGGL(fx16_t32_kernel<1>, grid, block, lds, stream, args);
     else if (args.out_kind == 2) hipLaunchKernelGGL(fx16_t32_kernel<2>, grid, block, lds, stream, args);
-    else hipLaunchKernelGGL(fx16_t32_kernel<3>, grid, block, lds, stream, args);
+    else if (args.out_kind == 3) hipLaunchKernelGGL(fx16_t32_kernel<3>, grid, block, lds, stream, args);
+    else hipLaunchKernelGGL(fx16_t32_kernel<4>, grid, block, lds, stream, args);
   } else {
     if (args.out_kind == 0) hipLaunchKernelGGL(fp32_t32_kernel<0>, grid, block, 0, stream, args);
     else if (args.out_kind == 1) hipLaunchKernelGGL(fp32_t32_kernel<1>, grid, block, 0, stream, args);
     else if (args.out_kind == 2) hipLaunchKernelGGL(fp32_t32_kernel<2>, grid, block, 0, stream, args);
-    else hipLaunchKernelGGL(fp32_t32_kernel<3>, grid, block, 0, stream, args);
+    else if (args.out_kind == 3) hipLaunchKernelGGL(fp32_t32_kernel<3>, grid, block, 0, stream, args);
+    else hipLaunchKernelGGL(fp32_t32_kernel<4>, grid, block, 0, stream, args);
   }
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }

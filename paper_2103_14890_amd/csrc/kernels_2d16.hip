@@ -49,12 +49,14 @@ int launch_2d16(const KernelArgs& args, hipStream_t stream) {
     if (args.out_kind == 0) hipLaunchKernelGGL(fx16_t16_kernel<0>, grid, block, 0, stream, args);
     else if (args.out_kind == 1) hipLaunchKernelGGL(fx16_t16_kernel<1>, grid, block, 0, stream, args);
     else if (args.out_kind == 2) hipLaunchKernelGGL(fx16_t16_kernel<2>, grid, block, 0, stream, args);
-    else hipLaunchKernelGGL(fx16_t16_kernel<3>, grid, block, 0, stream, args);
+    else if (args.out_kind == 3) hipLaunchKernelGGL(fx16_t16_kernel<3>, grid, block, 0, stream, args);
+    else hipLaunchKernelGGL(fx16_t16_kernel<4>, grid, block, 0, stream, args);
   } else {
     if (args.out_kind == 0) hipLaunchKernelGGL(fp32_t16_kernel<0>, grid, block, 0, stream, args);
     else if (args.out_kind == 1) hipLaunchKernelGGL(fp32_t16_kernel<1>, grid, block, 0, stream, args);
     else if (args.out_kind == 2) hipLaunchKernelGGL(fp32_t16_kernel<2>, grid, block, 0, stream, args);
-    else hipLaunchKernelGGL(fp32_t16_kernel<3>, grid, block, 0, stream, args);
+    else if (args.out_kind == 3) hipLaunchKernelGGL(fp32_t16_kernel<3>, grid, block, 0, stream, args);
+    else hipLaunchKernelGGL(fp32_t16_kernel<4>, grid, block, 0, stream, args);
   }
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }

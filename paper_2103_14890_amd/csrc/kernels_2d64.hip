@@ -226,7 +226,14 @@ load_subgrid(a, cell, p1, p2, fv);  // re-read: not kept live through the filter
     asm volatile("" : "+v"(elane));
     const int h = elane >> 5, c = elane & 31;
     const double v2c = -a.L + a.dv * (2 * c + p2);
-    if (OUT == 0) {
+    if (OUT == 4) {  // double Q without projection (fine-grid stage of the Galerkin variant)
+      double* Qc = reinterpret_cast<double*>(a.q) + cell * static_cast<int64_t>(n) * n;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int r = rrow(v, h);
+        if (r < np && c < np) Qc[(2 * r + p1) * n + 2 * c + p2] = gain[v];
+      }
+    } else if (OUT == 0) {
       float* Qc = reinterpret_cast<float*>(a.q) + cell * static_cast<int64_t>(n) * n;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
@@ -387,13 +394,16 @@ int launch_2d64(const KernelArgs& args, hipStream_t stream) {
                         hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<3>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<4>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     attr_set = true;
   }
   dim3 grid(static_cast<unsigned>(blocks)), block(256);
   if (args.out_kind == 0) hipLaunchKernelGGL(fx16_t64_kernel<0>, grid, block, kLdsBytes, stream, args);
   else if (args.out_kind == 1) hipLaunchKernelGGL(fx16_t64_kernel<1>, grid, block, kLdsBytes, stream, args);
   else if (args.out_kind == 2) hipLaunchKernelGGL(fx16_t64_kernel<2>, grid, block, kLdsBytes, stream, args);
-  else hipLaunchKernelGGL(fx16_t64_kernel<3>, grid, block, kLdsBytes, stream, args);
+  else if (args.out_kind == 3) hipLaunchKernelGGL(fx16_t64_kernel<3>, grid, block, kLdsBytes, stream, args);
+  else hipLaunchKernelGGL(fx16_t64_kernel<4>, grid, block, kLdsBytes, stream, args);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

@@ -88,7 +88,8 @@ __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, 
     if (a.out_kind == 0) finish_cell<0, LY>(a, cell, fv, q, lane);
     else if (a.out_kind == 1) finish_cell<1, LY>(a, cell, fv, q, lane);
     else if (a.out_kind == 2) finish_cell<2, LY>(a, cell, fv, q, lane);
-    else finish_cell<3, LY>(a, cell, fv, q, lane);
+    else if (a.out_kind == 3) finish_cell<3, LY>(a, cell, fv, q, lane);
+    else finish_cell<4, LY>(a, cell, fv, q, lane);
     return;
   }
   // The velocities and addresses below are the same for every cell; an opaque
@@ -105,6 +106,15 @@ __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, 
     for (int v = 0; v < kV; ++v) {
       const int r = LY::row(v, lane);
       if (r < n && c < n) Qc[r * n + c] = static_cast<float>(q[v]);
+    }
+    return;
+  }
+  if (OUT == 4) {  // Q as double, no projection (the fine-grid stage of the Galerkin variant)
+    double* Qc = reinterpret_cast<double*>(a.q) + base;
+#pragma unroll
+    for (int v = 0; v < kV; ++v) {
+      const int r = LY::row(v, lane);
+      if (r < n && c < n) Qc[r * n + c] = q[v];
     }
     return;
   }

@@ -373,4 +373,40 @@ int build_host_plan(HostPlan& hp, int d, int N, double L, int kernel, double b, 
   return QCOLL_OK;
 }
 
+void restrict_to_coarse_modes(HostPlan& hp, int Nc) {
+  const int d = hp.d, Nf = hp.N;
+  int64_t n = 1;
+  for (int a = 0; a < d; ++a) n *= Nf;
+  for (int64_t k = 0; k < n; ++k) {
+    int64_t rem = k;
+    bool keep = true;
+    for (int a = d - 1; a >= 0; --a) {
+      const int m = mode_of(static_cast<int>(rem % Nf), Nf);
+      rem /= Nf;
+      if (!(m > -Nc / 2 && m < Nc / 2)) keep = false;
+    }
+    if (keep) continue;
+    for (auto& v : hp.alpha) v[k] = 0.0;
+    for (auto& v : hp.alphap) v[k] = 0.0;
+    for (auto& v : hp.packed) v[k] = 0.0;
+    hp.loss[k] = 0.0;
+    hp.loss_scaled[k] = 0.0;
+  }
+}
+
+void galerkin_operators(int Nc, int Nf, std::vector<double>& interp, std::vector<double>& restrict_) {
+  const double two_pi = 6.283185307179586476925286766559;
+  interp.assign(static_cast<size_t>(Nf) * Nc, 0.0);
+  restrict_.assign(static_cast<size_t>(Nc) * Nf, 0.0);
+  for (int a = 0; a < Nf; ++a)
+    for (int j = 0; j < Nc; ++j) {
+      // sum over the active modes k = -Nc/2+1 .. Nc/2-1 of exp(2 pi i k (a/Nf - j/Nc)): real
+      const double x = static_cast<double>(a) / Nf - static_cast<double>(j) / Nc;
+      double s = 1.0;
+      for (int k = 1; k < Nc / 2; ++k) s += 2.0 * std::cos(two_pi * k * x);
+      interp[static_cast<size_t>(a) * Nc + j] = s / Nc;
+      restrict_[static_cast<size_t>(j) * Nf + a] = s / Nf;
+    }
+}
+
 }  // namespace qcoll

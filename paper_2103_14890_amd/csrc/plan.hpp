@@ -33,6 +33,18 @@ struct HostPlan {
 int build_host_plan(HostPlan& hp, int d, int N, double L, int kernel, double b, int M, int K_r,
                     unsigned flags);
 
+// Dealiased (Galerkin) variant: restrict a plan built on the fine grid
+// Nf = 3 Nc / 2 to the active modes of the Nc grid (integer components strictly
+// between -Nc/2 and Nc/2): filters, loss multiplier and packed multipliers are
+// zeroed elsewhere, so that products on the fine grid are the non-wrapping
+// convolutions of eq. (ode) for the kept modes.
+void restrict_to_coarse_modes(HostPlan& hp, int Nc);
+
+// Real trigonometric interpolation (Nf x Nc, row-major) from the Nc grid to the
+// Nf grid through the active Nc modes, and the matching restriction (Nc x Nf):
+// transform, keep the active Nc modes, transform back.
+void galerkin_operators(int Nc, int Nf, std::vector<double>& interp, std::vector<double>& restrict_);
+
 // Gauss-Legendre nodes and weights on [-1, 1] (Newton on the Legendre recurrence).
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 

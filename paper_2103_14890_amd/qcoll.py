@@ -19,7 +19,7 @@ HEADER = os.path.join(os.path.dirname(_PKG), "include", "qcoll.h")
 MAXWELL, HARD_SPHERE = 0, 1
 FP32, MIX_FX16 = 1, 4
 EXPLICIT_EULER, IMEX_EULER_PENALIZED, IMEX_ARS222, IMEX_BPR343 = 0, 1, 2, 3
-CONSERVE, R_LITERAL, HOST_ONLY = 0x1, 0x2, 0x100
+CONSERVE, R_LITERAL, GALERKIN, HOST_ONLY = 0x1, 0x2, 0x4, 0x100
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
 
 _KERNELS = {"maxwell": MAXWELL, "hard_sphere": HARD_SPHERE}
@@ -59,6 +59,10 @@ def _load() -> ctypes.CDLL:
     lib.qcoll_step_rk_work_bytes.restype = i64
     lib.qcoll_step_rk.argtypes = [vp, vp, i64, dbl, dbl, c_int, vp, i64, vp, vp]
     lib.qcoll_step_rk.restype = c_int
+    lib.qcoll_galerkin_work_bytes.argtypes = [vp, i64]
+    lib.qcoll_galerkin_work_bytes.restype = i64
+    lib.qcoll_eval_galerkin.argtypes = [vp, vp, vp, i64, vp, i64, vp]
+    lib.qcoll_eval_galerkin.restype = c_int
     lib.qcoll_plan_info.argtypes = [vp, ctypes.POINTER(c_int), ctypes.POINTER(c_int), ctypes.POINTER(dbl),
                                     ctypes.POINTER(i64)]
     lib.qcoll_plan_info.restype = c_int
@@ -123,14 +127,15 @@ class Plan:
 
     def __init__(self, d: int, N: int, L: float, kernel: str = "hard_sphere", M: int = 8, b: float = 0.0,
                  K_r: int = 0, precision: str = "fx16", conserve: bool = False, r_literal: bool = False,
-                 host_only: bool = False):
-        flags = (CONSERVE if conserve else 0) | (R_LITERAL if r_literal else 0) | (HOST_ONLY if host_only else 0)
+                 host_only: bool = False, galerkin: bool = False):
+        flags = ((CONSERVE if conserve else 0) | (R_LITERAL if r_literal else 0) | (HOST_ONLY if host_only else 0)
+                 | (GALERKIN if galerkin else 0))
         h = ctypes.c_void_p()
         _check(LIB.qcoll_plan(ctypes.byref(h), d, N, float(L), _KERNELS[kernel], float(b), M, K_r,
                               _PRECISIONS[precision], flags), "qcoll_plan")
         self._h = h
         self.d, self.N, self.L, self.kernel, self.M = d, N, float(L), kernel, M
-        self.precision, self.conserve = precision, conserve
+        self.precision, self.conserve, self.galerkin = precision, conserve, galerkin
 
     def step_rk(self, f, dt: float, eps: float = 1.0, scheme: str = "ars222", status=None, work=None,
                 stream=None):
@@ -161,7 +166,8 @@ class Plan:
 
     def table(self, which: int, index: int = 0, size: int | None = None):
         import numpy as np
-        cap = size if size is not None else max(self.n, 64)
+        grid = (3 * self.N // 2) ** self.d if self.galerkin else self.n   # Galerkin tables live on the 3N/2 grid
+        cap = size if size is not None else max(grid, 64)
         out = np.zeros(cap, dtype=np.float64)
         cnt = _check(LIB.qcoll_plan_table(self._h, which, index, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                           cap), "qcoll_plan_table")
@@ -178,6 +184,26 @@ class Plan:
                               cells, _stream_ptr(stream)), "qcoll_eval")
         return q
 
+    def galerkin_work_bytes(self, cells: int) -> int:
+        return _check(int(LIB.qcoll_galerkin_work_bytes(self._h, int(cells))), "qcoll_galerkin_work_bytes")
+
+    def eval_galerkin(self, f, q=None, work=None, stream=None):
+        """Dealiased Q_h(f) of a Galerkin plan (qcoll_eval_galerkin); work is a
+        device tensor of at least galerkin_work_bytes() bytes (allocated here
+        when not given)."""
+        import torch
+        cells = f.shape[0]
+        if q is None:
+            q = torch.empty(f.shape, dtype=torch.float64 if self.conserve else torch.float32, device=f.device)
+        need = self.galerkin_work_bytes(cells)
+        if work is None:
+            work = torch.empty(max(need // 8, 1), dtype=torch.float64, device=f.device)
+        _check(LIB.qcoll_eval_galerkin(self._h, _dev_ptr(f, torch.float32, "f"),
+                                       _dev_ptr(q, torch.float64 if self.conserve else torch.float32, "Q"), cells,
+                                       _dev_ptr(work, work.dtype, "work"), work.numel() * work.element_size(),
+                                       _stream_ptr(stream)), "qcoll_eval_galerkin")
+        return q
+
     def step(self, f, dt: float, eps: float = 1.0, scheme: str = "explicit", status=None, stream=None):
         """One homogeneous step of f (in place)."""
         import torch
@@ -189,7 +215,8 @@ class Plan:
     @property
     def key(self) -> str:
         """Identity of the plan's workload shape for the autotuning cache."""
-        return f"d{self.d}_N{self.N}_{self.kernel}_M{self.M}_{self.precision}_{'c' if self.conserve else 'n'}"
+        return (f"d{self.d}_N{self.N}_{self.kernel}_M{self.M}_{self.precision}_{'c' if self.conserve else 'n'}"
+                + ("_galerkin" if self.galerkin else ""))
 
     def launch(self) -> tuple[int, int]:
         w, b = ctypes.c_int(), ctypes.c_int64()

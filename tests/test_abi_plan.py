@@ -120,3 +120,34 @@ def test_multi_and_tuning_argument_checks():
     assert p.launch() == (2, 512)
     assert qc.LIB.qcoll_plan_autotune(p._h, None, None, 4, 1, None) == qc.EINVAL
     p.close()
+
+
+def test_galerkin_plan_host_tables_and_checks():
+    """Galerkin plans: argument checks, work size, and the fine-grid tables
+    (the Nf = 3N/2 bank restricted to the active N-grid modes) against the
+    oracle's dealiased bank."""
+    from oracle import galerkin as og
+    assert _plan(N=30, flags=qc.GALERKIN | qc.HOST_ONLY)[0] == qc.EINVAL      # N a multiple of 4
+    assert _plan(d=3, N=8, prec=1, flags=qc.GALERKIN | qc.HOST_ONLY)[0] == qc.EUNSUPPORTED
+    assert _plan(N=48, flags=qc.GALERKIN)[0] == qc.EUNSUPPORTED               # 72-point grid
+    p = qc.Plan(2, 16, 8.0, "hard_sphere", 8, host_only=True, galerkin=True)
+    assert p.galerkin_work_bytes(5) == 5 * 24 * 24 * 12
+    assert qc.LIB.qcoll_eval_galerkin(p._h, None, None, 4, None, 0, None) == qc.EUNSUPPORTED
+    assert qc.LIB.qcoll_eval_galerkin(p._h, None, None, -1, None, 0, None) == qc.EINVAL
+    plain = qc.Plan(2, 16, 8.0, "hard_sphere", 8, host_only=True)
+    assert qc.LIB.qcoll_galerkin_work_bytes(plain._h, 4) == -1
+    assert qc.LIB.qcoll_eval_galerkin(plain._h, None, None, 4, None, 0, None) == qc.EUNSUPPORTED
+    s = sp.Setup(d=2, N=16, L=8.0, kernel="hard_sphere", M=8)
+    sf, bank = og.galerkin_bank(s)
+    assert sf.N == 24
+    scale = max(np.abs(a).max() for _, a, _ in bank)
+    for t, (W, a, ap) in enumerate(bank):
+        assert np.abs(p.table(0, t) - a.reshape(-1)).max() <= 1e-12 * scale
+        assert np.abs(p.table(1, t) - ap.reshape(-1)).max() <= 1e-12 * scale
+    ell = sp.loss_multiplier(bank).reshape(-1)
+    assert np.abs(p.table(3) - ell).max() <= 1e-12 * np.abs(ell).max()
+    C = sp.moment_matrix(2, 16, 8.0)          # the projection acts on the N grid
+    Gi = np.linalg.inv(C @ C.T)
+    assert np.abs(p.table(5, size=16) - Gi.reshape(-1)).max() <= 1e-10 * np.abs(Gi).max()
+    p.close()
+    plain.close()
