@@ -68,17 +68,30 @@ def mfma_flops_per_cell_3d(T: int, transforms: int) -> float:
     return (2.5 + 3 * transforms) * per_pass
 
 
-def kernel_source_hash() -> str:
-    """SHA-256 over the device sources (csrc/*.hip, *.hpp): identifies the kernel
-    build that a stored hardware-counter profile belongs to."""
+# Source file of the dominant kernel of each workload.
+KERNEL_SOURCE = {"hs2d_32": "kernels_2d.hip", "hs2d_64_noisy": "kernels_2d64.hip", "hs3d": "kernels_3d.hip"}
+
+
+def kernel_source_hash(workload: str) -> str:
+    """SHA-256 over the dominant kernel's source file and every local header it
+    includes (recursively): identifies the kernel build that a stored
+    hardware-counter profile belongs to."""
     import hashlib
-    h = hashlib.sha256()
+    import re
     d = os.path.join(ROOT, "paper_2103_14890_amd", "csrc")
-    for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".hpp")):
-            h.update(name.encode())
-            with open(os.path.join(d, name), "rb") as fh:
-                h.update(fh.read())
+    seen, todo = set(), [KERNEL_SOURCE[workload]]
+    while todo:
+        name = todo.pop()
+        if name in seen or not os.path.exists(os.path.join(d, name)):
+            continue
+        seen.add(name)
+        with open(os.path.join(d, name)) as fh:
+            todo += re.findall(r'#include\s+"([^"]+)"', fh.read())
+    h = hashlib.sha256()
+    for name in sorted(seen):
+        h.update(name.encode())
+        with open(os.path.join(d, name), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
@@ -97,7 +110,7 @@ def measured_traffic(workload: str):
             if ":" in line:
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("source_sha256") != kernel_source_hash():
+    if vals.get("source_sha256") != kernel_source_hash(workload):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -315,6 +328,22 @@ def main() -> int:
 
     serve = serve_run(args.serve_seconds) if args.serve_seconds > 0 else None
 
+    # time steps of the homogeneous relaxation on the same cells (FX16 plan
+    # without projection): single-stage IMEX Euler (one launch) and the
+    # multi-stage penalised IMEX RK steps (one launch per stage)
+    step_ms = {}
+    splan = qcoll.Plan(2, NN, LL, KERN, MM, precision="fx16")
+    fs = f.clone()
+    work = torch.empty(max(1, int(qcoll.LIB.qcoll_step_rk_work_bytes(splan._h, qcoll.IMEX_BPR343, cells)) // 4),
+                       dtype=torch.float32, device=dev)
+    for name, fn in (("imex_euler", lambda: splan.step(fs, 0.01, 1.0, "imex")),
+                     ("ars222", lambda: splan.step_rk(fs, 0.01, 1.0, "ars222", work=work)),
+                     ("bpr343", lambda: splan.step_rk(fs, 0.01, 1.0, "bpr343", work=work))):
+        _, per_s = time_launches(fn, max(3, args.steps // 5), 1, stream)
+        step_ms[name] = float(np.median(per_s) * 1e3)
+    splan.close()
+    del fs, work
+
     mix = res["fx16"]
     T = float(np.mean(mix["per"]))
     value = cells / T
@@ -357,6 +386,7 @@ def main() -> int:
         "launch_ms": {"p5": float(np.percentile(mix["per"], 5) * 1e3),
                       "p50": float(np.median(mix["per"]) * 1e3),
                       "p95": float(np.percentile(mix["per"], 95) * 1e3)},
+        "step_ms": step_ms,
         "p99_latency_ms": None if serve is None else serve["p99_ms"],
         "serving": serve,
     }
