@@ -12,6 +12,10 @@ Contents (each function cites the passage of the paper it follows):
   sigma     -- O4: modelling check, the sigma/omega form of eq. (Boltzmann)
   bkw       -- the BKW closed form of section 4.1 and its time derivative
   stepping  -- explicit Euler and penalised IMEX steps (section 3.4)
+  galerkin  -- the dealiased (non-wrapping) variant of Q_h, 3/2 rule and
+               literal mode sum (section 3.3)
+  transport -- CWENO reconstruction and Rusanov fluxes on polygonal meshes
+               (section 2.2)
 
 Pin status of every function is listed in the module docstrings; a function
 with no independent pin says "parity unpinned" there.
