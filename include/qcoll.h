@@ -201,6 +201,66 @@ void qcoll_plan_destroy(qcoll_plan_t plan);
 /* Static string for an error code. */
 const char* qcoll_strerror(int code);
 
+/* ------------------------------------------------------------------------
+ * Transport on polygonal meshes (section 2.2): the CWENO reconstruction of
+ * the cell values of every discrete velocity (eqs. (CWENO:Popt), (CWENO:P0),
+ * (CWENO:Prec), (eqn.weights) with the Taylor basis of
+ * (eq.Dubiner_phi_spatial)) and the Rusanov fluxes through the cell faces
+ * (eqs. (finite_vol3), (finite_vol5)), on a periodic mesh of polygons.
+ *
+ * Mesh (host arrays, copied by the plan; polygon-major, float64 coordinates):
+ *   cell_ptr[cells+1]   face/vertex slots of cell i: cell_ptr[i] .. cell_ptr[i+1]-1
+ *                       (3 .. 12 faces per cell)
+ *   verts[2 m]          polygon vertices (x, y), counter-clockwise, in the cell's frame
+ *   nbr[m]              the cell across face k (from vertex k to vertex k+1)
+ *   shift[2 m]          offset that maps the neighbour's frame into this cell's frame
+ *   twin[m]             slot of the same face in the neighbour's list
+ *   gen[2 cells]        generator point of each cell (ranks the stencil candidates)
+ * degree: polynomial degree of the reconstruction, 1 (second order) or 2 (third).
+ * Velocities: the n_per_dim^2 nodes v = -L + j 2L/n_per_dim of the collision grid
+ * (2 <= n_per_dim <= 64); f is stored float[cells][n_per_dim][n_per_dim].
+ * Readings of the section's open choices: central stencil = the 2 dim(P_degree) - 1
+ * cells whose generators are nearest (within three face rings, ties by cell
+ * index and image offset); one-sided P1 stencil per face L = {P_i, neighbour
+ * across face L, neighbour across face L+1}; linear weights 1e5 (central) and 1
+ * (each one-sided), normalised; oscillation indicator = sum over derivatives of
+ * order 1..degree of the cell mean of the squared derivative in the scaled Taylor
+ * variables; Rusanov speed |v . n| per velocity.
+ * flags: QCOLL_HOST_ONLY builds the host tables only. */
+typedef struct qcoll_transport_s* qcoll_transport_t;
+int qcoll_transport_plan(qcoll_transport_t* out, int64_t cells, const int64_t* cell_ptr, const double* verts,
+                         const int64_t* nbr, const double* shift, const int64_t* twin, const double* gen,
+                         int degree, int n_per_dim, double L, unsigned flags);
+
+/* Bytes of the work buffer of a transport call: the reconstructed face values,
+ * float[faces][n_per_dim^2]. */
+int64_t qcoll_transport_work_bytes(qcoll_transport_t plan);
+
+/* R = -(1/|P_i|) sum over faces of the Rusanov flux of the reconstructed states
+ * (device float[cells][n^2] in and out, distinct buffers), or, for the step,
+ * out = f + dt R (explicit Euler transport step; out may not alias f). work: device
+ * buffer of at least qcoll_transport_work_bytes() bytes owned by the caller.
+ * Returns QCOLL_EINVAL for NULL pointers or a small work buffer,
+ * QCOLL_EUNSUPPORTED for a host-only plan. */
+int qcoll_transport_rhs(qcoll_transport_t plan, const float* f, float* R, void* work, int64_t work_bytes,
+                        hipStream_t stream);
+int qcoll_transport_step(qcoll_transport_t plan, const float* f, float* out, double dt, void* work,
+                         int64_t work_bytes, hipStream_t stream);
+
+/* Host tables of cell `index` for verification. which:
+ *   0 central stencil: cell indices followed by their image offsets (x then y)
+ *     (out[3 (n_e - 1)])
+ *   1 geometry: area, barycentre x, y, h (out[4])
+ *   2 least-squares operator of the optimal polynomial, [K][n_e - 1] row-major
+ *   3 face averages of the Taylor basis functions, [faces][K]
+ *   4 per face: outward normal x, y, |face| / |P_i|, inverse of the one-sided
+ *     stencil's 2x2 system (row-major), [faces][7]
+ *   5 oscillation form: coefficients of c_a c_b, a <= b, row by row (15 values)
+ * Returns the number of values written or QCOLL_EINVAL. */
+int qcoll_transport_table(qcoll_transport_t plan, int which, int64_t index, double* out, int64_t n);
+
+void qcoll_transport_destroy(qcoll_transport_t plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -271,7 +271,8 @@ class Transport:
 
 def velocity_pairs(N: int, L: float) -> np.ndarray:
     """(N*N, 2) velocities of the flattened grid f[i, a, b] -> (v_a, v_b), with the
-    nodes v = -L + j 2L/N of the collision grid."""
-    v = -L + np.arange(N) * (2.0 * L / N)
+    nodes of the collision grid, v_j = -L + j 2L/N, written as (2j - N) L/N (the
+    same numbers, with the centre node exactly 0)."""
+    v = (2.0 * np.arange(N) - N) * (L / N)
     a, b = np.meshgrid(v, v, indexing="ij")
     return np.stack([a.reshape(-1), b.reshape(-1)], axis=1)

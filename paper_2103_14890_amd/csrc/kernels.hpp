@@ -112,6 +112,39 @@ struct GalerkinArgs {
 int launch_galerkin_interp(const GalerkinArgs& args, hipStream_t stream);
 int launch_galerkin_restrict(const GalerkinArgs& args, hipStream_t stream);
 
+// Transport on polygonal meshes: per-cell and per-face tables (FP32, read with
+// wave-uniform scalar loads) of the CWENO reconstruction and the fluxes.
+constexpr int kTrMaxFaces = 12;
+constexpr int kTrMaxStencil = 11;   // central stencil without the cell itself (degree 2)
+constexpr int kTrMaxK = 5;          // non-constant Taylor basis functions (degree 2)
+struct TrCell {
+  int slot0 = 0, nf = 0, pad0 = 0, pad1 = 0;
+  int stencil[kTrMaxStencil + 1] = {};          // central stencil cells
+  float pinv[kTrMaxK][kTrMaxStencil + 1] = {};  // least-squares operator of the optimal polynomial
+  float S[16] = {};                             // oscillation form, upper triangle row by row
+};
+struct TrFace {
+  int nbr = 0, twin = 0, nbr_next = 0;  // across this face, this face in the neighbour's list, across the next face
+  float nx = 0, ny = 0, coef = 0;       // outward unit normal, |face| / |P_i|
+  float binv[4] = {};                   // one-sided stencil (this face, next face): 2x2 inverse, row-major
+  float phi[kTrMaxK] = {};              // face average of the Taylor basis functions of the cell
+  float pad = 0;
+};
+struct TransportArgs {
+  const TrCell* cells = nullptr;
+  const TrFace* faces = nullptr;
+  const float* f = nullptr;     // [cells][V]
+  float* fv = nullptr;          // [faces][V] reconstructed face averages
+  float* out = nullptr;         // [cells][V]
+  int64_t ncells = 0;
+  int V = 0, N = 0;             // velocities, nodes per axis
+  float vh = 0;                 // v = (2 j - N) vh per axis (vh = L / N, exact at v = 0)
+  int degree = 2;
+  int step = 0;                 // 0: out = R, 1: out = f + dt R
+  float dt = 0;
+};
+int launch_transport(const TransportArgs& args, hipStream_t stream);
+
 // Single-plan launches (args.tile selects the 16x16 or 32x32 kernel family).
 int launch_2d16(const KernelArgs& args, hipStream_t stream);
 int launch_2d32(const KernelArgs& args, hipStream_t stream);

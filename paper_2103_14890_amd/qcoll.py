@@ -84,6 +84,20 @@ def _load() -> ctypes.CDLL:
     lib.qcoll_plan_destroy.restype = None
     lib.qcoll_strerror.argtypes = [c_int]
     lib.qcoll_strerror.restype = ctypes.c_char_p
+    pi64, pdbl = ctypes.POINTER(i64), ctypes.POINTER(dbl)
+    lib.qcoll_transport_plan.argtypes = [ctypes.POINTER(vp), i64, pi64, pdbl, pi64, pdbl, pi64, pdbl, c_int, c_int,
+                                         dbl, ctypes.c_uint]
+    lib.qcoll_transport_plan.restype = c_int
+    lib.qcoll_transport_work_bytes.argtypes = [vp]
+    lib.qcoll_transport_work_bytes.restype = i64
+    lib.qcoll_transport_rhs.argtypes = [vp, vp, vp, vp, i64, vp]
+    lib.qcoll_transport_rhs.restype = c_int
+    lib.qcoll_transport_step.argtypes = [vp, vp, vp, dbl, vp, i64, vp]
+    lib.qcoll_transport_step.restype = c_int
+    lib.qcoll_transport_table.argtypes = [vp, c_int, i64, pdbl, i64]
+    lib.qcoll_transport_table.restype = c_int
+    lib.qcoll_transport_destroy.argtypes = [vp]
+    lib.qcoll_transport_destroy.restype = None
     return lib
 
 
@@ -302,3 +316,74 @@ def step_multi(plans, fs, dt: float, eps: float = 1.0, scheme: str = "explicit",
     _check(LIB.qcoll_step_multi(pl, n, fp, cells, float(dt), float(eps), _SCHEMES[scheme], st,
                                 _stream_ptr(stream)), "qcoll_step_multi")
     return fs
+
+
+class TransportPlan:
+    """CWENO + Rusanov transport on a polygonal mesh (qcoll_transport_*): mesh is
+    any object with the arrays cell_ptr, verts, nbr, shift, twin and gen."""
+
+    def __init__(self, mesh, degree: int, N: int, L: float, host_only: bool = False):
+        import numpy as np
+        self._keep = [np.ascontiguousarray(a, dtype=t) for a, t in (
+            (mesh.cell_ptr, np.int64), (mesh.verts, np.float64), (mesh.nbr, np.int64),
+            (mesh.shift, np.float64), (mesh.twin, np.int64), (mesh.gen, np.float64))]
+        cp, vt, nb, sh, tw, gn = self._keep
+        P64, PD = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
+        h = ctypes.c_void_p()
+        _check(LIB.qcoll_transport_plan(ctypes.byref(h), len(gn), cp.ctypes.data_as(P64), vt.ctypes.data_as(PD),
+                                        nb.ctypes.data_as(P64), sh.ctypes.data_as(PD), tw.ctypes.data_as(P64),
+                                        gn.ctypes.data_as(PD), int(degree), int(N), float(L),
+                                        HOST_ONLY if host_only else 0), "qcoll_transport_plan")
+        self._h = h
+        self.cells, self.degree, self.N, self.L = len(gn), degree, N, float(L)
+
+    def work_bytes(self) -> int:
+        return _check(int(LIB.qcoll_transport_work_bytes(self._h)), "qcoll_transport_work_bytes")
+
+    def _work(self, work, like):
+        import torch
+        if work is None:
+            work = torch.empty(max(self.work_bytes() // 4, 1), dtype=torch.float32, device=like.device)
+        return work
+
+    def rhs(self, f, R=None, work=None, stream=None):
+        """R = -(1/|P_i|) sum of the face fluxes, f and R float32 [cells, N, N]."""
+        import torch
+        if R is None:
+            R = torch.empty_like(f)
+        work = self._work(work, f)
+        _check(LIB.qcoll_transport_rhs(self._h, _dev_ptr(f, torch.float32, "f"), _dev_ptr(R, torch.float32, "R"),
+                                       _dev_ptr(work, work.dtype, "work"), work.numel() * work.element_size(),
+                                       _stream_ptr(stream)), "qcoll_transport_rhs")
+        return R
+
+    def step(self, f, dt: float, out=None, work=None, stream=None):
+        """out = f + dt R(f) (explicit Euler transport step)."""
+        import torch
+        if out is None:
+            out = torch.empty_like(f)
+        work = self._work(work, f)
+        _check(LIB.qcoll_transport_step(self._h, _dev_ptr(f, torch.float32, "f"), _dev_ptr(out, torch.float32, "out"),
+                                        float(dt), _dev_ptr(work, work.dtype, "work"),
+                                        work.numel() * work.element_size(), _stream_ptr(stream)),
+               "qcoll_transport_step")
+        return out
+
+    def table(self, which: int, cell: int, size: int = 256):
+        import numpy as np
+        out = np.zeros(size, dtype=np.float64)
+        cnt = _check(LIB.qcoll_transport_table(self._h, which, int(cell),
+                                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), size),
+                     "qcoll_transport_table")
+        return out[:cnt].copy()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            LIB.qcoll_transport_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
