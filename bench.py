@@ -69,7 +69,16 @@ def mfma_flops_per_cell_3d(T: int, transforms: int) -> float:
 
 
 # Source file of the dominant kernel of each workload.
-KERNEL_SOURCE = {"hs2d_32": "kernels_2d.hip", "hs2d_64_noisy": "kernels_2d64.hip", "hs3d": "kernels_3d.hip"}
+KERNEL_SOURCE = {"hs2d_32": "kernels_2d.hip", "hs2d_64_noisy": "kernels_2d64.hip", "hs3d": "kernels_3d.hip",
+                 "explosion_16k": "kernels_transport.hip"}
+
+# Transport workloads (CWENO reconstruction + Rusanov fluxes on a polygonal mesh).
+WORKLOADS_TRANSPORT = {
+    "explosion_16k": "16384-polygon periodic centroid-dual mesh of the unit square (jittered 128 x 128 "
+                     "generators, Morton order), 32x32 velocities on [-10,10]^2, third-order CWENO "
+                     "(degree 2), explicit Euler transport step, circular explosion data",
+}
+HBM_PEAK = 8.0e12
 
 
 def kernel_source_hash(workload: str) -> str:
@@ -274,13 +283,86 @@ def bench_3d(args) -> int:
     return 0
 
 
+def transport_run(name: str, steps: int, warmup: int, stream):
+    """Time the transport step (reconstruction + flux kernels) on a workload;
+    returns the plan, inputs and per-step durations."""
+    import torch
+    from workloads import mesh as wm
+    from paper_2103_14890_amd import qcoll
+    mesh, f64, N, L = wm.transport_case(name)
+    f = torch.tensor(f64, dtype=torch.float32, device="cuda:0")
+    plan = qcoll.TransportPlan(mesh, 2, N, L)
+    out = torch.empty_like(f)
+    work = torch.empty(plan.work_bytes() // 4, dtype=torch.float32, device="cuda:0")
+    dt = 0.4 / 128 / (math.sqrt(2.0) * L)
+    _, per = time_launches(lambda: plan.step(f, dt, out=out, work=work), steps, warmup, stream)
+    return mesh, f64, N, L, plan, f, out, dt, per
+
+
+def bench_transport(args) -> int:
+    import torch
+    from oracle import transport as tr
+    stream = torch.cuda.current_stream()
+    mesh, f64, N, L, plan, f, out, dt, per = transport_run(args.workload, args.steps, args.warmup, stream)
+    copy_calibration(args.calibrate_copy, torch.device("cuda:0"))
+    T_ = float(np.mean(per))
+    V = N * N
+    units = mesh.n * V
+    alg_bytes = 8.0 * units            # f read once, the updated f written once
+    # the oracle on a bounded sample of cells (its tables built lazily for them)
+    T = tr.Transport(mesh, 2)
+    vel = tr.velocity_pairs(N, L)
+    f32 = f64.reshape(mesh.n, V).astype(np.float32).astype(np.float64)
+    og = out.cpu().double().numpy().reshape(mesh.n, V)
+    rng = np.random.default_rng(11)
+    order = rng.permutation(mesh.n)
+    done, t_cpu, errs = 0, 0.0, []
+    while t_cpu < args.cpu_seconds and done < mesh.n:
+        c = order[done:done + 8]
+        t0 = time.perf_counter()
+        ref = T.step(f32, vel, dt, c)
+        t_cpu += time.perf_counter() - t0
+        errs.append(np.abs(og[c] - ref).max(axis=0))
+        done += len(c)
+    scale = np.maximum(np.abs(f32).max(axis=0), 1e-30)
+    err = float((np.max(errs, axis=0) / scale).max())
+    out_line = {
+        "metric": "transport updates/s (cell x velocity), CWENO-3 + Rusanov on a polygonal mesh",
+        "value": units / T_,
+        "unit": "cell-velocity updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": T_ * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS_TRANSPORT[args.workload]}", "cells": mesh.n,
+                   "faces": int(len(mesh.nbr)), "N_v": f"{N}x{N}", "degree": 2},
+        "roofline": {"bound": "hbm", "achieved": alg_bytes / T_ / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": alg_bytes / T_ / HBM_PEAK, "traffic": measured_traffic(args.workload)},
+        "cpu_baseline": {"value": done * V / t_cpu, "unit": "cell-velocity updates/s", "cores": 1, "kind": "oracle",
+                         "sample": f"{done} random cells x {V} velocities, FP64 numpy oracle step, {t_cpu:.1f} s"},
+        "max_err_scaled": err,
+        "launch_ms": {"p5": float(np.percentile(per, 5) * 1e3), "p50": float(np.median(per) * 1e3),
+                      "p95": float(np.percentile(per, 95) * 1e3)},
+        "p99_latency_ms": None,
+    }
+    print(json.dumps(out_line))
+    plan.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", default="hs2d_32", choices=sorted(WORKLOADS) + sorted(WORKLOADS_3D))
+    ap.add_argument("--workload", default="hs2d_32",
+                    choices=sorted(WORKLOADS) + sorted(WORKLOADS_3D) + sorted(WORKLOADS_TRANSPORT))
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the open-loop serving run (Poisson arrivals at 200 requests/s) "
                          "behind p99_latency_ms; 0 skips it")
@@ -300,6 +382,8 @@ def main() -> int:
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload in WORKLOADS_3D:
         return bench_3d(args)
+    if args.workload in WORKLOADS_TRANSPORT:
+        return bench_transport(args)
     dev = torch.device("cuda:0")
     NN, LL, KERN, MM, DESC = WORKLOADS[args.workload]
     f64 = wl.config_inputs(args.workload)
@@ -344,6 +428,14 @@ def main() -> int:
     splan.close()
     del fs, work
 
+    # the transport step of the explosion_16k mesh (the second HBM-bound path)
+    mesh_t, _, Nt, _, tplan, _, _, _, per_t = transport_run("explosion_16k", max(5, args.steps // 5), 2, stream)
+    Tt = float(np.mean(per_t))
+    transport = {"workload": "explosion_16k", "ms_per_step": Tt * 1e3,
+                 "value": mesh_t.n * Nt * Nt / Tt, "unit": "cell-velocity updates/s",
+                 "hbm_frac": 8.0 * mesh_t.n * Nt * Nt / Tt / HBM_PEAK}
+    tplan.close()
+
     mix = res["fx16"]
     T = float(np.mean(mix["per"]))
     value = cells / T
@@ -387,6 +479,7 @@ def main() -> int:
                       "p50": float(np.median(mix["per"]) * 1e3),
                       "p95": float(np.percentile(mix["per"], 95) * 1e3)},
         "step_ms": step_ms,
+        "transport": transport,
         "p99_latency_ms": None if serve is None else serve["p99_ms"],
         "serving": serve,
     }
