@@ -7,10 +7,10 @@
 //  2. fluxes: the Rusanov flux of every face (linear in the two face states,
 //     so the face integral needs only the face averages) and the update of
 //     eq. (finite_vol5).
-// One workgroup = 256 consecutive velocities of one cell (four wavefronts); the
-// cell and face tables are wave-uniform and come through scalar loads. Blocks
-// are dealt to the XCDs in contiguous ranges of cells, so that neighbouring
-// cells (numbered along a space-filling curve) share an XCD's L2.
+// One workgroup = 256 (flux: 1024) consecutive velocities of one cell (four
+// wavefronts); the cell tables are wave-uniform and come through scalar
+// loads. Blocks are dealt to the XCDs in contiguous ranges of cells, so that
+// neighbouring cells (numbered along a space-filling curve) share an XCD's L2.
 
 #include <hip/hip_runtime.h>
 
@@ -27,18 +27,21 @@ constexpr float kLamCentral = 1e5f;
 
 struct Block {
   int64_t cell;
-  int v;
+  int v;       // first velocity of this thread (then v + 256, v + 512, ...)
   bool valid;
 };
 
+// Workgroups are dealt to the XCDs round-robin by the hardware; logical block
+// b % 8 * (grid / 8) + b / 8 gives each XCD a contiguous range of cells.
+template <int VPT>
 __device__ inline Block map_block(int64_t ncells, int V) {
-  const int chunks = (V + 255) / 256;
+  const int chunks = (V + 256 * VPT - 1) / (256 * VPT);
   const int64_t per_xcd = gridDim.x / kXcds;
   const int64_t b = blockIdx.x;
   const int64_t logical = (b % kXcds) * per_xcd + b / kXcds;
   Block r;
   r.cell = logical / chunks;
-  r.v = static_cast<int>(logical - r.cell * chunks) * 256 + static_cast<int>(threadIdx.x);
+  r.v = static_cast<int>(logical - r.cell * chunks) * 256 * VPT + static_cast<int>(threadIdx.x);
   r.valid = r.cell < ncells;
   return r;
 }
@@ -48,54 +51,63 @@ __device__ inline float pow4(float x) {
   return x2 * x2;
 }
 
-template <int DEG>
-__global__ __launch_bounds__(256) void transport_recon_kernel(TransportArgs a) {
+__device__ inline float min2(float a, float b) { return a < b ? a : b; }
+
+// Element at a 32-bit byte offset from a wave-uniform row base: the address is
+// formed as scalar base + 32-bit vector offset.
+__device__ inline const float& at(const float* base, unsigned byte_off) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+__device__ inline float& at(float* base, unsigned byte_off) {
+  return *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + byte_off);
+}
+
+// The face count of a cell is a template parameter (the kernels branch once on
+// it): every loop below is then fully unrolled and free of branches, so the
+// scalar loads of the cell's tables are issued together, not one per face.
+template <int DEG, int NF>
+__device__ __forceinline__ void recon_cell(const float* __restrict__ f, const TrCell* __restrict__ cells,
+                                           float* __restrict__ fv, int V, const Block& blk) {
   constexpr int K = DEG == 2 ? 5 : 2;
   constexpr int NS = DEG == 2 ? 11 : 5;
-  const Block blk = map_block(a.ncells, a.V);
-  if (!blk.valid) return;
-  const int V = a.V;
-  const int vv = blk.v < V ? blk.v : V - 1;
-  const TrCell& C = a.cells[blk.cell];
-  const int nf = C.nf;
-  const TrFace* F = a.faces + C.slot0;
-  const float* f = a.f;
-  const float fi = f[blk.cell * V + vv];
+  const unsigned vb = 4u * static_cast<unsigned>(blk.v < V ? blk.v : V - 1);  // byte offset in a row
+  const TrCell& C = cells[blk.cell];
+  const float fi = at(f + blk.cell * V, vb);
 
-  // optimal polynomial (least squares over the central stencil)
-  float d[NS];
+  // all loads of the cell's data at once: the central stencil and the face neighbours
+  float d[NS], dn[NF];
 #pragma unroll
-  for (int j = 0; j < NS; ++j) d[j] = f[static_cast<int64_t>(C.stencil[j]) * V + vv] - fi;
+  for (int j = 0; j < NS; ++j) d[j] = at(f + static_cast<int64_t>(C.stencil[j]) * V, vb);
+#pragma unroll
+  for (int L = 0; L < NF; ++L) dn[L] = at(f + static_cast<int64_t>(C.nbr[L]) * V, vb);
+  // optimal polynomial (least squares over the central stencil)
   float copt[K];
 #pragma unroll
-  for (int l = 0; l < K; ++l) {
-    float s = 0.0f;
+  for (int l = 0; l < K; ++l) copt[l] = 0.0f;
 #pragma unroll
-    for (int j = 0; j < NS; ++j) s += C.pinv[l][j] * d[j];
-    copt[l] = s;
+  for (int j = 0; j < NS; ++j) {
+    const float e = d[j] - fi;
+#pragma unroll
+    for (int l = 0; l < K; ++l) copt[l] += C.pinv[l][j] * e;
   }
   // one-sided P1 polynomials
-  float dn[kTrMaxFaces];
 #pragma unroll
-  for (int L = 0; L < kTrMaxFaces; ++L)
-    if (L < nf) dn[L] = f[static_cast<int64_t>(F[L].nbr) * V + vv] - fi;
-  float c1[kTrMaxFaces], c2[kTrMaxFaces], sig[kTrMaxFaces];
+  for (int L = 0; L < NF; ++L) dn[L] -= fi;
+  float c1[NF], c2[NF], sig[NF];
   float sum1 = 0.0f, sum2 = 0.0f;
 #pragma unroll
-  for (int L = 0; L < kTrMaxFaces; ++L) {
-    if (L < nf) {
-      const float e0 = dn[L], e1 = (L + 1 == nf) ? dn[0] : dn[(L + 1) % kTrMaxFaces];
-      c1[L] = F[L].binv[0] * e0 + F[L].binv[1] * e1;
-      c2[L] = F[L].binv[2] * e0 + F[L].binv[3] * e1;
-      sig[L] = c1[L] * c1[L] + c2[L] * c2[L];
-      sum1 += c1[L];
-      sum2 += c2[L];
-    }
+  for (int L = 0; L < NF; ++L) {
+    const float e0 = dn[L], e1 = dn[(L + 1) % NF];
+    c1[L] = C.binv[L][0] * e0 + C.binv[L][1] * e1;
+    c2[L] = C.binv[L][2] * e0 + C.binv[L][3] * e1;
+    sig[L] = c1[L] * c1[L] + c2[L] * c2[L];
+    sum1 += c1[L];
+    sum2 += c2[L];
   }
   // central polynomial of eq. (CWENO:P0) and its oscillation indicator
-  const float lamL = 1.0f / (kLamCentral + static_cast<float>(nf));
-  const float lam0 = kLamCentral * lamL;
-  const float inv0 = 1.0f / lam0;
+  constexpr float lamL = 1.0f / (kLamCentral + NF);
+  constexpr float lam0 = kLamCentral * lamL;
+  constexpr float inv0 = 1.0f / lam0;
   float c0[K];
 #pragma unroll
   for (int l = 0; l < K; ++l) c0[l] = copt[l] * inv0;
@@ -112,80 +124,135 @@ __global__ __launch_bounds__(256) void transport_recon_kernel(TransportArgs a) {
   }
   // nonlinear weights lam_s / (sigma_s + eps)^4, normalised; evaluated as
   // lam_s ((sigma_min + eps) / (sigma_s + eps))^4, which has the same ratios
+  // (reciprocals to 1 ulp: the weights only enter through their ratios)
   float smin = sig0;
 #pragma unroll
-  for (int L = 0; L < kTrMaxFaces; ++L)
-    if (L < nf) smin = fminf(smin, sig[L]);
+  for (int L = 0; L < NF; ++L) smin = min2(smin, sig[L]);
   smin += kEpsW;
-  const float w0 = lam0 * pow4(smin / (sig0 + kEpsW));
+  const float w0 = lam0 * pow4(smin * __builtin_amdgcn_rcpf(sig0 + kEpsW));
   float wsum = w0;
   float cw[K];
 #pragma unroll
   for (int l = 0; l < K; ++l) cw[l] = w0 * c0[l];
 #pragma unroll
-  for (int L = 0; L < kTrMaxFaces; ++L) {
-    if (L < nf) {
-      const float w = lamL * pow4(smin / (sig[L] + kEpsW));
-      wsum += w;
-      cw[0] += w * c1[L];
-      cw[1] += w * c2[L];
-    }
+  for (int L = 0; L < NF; ++L) {
+    const float w = lamL * pow4(smin * __builtin_amdgcn_rcpf(sig[L] + kEpsW));
+    wsum += w;
+    cw[0] += w * c1[L];
+    cw[1] += w * c2[L];
   }
   const float inv = 1.0f / wsum;
-  // face averages of the reconstruction
+#pragma unroll
+  for (int l = 0; l < K; ++l) cw[l] *= inv;
+  // face averages of the reconstruction (all computed before the first store)
+  float u[NF];
+#pragma unroll
+  for (int L = 0; L < NF; ++L) {
+    u[L] = fi;
+#pragma unroll
+    for (int l = 0; l < K; ++l) u[L] += cw[l] * C.phi[L][l];
+  }
   if (blk.v < V) {
 #pragma unroll
-    for (int L = 0; L < kTrMaxFaces; ++L) {
-      if (L < nf) {
-        float u = 0.0f;
-#pragma unroll
-        for (int l = 0; l < K; ++l) u += cw[l] * F[L].phi[l];
-        a.fv[static_cast<int64_t>(C.slot0 + L) * V + vv] = fi + u * inv;
-      }
-    }
+    for (int L = 0; L < NF; ++L) at(fv + static_cast<int64_t>(C.slot0 + L) * V, vb) = u[L];
   }
 }
 
-__global__ __launch_bounds__(256) void transport_flux_kernel(TransportArgs a) {
-  const Block blk = map_block(a.ncells, a.V);
-  if (!blk.valid) return;
+template <int VPT, int NF>
+__device__ __forceinline__ void flux_cell(const float* __restrict__ f, const TrFlux* __restrict__ flux,
+                                          const float* __restrict__ fv, float* __restrict__ out,
+                                          const TransportArgs& a, const Block& blk) {
   const int V = a.V;
-  const int vv = blk.v < V ? blk.v : V - 1;
-  const TrCell& C = a.cells[blk.cell];
-  const int nf = C.nf;
-  const TrFace* F = a.faces + C.slot0;
-  const float vx = static_cast<float>(2 * (vv / a.N) - a.N) * a.vh;
-  const float vy = static_cast<float>(2 * (vv % a.N) - a.N) * a.vh;
-  float acc = 0.0f;
+  const TrFlux& X = flux[blk.cell];
+  unsigned vb[VPT];
+  float vx[VPT], vy[VPT], acc[VPT];
 #pragma unroll
-  for (int L = 0; L < kTrMaxFaces; ++L) {
-    if (L < nf) {
-      const float vn = vx * F[L].nx + vy * F[L].ny;
+  for (int r = 0; r < VPT; ++r) {
+    const int v = blk.v + 256 * r;
+    const int w = v < V ? v : V - 1;
+    vb[r] = 4u * static_cast<unsigned>(w);
+    vx[r] = static_cast<float>(2 * (w / a.N) - a.N) * a.vh;
+    vy[r] = static_cast<float>(2 * (w % a.N) - a.N) * a.vh;
+    acc[r] = 0.0f;
+  }
+#pragma unroll
+  for (int L = 0; L < NF; ++L) {
+    const float* own = fv + static_cast<int64_t>(X.slot0 + L) * V;
+    const float* other = fv + static_cast<int64_t>(X.twin[L]) * V;
+#pragma unroll
+    for (int r = 0; r < VPT; ++r) {
+      const float vn = vx[r] * X.nx[L] + vy[r] * X.ny[L];
       // Rusanov with speed |v.n| is the upwind state
-      const int64_t row = vn > 0.0f ? static_cast<int64_t>(C.slot0 + L) : static_cast<int64_t>(F[L].twin);
-      acc += F[L].coef * vn * a.fv[row * V + vv];
+      acc[r] += X.coef[L] * vn * (vn > 0.0f ? at(own, vb[r]) : at(other, vb[r]));
     }
   }
-  if (blk.v < V) {
-    const int64_t o = blk.cell * V + vv;
-    a.out[o] = a.step ? a.f[o] - a.dt * acc : -acc;
+  const float* fc = f + blk.cell * V;
+  float* oc = out + blk.cell * V;
+#pragma unroll
+  for (int r = 0; r < VPT; ++r)
+    if (blk.v + 256 * r < V) at(oc, vb[r]) = a.step ? at(fc, vb[r]) - a.dt * acc[r] : -acc[r];
+}
+
+#define QCOLL_TR_SWITCH(NFV, CALL) \
+  switch (NFV) {                   \
+    case 3: CALL(3); break;        \
+    case 4: CALL(4); break;        \
+    case 5: CALL(5); break;        \
+    case 6: CALL(6); break;        \
+    case 7: CALL(7); break;        \
+    case 8: CALL(8); break;        \
+    case 9: CALL(9); break;        \
+    case 10: CALL(10); break;      \
+    case 11: CALL(11); break;      \
+    default: CALL(12); break;      \
   }
+
+template <int DEG>
+__global__ __launch_bounds__(256) void transport_recon_kernel(const float* __restrict__ f,
+                                                              const TrCell* __restrict__ cells,
+                                                              float* __restrict__ fv, int64_t ncells, int V) {
+  const Block blk = map_block<1>(ncells, V);
+  if (!blk.valid) return;
+#define QCOLL_RECON(n) recon_cell<DEG, n>(f, cells, fv, V, blk)
+  QCOLL_TR_SWITCH(cells[blk.cell].nf, QCOLL_RECON)
+#undef QCOLL_RECON
+}
+
+template <int VPT>
+__global__ __launch_bounds__(256) void transport_flux_kernel(const float* __restrict__ f,
+                                                             const TrFlux* __restrict__ flux,
+                                                             const float* __restrict__ fv, float* __restrict__ out,
+                                                             TransportArgs a) {
+  const Block blk = map_block<VPT>(a.ncells, a.V);
+  if (!blk.valid) return;
+#define QCOLL_FLUX(n) flux_cell<VPT, n>(f, flux, fv, out, a, blk)
+  QCOLL_TR_SWITCH(flux[blk.cell].nf, QCOLL_FLUX)
+#undef QCOLL_FLUX
 }
 
 }  // namespace
 
 int launch_transport(const TransportArgs& args, hipStream_t stream) {
   if (args.ncells <= 0) return 0;
-  const int chunks = (args.V + 255) / 256;
-  const int64_t blocks = args.ncells * chunks;
-  const int64_t grid = (blocks + kXcds - 1) / kXcds * kXcds;
-  if (grid > 0x7fffffff) return -1;
+  auto grid_of = [&](int vpt) {
+    const int64_t chunks = (args.V + 256 * vpt - 1) / (256 * vpt);
+    return (args.ncells * chunks + kXcds - 1) / kXcds * kXcds;
+  };
+  const int64_t g1 = grid_of(1);
+  if (g1 > 0x7fffffff) return -1;
   if (args.degree == 2)
-    hipLaunchKernelGGL(transport_recon_kernel<2>, dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream, args);
+    hipLaunchKernelGGL(transport_recon_kernel<2>, dim3(static_cast<unsigned>(g1)), dim3(256), 0, stream, args.f,
+                       args.cells, args.fv, args.ncells, args.V);
   else
-    hipLaunchKernelGGL(transport_recon_kernel<1>, dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream, args);
+    hipLaunchKernelGGL(transport_recon_kernel<1>, dim3(static_cast<unsigned>(g1)), dim3(256), 0, stream, args.f,
+                       args.cells, args.fv, args.ncells, args.V);
   if (hipGetLastError() != hipSuccess) return -3;
-  hipLaunchKernelGGL(transport_flux_kernel, dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream, args);
+  if (args.V >= 1024)
+    hipLaunchKernelGGL(transport_flux_kernel<4>, dim3(static_cast<unsigned>(grid_of(4))), dim3(256), 0, stream,
+                       args.f, args.flux, args.fv, args.out, args);
+  else
+    hipLaunchKernelGGL(transport_flux_kernel<1>, dim3(static_cast<unsigned>(g1)), dim3(256), 0, stream, args.f,
+                       args.flux, args.fv, args.out, args);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

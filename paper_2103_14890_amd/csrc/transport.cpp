@@ -43,7 +43,7 @@ struct qcoll_transport_s {
   bool on_device = false;
   int device = 0;
   qcoll::TrCell* d_cells = nullptr;
-  qcoll::TrFace* d_faces = nullptr;
+  qcoll::TrFlux* d_flux = nullptr;
 };
 
 namespace {
@@ -88,6 +88,10 @@ Poly polygon(const qcoll_transport_s& t, int64_t c, double sx, double sy) {
   Poly P;
   for (int64_t k = t.cell_ptr[c]; k < t.cell_ptr[c + 1]; ++k) P.emplace_back(t.verts[2 * k] + sx, t.verts[2 * k + 1] + sy);
   return P;
+}
+
+int64_t owner_of(const qcoll_transport_s& t, int64_t slot) {
+  return std::upper_bound(t.cell_ptr.begin(), t.cell_ptr.end(), slot) - t.cell_ptr.begin() - 1;
 }
 
 double ipow(double x, int p) {
@@ -297,6 +301,17 @@ int build_tables(qcoll_transport_s& t) {
       t.binv[k * 4 + 3] = b0[0] / det;
     }
   }
+  // the two sides of a face share its length and have exactly opposite normals
+  // (the flux kernels decide in/outflow by the sign of v.n on each side)
+  for (int64_t k = 0; k < t.nslots; ++k) {
+    const int64_t tw = t.twin[k];
+    if (tw <= k) continue;
+    const int64_t j = t.nbr[k];
+    const double len = t.fcoef[k] * t.area[owner_of(t, k)];
+    t.fnx[tw] = -t.fnx[k];
+    t.fny[tw] = -t.fny[k];
+    t.fcoef[tw] = len / t.area[j];
+  }
   return QCOLL_OK;
 }
 
@@ -304,33 +319,31 @@ int upload_tables(qcoll_transport_s& t) {
   const int64_t n = t.ncells;
   const int K = t.K, ns = t.ne - 1;
   std::vector<qcoll::TrCell> cells(n);
-  std::vector<qcoll::TrFace> faces(t.nslots);
+  std::vector<qcoll::TrFlux> flux(n);
   for (int64_t i = 0; i < n; ++i) {
     qcoll::TrCell& c = cells[i];
-    c.slot0 = static_cast<int>(t.cell_ptr[i]);
-    c.nf = static_cast<int>(t.cell_ptr[i + 1] - t.cell_ptr[i]);
+    qcoll::TrFlux& x = flux[i];
+    c.slot0 = x.slot0 = static_cast<int>(t.cell_ptr[i]);
+    c.nf = x.nf = static_cast<int>(t.cell_ptr[i + 1] - t.cell_ptr[i]);
     for (int s = 0; s < ns; ++s) c.stencil[s] = static_cast<int>(t.st_cell[i * ns + s]);
     for (int a = 0; a < K; ++a)
       for (int s = 0; s < ns; ++s) c.pinv[a][s] = static_cast<float>(t.pinv[(i * K + a) * ns + s]);
     for (int e = 0; e < 15; ++e) c.S[e] = static_cast<float>(t.S[i * 15 + e]);
-    const int64_t s0 = t.cell_ptr[i], nf = c.nf;
-    for (int64_t L = 0; L < nf; ++L) {
-      const int64_t k = s0 + L, k1 = s0 + (L + 1) % nf;
-      qcoll::TrFace& f = faces[k];
-      f.nbr = static_cast<int>(t.nbr[k]);
-      f.twin = static_cast<int>(t.twin[k]);
-      f.nbr_next = static_cast<int>(t.nbr[k1]);
-      f.nx = static_cast<float>(t.fnx[k]);
-      f.ny = static_cast<float>(t.fny[k]);
-      f.coef = static_cast<float>(t.fcoef[k]);
-      for (int e = 0; e < 4; ++e) f.binv[e] = static_cast<float>(t.binv[k * 4 + e]);
-      for (int l = 0; l < K; ++l) f.phi[l] = static_cast<float>(t.face_phi[k * K + l]);
+    for (int L = 0; L < c.nf; ++L) {
+      const int64_t k = c.slot0 + L;
+      c.nbr[L] = static_cast<int>(t.nbr[k]);
+      for (int e = 0; e < 4; ++e) c.binv[L][e] = static_cast<float>(t.binv[k * 4 + e]);
+      for (int l = 0; l < K; ++l) c.phi[L][l] = static_cast<float>(t.face_phi[k * K + l]);
+      x.twin[L] = static_cast<int>(t.twin[k]);
+      x.nx[L] = static_cast<float>(t.fnx[k]);
+      x.ny[L] = static_cast<float>(t.fny[k]);
+      x.coef[L] = static_cast<float>(t.fcoef[k]);
     }
   }
   if (hipMalloc(&t.d_cells, sizeof(qcoll::TrCell) * n) != hipSuccess) return QCOLL_ENOMEM;
-  if (hipMalloc(&t.d_faces, sizeof(qcoll::TrFace) * t.nslots) != hipSuccess) return QCOLL_ENOMEM;
+  if (hipMalloc(&t.d_flux, sizeof(qcoll::TrFlux) * n) != hipSuccess) return QCOLL_ENOMEM;
   if (hipMemcpy(t.d_cells, cells.data(), sizeof(qcoll::TrCell) * n, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(t.d_faces, faces.data(), sizeof(qcoll::TrFace) * t.nslots, hipMemcpyHostToDevice) != hipSuccess)
+      hipMemcpy(t.d_flux, flux.data(), sizeof(qcoll::TrFlux) * n, hipMemcpyHostToDevice) != hipSuccess)
     return QCOLL_EDEVICE;
   return QCOLL_OK;
 }
@@ -341,7 +354,7 @@ void release(qcoll_transport_s* t) {
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(t->device);
     (void)hipFree(t->d_cells);
-    (void)hipFree(t->d_faces);
+    (void)hipFree(t->d_flux);
     (void)hipSetDevice(cur);
   }
   delete t;
@@ -429,7 +442,7 @@ static int transport_call(qcoll_transport_t t, const float* f, float* out, int s
     return QCOLL_EINVAL;
   qcoll::TransportArgs a;
   a.cells = t->d_cells;
-  a.faces = t->d_faces;
+  a.flux = t->d_flux;
   a.f = f;
   a.fv = static_cast<float*>(work);
   a.out = out;
