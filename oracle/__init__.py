@@ -16,6 +16,8 @@ Contents (each function cites the passage of the paper it follows):
                literal mode sum (section 3.3)
   transport -- CWENO reconstruction and Rusanov fluxes on polygonal meshes
                (section 2.2)
+  classical -- the classical O(N^4) method: direct double sum with exact
+               kernel modes (section 3.3)
 
 Pin status of every function is listed in the module docstrings; a function
 with no independent pin says "parity unpinned" there.

@@ -26,7 +26,7 @@ import math
 
 import numpy as np
 
-from .spectral import Setup, active_mask, directions, forward_dft, mode_indices
+from .spectral import Setup, active_mask, directions, forward_dft, mode_indices, vhs_weight
 
 
 def _interpolant(f: np.ndarray, s: Setup):
@@ -89,7 +89,8 @@ def q_brute(f: np.ndarray, s: Setup, n_line: int | None = None, n_r: int | None 
             x, w = np.polynomial.legendre.leggauss(s.n_rho)
             rho = np.concatenate([-0.5 * R * (x + 1.0), 0.5 * R * (x + 1.0)])
             wr = np.concatenate([0.5 * R * w, 0.5 * R * w])
-            Bt = lambda r1, r2: 2.0 * b * np.sqrt(r1 ** 2 + r2 ** 2)  # noqa: E731
+            g = 1.0 if s.kernel == "hard_sphere" else s.gamma
+            Bt = lambda r1, r2: 2.0 * b * vhs_weight(r1, r2, g)  # noqa: E731
         R1, R2 = np.meshgrid(rho, rho, indexing="ij")
         W2 = np.outer(wr, wr) * Bt(R1, R2)                  # (q, q)
         for p in range(len(dw)):

@@ -50,8 +50,9 @@ def _sphere_rule(d: int, n: int):
 
 
 def q_sigma(fun, targets: np.ndarray, kernel: str, b: float, box: float,
-            n_star: int, n_omega: int) -> np.ndarray:
-    """Q(f) at the target velocities (T, d) by nested quadrature."""
+            n_star: int, n_omega: int, gamma: float = 1.0) -> np.ndarray:
+    """Q(f) at the target velocities (T, d) by nested quadrature; kernel
+    "maxwell" (B = b), "hard_sphere" (B = b|q|) or "vhs" (B = b|q|^gamma)."""
     targets = np.asarray(targets, dtype=np.float64)
     d = targets.shape[1]
     h = 2.0 * box / n_star
@@ -64,7 +65,12 @@ def q_sigma(fun, targets: np.ndarray, kernel: str, b: float, box: float,
     for i, v in enumerate(targets):
         q = v[None, :] - vs
         qn = np.linalg.norm(q, axis=1)
-        B = b * np.ones_like(qn) if kernel == "maxwell" else b * qn
+        if kernel == "maxwell":
+            B = b * np.ones_like(qn)
+        elif kernel == "hard_sphere":
+            B = b * qn
+        else:
+            B = b * np.where(qn > 0, qn, 1.0) ** gamma * (qn > 0)
         c = 0.5 * (v[None, :] + vs)
         gain = 0.0
         for o, w in zip(om, wo):

@@ -28,6 +28,8 @@ reasoning in the project's design notes):
       2D hard spheres (B=b|q|): B~ = 2 b sqrt(rho^2+rho'^2) (not separable:
         expanded in K_r products of even radial functions, see
         hs2d_radial_expansion)
+      2D variable hard spheres (B = b|q|^gamma): B~ = 2 b (rho^2+rho'^2)^(gamma/2),
+        the same expansion
       3D hard spheres:          B~ = 4 b           (separable)
   * default b = 1/|S^(d-1)| (1/(2 pi) in 2D, fixed by the BKW closed form);
   * the loss term uses the same direction quadrature as the gain.
@@ -66,7 +68,7 @@ class Setup:
     d: int
     N: int
     L: float
-    kernel: str = "maxwell"          # "maxwell" | "hard_sphere"
+    kernel: str = "maxwell"          # "maxwell" | "hard_sphere" | "vhs" (B = b |q|^gamma, 2D)
     M: int = 8                       # number of collision directions (the paper's A)
     b: float | None = None           # kernel constant b_0 or b_1
     K_r: int | None = None           # HS-2D radial rank; None -> smallest with ratio < tol
@@ -74,6 +76,7 @@ class Setup:
     r_literal: bool = False
     n_rho: int = 32                  # HS-2D: Gauss-Legendre nodes on [0, R]
     kr_tol: float = 1e-4             # HS-2D: eigenvalue ratio cut for the auto K_r
+    gamma: float = 1.0               # VHS exponent (kernel "vhs"), -1 <= gamma <= 1
 
     @property
     def radius(self) -> float:
@@ -157,8 +160,19 @@ def psi_disc(t, R: float) -> np.ndarray:
     return out
 
 
+def vhs_weight(r1, r2, gamma: float):
+    """(rho^2 + rho'^2)^(gamma/2): the radial part of the 2D Carleman kernel of
+    B = b |q|^gamma (|z|^2 = rho^2 + rho'^2); the square root for gamma = 1."""
+    r2s = r1 ** 2 + r2 ** 2
+    if gamma == 1.0:
+        return np.sqrt(r2s)
+    if gamma == 0.0:
+        return np.ones_like(r2s)
+    return r2s ** (0.5 * gamma)
+
+
 def hs2d_radial_expansion(R: float, n_rho: int = 32, K_r: int | None = None,
-                          tol: float = 1e-4):
+                          tol: float = 1e-4, gamma: float = 1.0):
     """Separable expansion of the 2D hard-sphere Carleman weight.
 
     The gain needs int int_{[-R,R]^2} sqrt(rho^2 + rho'^2) F(rho) G(rho'). The
@@ -173,12 +187,15 @@ def hs2d_radial_expansion(R: float, n_rho: int = 32, K_r: int | None = None,
     Pairs are sorted by |lam| descending; K_r = None keeps the smallest count
     with |lam_{K_r}| / |lam_0| < tol. The sign of V_j is fixed by Phi_j(0) >= 0.
 
+    The same expansion serves the variable-hard-sphere kernels B = b |q|^gamma
+    with the weight (rho^2 + rho'^2)^(gamma/2) (gamma = 1: hard spheres).
+
     Returns (lam[K], rho[n_rho], w[n_rho], V[n_rho, K]).
     """
     x, w = np.polynomial.legendre.leggauss(n_rho)
     rp = 0.5 * R * (x + 1.0)
     wp = 0.5 * R * w
-    A = 4.0 * np.sqrt(np.outer(wp, wp)) * np.sqrt(rp[:, None] ** 2 + rp[None, :] ** 2)
+    A = 4.0 * np.sqrt(np.outer(wp, wp)) * vhs_weight(rp[:, None], rp[None, :], gamma)
     lam, V = np.linalg.eigh(A)
     idx = np.argsort(-np.abs(lam))
     lam, V = lam[idx], V[:, idx]
@@ -256,8 +273,9 @@ def filter_bank(s: Setup):
     if s.d == 2:
         if s.kernel == "maxwell":
             fams = [(1.0, lambda x: phi_segment(x, R))]
-        elif s.kernel == "hard_sphere":
-            lam, rp, wp, V = hs2d_radial_expansion(R, s.n_rho, s.K_r, s.kr_tol)
+        elif s.kernel in ("hard_sphere", "vhs"):
+            g = 1.0 if s.kernel == "hard_sphere" else s.gamma
+            lam, rp, wp, V = hs2d_radial_expansion(R, s.n_rho, s.K_r, s.kr_tol, gamma=g)
             fams = [(lam[j], (lambda x, j=j: hs2d_phi(x, rp, wp, V[:, j])))
                     for j in range(len(lam))]
         else:
