@@ -43,7 +43,7 @@ typedef struct qcoll_plan_s* qcoll_plan_t;
 /* Collision kernel B of eq. (Boltzmann). Maxwell pseudo-molecules B = b
  * (section 2); hard spheres B = b |q|. Supported: 2D Maxwell, 2D and 3D hard
  * spheres. */
-enum { QCOLL_MAXWELL = 0, QCOLL_HARD_SPHERE = 1 };
+enum { QCOLL_MAXWELL = 0, QCOLL_HARD_SPHERE = 1, QCOLL_VHS = 2 };
 
 /* Arithmetic of the velocity DFTs (all variants compute the same Q_h):
  *   QCOLL_FP32     DFT-GEMMs on FP32 MFMA, FP32 spectra and filters.
@@ -77,6 +77,9 @@ enum {
 #define QCOLL_R_LITERAL 0x2u  /* Carleman radius 2L/(3+sqrt 2)                  */
 #define QCOLL_HOST_ONLY 0x100u /* build the FP64 host tables only (no device)  */
 #define QCOLL_GALERKIN 0x4u   /* dealiased variant (qcoll_eval_galerkin), 2D   */
+#define QCOLL_CLASSICAL 0x8u  /* classical O(N^4) method, dense kernel modes  */
+#define QCOLL_SEPARABLE_MODES 0x10u /* with QCOLL_CLASSICAL: the plan's own
+                                       separable modes instead of exact ones */
 
 /* Build a plan (section 3.3: directions, filters, loss multiplier; section
  * 3.1: grid). d in {2,3}; n_per_dim = N (even, 4..256); L > 0 half-width of
@@ -97,6 +100,29 @@ enum {
  * QCOLL_EUNSUPPORTED on the device (their host tables build). */
 int qcoll_plan(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, double b,
                int M, int K_r, int precision, unsigned flags);
+
+/* Variable hard spheres B(|q|) = b |q|^gamma in 2D (-1 <= gamma <= 1; gamma = 1
+ * is QCOLL_HARD_SPHERE, gamma = 0 Maxwell molecules): the Carleman weight
+ * 2 b (rho^2 + rho'^2)^(gamma/2) expanded in K_r separable radial products as
+ * for hard spheres (section 3.3, eqs. (Btilde), (FKM)). Other arguments and the
+ * device support as for qcoll_plan with d = 2. */
+int qcoll_plan_vhs(qcoll_plan_t* out, int n_per_dim, double L, double gamma, double b, int M, int K_r,
+                   int precision, unsigned flags);
+
+/* Classical spectral method (QCOLL_CLASSICAL, d = 2): Q_hat_k = sum over l + m = k
+ * (modulo N, as the collocation of the fast method) of beta(l, m) f_l f_m with
+ * beta(l, m) = B(l, m) - B(m, m) held as a dense N^2 x N^2 table (eqs. (CF1),
+ * (KM), (ode), (FKM)), O(N^4) per cell, computed in FP64 on the device
+ * (precision is ignored). The kernel modes B(l, m) are the exact ones, evaluated
+ * with 8 N collision directions and, for hard and variable hard spheres, the
+ * full-rank radial expansion on 2 N + 16 Gauss-Legendre nodes (converged to
+ * rounding for Maxwell molecules; to about 1e-10 of the largest mode for hard
+ * spheres, whose weight has a cone point); with QCOLL_SEPARABLE_MODES the table is the
+ * plan's own separable sum over its M directions and K_r ranks, so that the
+ * result is the fast operator computed by the direct sum. Device plans: N <= 24.
+ * Classical plans evaluate through qcoll_eval (Q as double with QCOLL_CONSERVE)
+ * and accept no other call; building the exact table takes O(N^4 x directions
+ * x ranks) host work. */
 
 /* Q = Q_h(f) for `cells` cells. f: device, float[cells][N^d]; Q: device,
  * float[cells][N^d], or double[cells][N^d] when the plan has QCOLL_CONSERVE
@@ -190,6 +216,8 @@ int qcoll_plan_info(qcoll_plan_t plan, int* transforms, int* K_r, double* R, int
  *   3 loss multiplier l(k) = sum_t W_t alpha_t alpha'_t (out[N^d])
  *   4 radial eigenvalues lambda_j (out[K_r]; {1} for separable kernels)
  *   5 inverse Gram matrix of phi = (1, v, |v|^2) on the grid (out[(d+2)^2])
+ *   6 classical plans: row m of the kernel-mode table, beta(l, m) over l
+ *     (index = m, out[N^2], FFT order)
  * A Galerkin plan returns tables 0-4 of its Nf grid (0, 1 and 3 zero outside the
  * active N-grid modes) and table 5 of the N grid.
  * n is the capacity of out; returns the number of values written or QCOLL_EINVAL. */

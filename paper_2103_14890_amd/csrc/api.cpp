@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "kernels.hpp"
@@ -17,6 +18,10 @@ struct qcoll_plan_s {
   bool galerkin = false;
   double* gal_interp = nullptr;    // [Nf][N]
   double* gal_restrict = nullptr;  // [N][Nf]
+  bool classical = false;
+  std::vector<double> beta;        // classical plans: beta[l][m] (host, FP64)
+  double* cl_betaT = nullptr;      // device betaT[m][k] = beta((k - m) mod N, m)
+  double* cl_tw = nullptr;         // device exp(-2 pi i j / N)
   int precision = 0;
   unsigned flags = 0;
   int device = -1;
@@ -78,6 +83,9 @@ void free_device(qcoll_plan_s* p) {
   hipFree(p->gal_interp);
   hipFree(p->gal_restrict);
   p->gal_interp = p->gal_restrict = nullptr;
+  hipFree(p->cl_betaT);
+  hipFree(p->cl_tw);
+  p->cl_betaT = p->cl_tw = nullptr;
   p->filt3 = nullptr;
   p->scratch = nullptr;
   p->tw = nullptr;
@@ -463,6 +471,36 @@ qcoll::KernelArgs make_args(const qcoll_plan_s* p) {
 
 // 2D grids up to 32 points per axis run on the 16x16 (N <= 16) or 32x32 tile
 // kernels; grids of 34..64 points on the tile-64 kernel (FX16 only).
+// Dense kernel-mode table of the classical method: beta[l][m] = B(l, m) - B(m, m)
+// with B(l, m) = sum_t W_t alpha_t(l) alpha'_t(m) over the terms of `src` (zero
+// wherever l or m is a Nyquist mode, as the filters are). Rows split over host
+// threads.
+void classical_table(const qcoll::HostPlan& src, std::vector<double>& beta) {
+  const int64_t n = static_cast<int64_t>(src.N) * src.N;
+  const int T = static_cast<int>(src.W.size());
+  beta.assign(n * n, 0.0);
+  unsigned nth = std::thread::hardware_concurrency();
+  nth = nth < 1 ? 1 : (nth > 16 ? 16 : nth);
+  std::vector<std::thread> pool;
+  for (unsigned th = 0; th < nth; ++th)
+    pool.emplace_back([&, th] {
+      std::vector<double> row(n);
+      for (int64_t l = th; l < n; l += nth) {
+        std::fill(row.begin(), row.end(), 0.0);
+        for (int t = 0; t < T; ++t) {
+          const double a = src.W[t] * src.alpha[t][l];
+          if (a == 0.0) continue;
+          const double* ap = src.alphap[t].data();
+          for (int64_t m = 0; m < n; ++m) row[m] += a * ap[m];
+        }
+        // B(m, m) is the loss multiplier; it multiplies f_l for every l, Nyquist
+        // modes included (the loss is f times a filtered field)
+        for (int64_t m = 0; m < n; ++m) beta[l * n + m] = row[m] - src.loss[m];
+      }
+    });
+  for (auto& th : pool) th.join();
+}
+
 bool device_supported(const qcoll::HostPlan& hp, int precision) {
   if (hp.d == 3) return hp.N <= 32 && precision == QCOLL_FP32;
   if (hp.d != 2) return false;
@@ -474,36 +512,53 @@ bool device_supported(const qcoll::HostPlan& hp, int precision) {
 
 extern "C" {
 
-int qcoll_plan(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, double b, int M,
-               int K_r, int precision, unsigned flags) {
+static int plan_create(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, double gamma, double b,
+                       int M, int K_r, int precision, unsigned flags) {
   if (!out) return QCOLL_EINVAL;
   *out = nullptr;
   if (precision != QCOLL_FP32 && precision != QCOLL_MIX_FX16) return QCOLL_EINVAL;
-  if (flags & ~(QCOLL_CONSERVE | QCOLL_R_LITERAL | QCOLL_HOST_ONLY | QCOLL_GALERKIN)) return QCOLL_EINVAL;
+  if (flags & ~(QCOLL_CONSERVE | QCOLL_R_LITERAL | QCOLL_HOST_ONLY | QCOLL_GALERKIN | QCOLL_CLASSICAL |
+                QCOLL_SEPARABLE_MODES))
+    return QCOLL_EINVAL;
+  if ((flags & QCOLL_SEPARABLE_MODES) && !(flags & QCOLL_CLASSICAL)) return QCOLL_EINVAL;
+  if ((flags & QCOLL_CLASSICAL) && (flags & QCOLL_GALERKIN)) return QCOLL_EINVAL;
   qcoll_plan_s* p = new (std::nothrow) qcoll_plan_s;
   if (!p) return QCOLL_ENOMEM;
   p->precision = precision;
   p->flags = flags;
   int rc;
-  if (flags & QCOLL_GALERKIN) {
+  if (flags & QCOLL_CLASSICAL) {
+    p->classical = true;
+    rc = qcoll::build_host_plan(p->hp, d, n_per_dim, L, kernel, b, M, K_r, flags, gamma);
+    if (!rc && d != 2) rc = QCOLL_EUNSUPPORTED;
+    if (!rc && (flags & QCOLL_SEPARABLE_MODES)) {
+      classical_table(p->hp, p->beta);
+    } else if (!rc) {
+      // exact kernel modes: 8 N directions, full-rank radial expansion on 2 N + 16 nodes
+      qcoll::HostPlan hx;
+      const int nr = 2 * n_per_dim + 16;
+      rc = qcoll::build_host_plan(hx, d, n_per_dim, L, kernel, b, 8 * n_per_dim, nr, flags, gamma, nr);
+      if (!rc) classical_table(hx, p->beta);
+    }
+  } else if (flags & QCOLL_GALERKIN) {
     if (n_per_dim % 4) {
       delete p;
       return QCOLL_EINVAL;
     }
     p->galerkin = true;
-    rc = qcoll::build_host_plan(p->hp_coarse, d, n_per_dim, L, kernel, b, M, K_r, flags);
+    rc = qcoll::build_host_plan(p->hp_coarse, d, n_per_dim, L, kernel, b, M, K_r, flags, gamma);
     if (!rc && d != 2) rc = QCOLL_EUNSUPPORTED;
-    if (!rc) rc = qcoll::build_host_plan(p->hp, d, 3 * n_per_dim / 2, L, kernel, b, M, K_r, flags);
+    if (!rc) rc = qcoll::build_host_plan(p->hp, d, 3 * n_per_dim / 2, L, kernel, b, M, K_r, flags, gamma);
     if (!rc) qcoll::restrict_to_coarse_modes(p->hp, n_per_dim);
   } else {
-    rc = qcoll::build_host_plan(p->hp, d, n_per_dim, L, kernel, b, M, K_r, flags);
+    rc = qcoll::build_host_plan(p->hp, d, n_per_dim, L, kernel, b, M, K_r, flags, gamma);
   }
   if (rc) {
     delete p;
     return rc;
   }
   if (!(flags & QCOLL_HOST_ONLY)) {
-    if (!device_supported(p->hp, precision)) {
+    if (p->classical ? (p->hp.N > 24) : !device_supported(p->hp, precision)) {
       delete p;
       return QCOLL_EUNSUPPORTED;
     }
@@ -518,8 +573,27 @@ int qcoll_plan(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, do
     p->cus = cus;
     p->max_blocks = static_cast<int64_t>(cus) * 8;
     p->tile = p->hp.N > 32 ? 64 : (p->hp.N > 16 ? 32 : 16);
-    if (p->hp.d == 3) rc = build_device_3d(p);
-    else rc = p->tile == 64 ? build_device_2d64(p) : (p->tile == 32 ? build_device_2d32(p) : build_device_2d16(p));
+    if (p->classical) {
+      const int N = p->hp.N;
+      const int64_t n = static_cast<int64_t>(N) * N;
+      std::vector<double> bt(n * n), tw(2 * N);
+      for (int64_t m = 0; m < n; ++m) {
+        const int64_t m1 = m / N, m2 = m % N;
+        for (int64_t k = 0; k < n; ++k) {
+          const int64_t l = ((k / N - m1 + N) % N) * N + (k % N - m2 + N) % N;
+          bt[m * n + k] = p->beta[l * n + m];
+        }
+      }
+      for (int j = 0; j < N; ++j) {
+        tw[2 * j] = std::cos(2.0 * kPi * j / N);
+        tw[2 * j + 1] = -std::sin(2.0 * kPi * j / N);
+      }
+      if (!(rc = upload(bt, &p->cl_betaT, p->device_bytes))) rc = upload(tw, &p->cl_tw, p->device_bytes);
+    } else if (p->hp.d == 3) {
+      rc = build_device_3d(p);
+    } else {
+      rc = p->tile == 64 ? build_device_2d64(p) : (p->tile == 32 ? build_device_2d32(p) : build_device_2d16(p));
+    }
     if (!rc && p->galerkin) {
       std::vector<double> gi, gr;
       qcoll::galerkin_operators(p->hp_coarse.N, p->hp.N, gi, gr);
@@ -536,11 +610,37 @@ int qcoll_plan(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, do
   return QCOLL_OK;
 }
 
+int qcoll_plan(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, double b, int M,
+               int K_r, int precision, unsigned flags) {
+  if (kernel == QCOLL_VHS) return QCOLL_EINVAL;   // needs its exponent: qcoll_plan_vhs
+  return plan_create(out, d, n_per_dim, L, kernel, 1.0, b, M, K_r, precision, flags);
+}
+
+int qcoll_plan_vhs(qcoll_plan_t* out, int n_per_dim, double L, double gamma, double b, int M, int K_r,
+                   int precision, unsigned flags) {
+  if (!(gamma >= -1.0 && gamma <= 1.0)) return QCOLL_EINVAL;
+  return plan_create(out, 2, n_per_dim, L, QCOLL_VHS, gamma, b, M, K_r, precision, flags);
+}
+
 int qcoll_eval(qcoll_plan_t p, const float* f, void* Q, int64_t cells, hipStream_t stream) {
   if (!p || cells < 0) return QCOLL_EINVAL;
   if (!p->on_device || p->galerkin) return QCOLL_EUNSUPPORTED;
   if (cells == 0) return QCOLL_OK;
   if (!f || !Q) return QCOLL_EINVAL;
+  if (p->classical) {
+    qcoll::ClassicalArgs c;
+    c.f = f;
+    c.q = Q;
+    c.cells = cells;
+    c.N = p->hp.N;
+    c.betaT = p->cl_betaT;
+    c.tw = p->cl_tw;
+    c.conserve = (p->flags & QCOLL_CONSERVE) ? 1 : 0;
+    for (int i = 0; i < 16; ++i) c.gram_inv[i] = p->hp.gram_inv[i];
+    c.L = p->hp.L;
+    c.dv = 2.0 * p->hp.L / p->hp.N;
+    return qcoll::launch_classical(c, stream) ? QCOLL_EDEVICE : QCOLL_OK;
+  }
   int64_t n = static_cast<int64_t>(p->hp.N) * p->hp.N * (p->hp.d == 3 ? p->hp.N : 1);
   if (cells > (INT64_MAX / 8) / n) return QCOLL_EINVAL;
   if (p->hp.d == 3) {
@@ -564,7 +664,7 @@ int qcoll_step(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps, i
   if (!p || cells < 0) return QCOLL_EINVAL;
   if (!(dt > 0.0) || !(eps > 0.0) || !std::isfinite(dt) || !std::isfinite(eps)) return QCOLL_EINVAL;
   if (scheme != QCOLL_EXPLICIT_EULER && scheme != QCOLL_IMEX_EULER_PENALIZED) return QCOLL_EINVAL;
-  if (!p->on_device || p->galerkin) return QCOLL_EUNSUPPORTED;
+  if (!p->on_device || p->galerkin || p->classical) return QCOLL_EUNSUPPORTED;
   if (cells == 0) return QCOLL_OK;
   if (!f) return QCOLL_EINVAL;
   if (p->hp.d == 3) {
@@ -644,7 +744,7 @@ int qcoll_step_rk(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps
   if (!(dt > 0.0) || !(eps > 0.0) || !std::isfinite(dt) || !std::isfinite(eps)) return QCOLL_EINVAL;
   const int S = rk_stages(scheme);
   if (S == 0) return QCOLL_EINVAL;
-  if (!p->on_device || p->galerkin) return QCOLL_EUNSUPPORTED;
+  if (!p->on_device || p->galerkin || p->classical) return QCOLL_EUNSUPPORTED;
   if (cells == 0) return QCOLL_OK;
   if (!f || !work || work_bytes < qcoll_step_rk_work_bytes(p, scheme, cells)) return QCOLL_EINVAL;
   const int64_t stride = cells * static_cast<int64_t>(p->hp.N) * p->hp.N * (p->hp.d == 3 ? p->hp.N : 1);
@@ -697,7 +797,7 @@ static int multi_launch(const qcoll_plan_t* plans, int nplans, const float* cons
   for (int i = 0; i < nplans; ++i) {
     const qcoll_plan_s* p = plans[i];
     if (!p || cells[i] < 0) return QCOLL_EINVAL;
-    if (!p->on_device || p->galerkin) return QCOLL_EUNSUPPORTED;
+    if (!p->on_device || p->galerkin || p->classical) return QCOLL_EUNSUPPORTED;
     if (dev >= 0 && p->device != dev) return QCOLL_EINVAL;
     dev = p->device;
     if (cells[i] > 0 && (!f[i] || (!step && !Q[i]))) return QCOLL_EINVAL;
@@ -799,7 +899,7 @@ int qcoll_plan_get_launch(qcoll_plan_t p, int* waves_per_block, int64_t* max_blo
 // stream. Q receives the result of the last timed launch.
 int qcoll_plan_autotune(qcoll_plan_t p, const float* f, void* Q, int64_t cells, int reps, hipStream_t stream) {
   if (!p || !f || !Q || cells < 1 || reps < 1) return QCOLL_EINVAL;
-  if (!p->on_device || p->hp.d == 3 || p->galerkin) return QCOLL_EUNSUPPORTED;  // one fixed launch shape
+  if (!p->on_device || p->hp.d == 3 || p->galerkin || p->classical) return QCOLL_EUNSUPPORTED;  // one fixed launch shape
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return QCOLL_EDEVICE;
   const int wpbs[3] = {1, 2, 4};
@@ -862,6 +962,14 @@ int qcoll_plan_table(qcoll_plan_t p, int which, int index, double* out, int64_t 
     case 3: src = &hp.loss; break;
     case 4: src = &hp.lambda; break;
     case 5: src = p->galerkin ? &p->hp_coarse.gram_inv : &hp.gram_inv; break;
+    case 6: {
+      if (!p->classical) return QCOLL_EINVAL;
+      const int64_t nn = static_cast<int64_t>(hp.N) * hp.N;
+      if (index < 0 || index >= nn) return QCOLL_EINVAL;
+      if (n < nn) return QCOLL_EINVAL;
+      for (int64_t l = 0; l < nn; ++l) out[l] = p->beta[l * nn + index];
+      return static_cast<int>(nn);
+    }
     default: return QCOLL_EINVAL;
   }
   if (static_cast<int64_t>(src->size()) > n) return QCOLL_EINVAL;

@@ -130,11 +130,14 @@ void jacobi_eigen(int n, std::vector<double> a, std::vector<double>& evals,
 }
 
 int build_host_plan(HostPlan& hp, int d, int N, double L, int kernel, double b, int M, int K_r,
-                    unsigned flags) {
+                    unsigned flags, double gamma, int n_rho) {
   if (d != 2 && d != 3) return QCOLL_EINVAL;
   if (N < 4 || (N & 1) || N > 256) return QCOLL_EINVAL;
   if (!(L > 0.0) || !std::isfinite(L)) return QCOLL_EINVAL;
-  if (kernel != QCOLL_MAXWELL && kernel != QCOLL_HARD_SPHERE) return QCOLL_EINVAL;
+  if (kernel != QCOLL_MAXWELL && kernel != QCOLL_HARD_SPHERE && kernel != QCOLL_VHS) return QCOLL_EINVAL;
+  if (kernel == QCOLL_VHS && (d != 2 || !(gamma >= -1.0 && gamma <= 1.0))) return QCOLL_EINVAL;
+  if (n_rho < 4 || n_rho > 512) return QCOLL_EINVAL;
+  if (kernel == QCOLL_HARD_SPHERE) gamma = 1.0;
   if (M < 1) return QCOLL_EINVAL;
   if (d == 2 && (M & 1)) return QCOLL_EINVAL;
   if (K_r < 0) return QCOLL_EINVAL;
@@ -151,6 +154,7 @@ int build_host_plan(HostPlan& hp, int d, int N, double L, int kernel, double b, 
   hp.L = L;
   hp.M = M;
   hp.kernel = kernel;
+  hp.gamma = gamma;
   hp.R = ((flags & QCOLL_R_LITERAL) ? lam : 2.0 * lam) * L;
   hp.b = b > 0.0 ? b : (d == 2 ? 1.0 / (2.0 * kPi) : 1.0 / (4.0 * kPi));
   const double R = hp.R;
@@ -183,8 +187,8 @@ int build_host_plan(HostPlan& hp, int d, int N, double L, int kernel, double b, 
 
   // ---- radial families (2D)
   std::vector<double> rnode, rw, V;  // HS-2D: nodes on [0, R], weights, eigenvectors
-  int nr = 32;
-  if (d == 2 && kernel == QCOLL_HARD_SPHERE) {
+  const int nr = n_rho;
+  if (d == 2 && kernel != QCOLL_MAXWELL) {
     std::vector<double> x, w;
     gauss_legendre(nr, x, w);
     rnode.resize(nr);
@@ -193,12 +197,15 @@ int build_host_plan(HostPlan& hp, int d, int N, double L, int kernel, double b, 
       rnode[a] = 0.5 * R * (x[a] + 1.0);
       rw[a] = 0.5 * R * w[a];
     }
-    // even-part kernel matrix on [0,R]^2 (the weight is even in each argument)
+    // even-part kernel matrix on [0,R]^2 (the weight (rho^2 + rho'^2)^(gamma/2)
+    // is even in each argument; gamma = 1 for hard spheres)
     std::vector<double> A(static_cast<size_t>(nr) * nr);
     for (int a = 0; a < nr; ++a)
-      for (int c = 0; c < nr; ++c)
-        A[a * nr + c] = 4.0 * std::sqrt(rw[a] * rw[c]) *
-                        std::sqrt(rnode[a] * rnode[a] + rnode[c] * rnode[c]);
+      for (int c = 0; c < nr; ++c) {
+        const double r2 = rnode[a] * rnode[a] + rnode[c] * rnode[c];
+        const double wgt = gamma == 1.0 ? std::sqrt(r2) : (gamma == 0.0 ? 1.0 : std::pow(r2, 0.5 * gamma));
+        A[a * nr + c] = 4.0 * std::sqrt(rw[a] * rw[c]) * wgt;
+      }
     std::vector<double> ev, vec;
     jacobi_eigen(nr, A, ev, vec);
     std::vector<int> ord(nr);

@@ -14,6 +14,7 @@ namespace qcoll {
 struct HostPlan {
   int d = 2, N = 0, M = 0, K_r = 1, kernel = 0;
   double L = 0, R = 0, b = 0;
+  double gamma = 1.0;             // variable-hard-sphere exponent (kernel QCOLL_VHS)
   std::vector<double> dir;        // M x d unit vectors
   std::vector<double> dir_w;      // quadrature weight of each direction
   std::vector<double> lambda;     // radial eigenvalues (K_r), {1} when separable
@@ -30,8 +31,10 @@ struct HostPlan {
   std::vector<double> loss_scaled;                         // l / N^d
 };
 
+// kernel QCOLL_MAXWELL, QCOLL_HARD_SPHERE or QCOLL_VHS (2D, B = b |q|^gamma,
+// -1 <= gamma <= 1); n_rho Gauss-Legendre nodes of the 2D radial expansion.
 int build_host_plan(HostPlan& hp, int d, int N, double L, int kernel, double b, int M, int K_r,
-                    unsigned flags);
+                    unsigned flags, double gamma = 1.0, int n_rho = 32);
 
 // Dealiased (Galerkin) variant: restrict a plan built on the fine grid
 // Nf = 3 Nc / 2 to the active modes of the Nc grid (integer components strictly

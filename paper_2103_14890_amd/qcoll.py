@@ -16,13 +16,13 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libqcoll.so")
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "qcoll.h")
 
-MAXWELL, HARD_SPHERE = 0, 1
+MAXWELL, HARD_SPHERE, VHS = 0, 1, 2
 FP32, MIX_FX16 = 1, 4
 EXPLICIT_EULER, IMEX_EULER_PENALIZED, IMEX_ARS222, IMEX_BPR343 = 0, 1, 2, 3
-CONSERVE, R_LITERAL, GALERKIN, HOST_ONLY = 0x1, 0x2, 0x4, 0x100
+CONSERVE, R_LITERAL, GALERKIN, CLASSICAL, SEPARABLE_MODES, HOST_ONLY = 0x1, 0x2, 0x4, 0x8, 0x10, 0x100
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
 
-_KERNELS = {"maxwell": MAXWELL, "hard_sphere": HARD_SPHERE}
+_KERNELS = {"maxwell": MAXWELL, "hard_sphere": HARD_SPHERE, "vhs": VHS}
 _PRECISIONS = {"fp32": FP32, "fx16": MIX_FX16}
 _SCHEMES = {"explicit": EXPLICIT_EULER, "imex": IMEX_EULER_PENALIZED}
 _RK_SCHEMES = {"ars222": IMEX_ARS222, "bpr343": IMEX_BPR343}
@@ -51,6 +51,8 @@ def _load() -> ctypes.CDLL:
     lib.qcoll_plan.argtypes = [ctypes.POINTER(vp), c_int, c_int, dbl, c_int, dbl, c_int, c_int, c_int,
                                ctypes.c_uint]
     lib.qcoll_plan.restype = c_int
+    lib.qcoll_plan_vhs.argtypes = [ctypes.POINTER(vp), c_int, dbl, dbl, dbl, c_int, c_int, c_int, ctypes.c_uint]
+    lib.qcoll_plan_vhs.restype = c_int
     lib.qcoll_eval.argtypes = [vp, vp, vp, i64, vp]
     lib.qcoll_eval.restype = c_int
     lib.qcoll_step.argtypes = [vp, vp, i64, dbl, dbl, c_int, vp, vp]
@@ -141,12 +143,21 @@ class Plan:
 
     def __init__(self, d: int, N: int, L: float, kernel: str = "hard_sphere", M: int = 8, b: float = 0.0,
                  K_r: int = 0, precision: str = "fx16", conserve: bool = False, r_literal: bool = False,
-                 host_only: bool = False, galerkin: bool = False):
+                 host_only: bool = False, galerkin: bool = False, gamma: float = 1.0, classical: bool = False,
+                 separable_modes: bool = False):
         flags = ((CONSERVE if conserve else 0) | (R_LITERAL if r_literal else 0) | (HOST_ONLY if host_only else 0)
-                 | (GALERKIN if galerkin else 0))
+                 | (GALERKIN if galerkin else 0) | (CLASSICAL if classical else 0)
+                 | (SEPARABLE_MODES if separable_modes else 0))
         h = ctypes.c_void_p()
-        _check(LIB.qcoll_plan(ctypes.byref(h), d, N, float(L), _KERNELS[kernel], float(b), M, K_r,
-                              _PRECISIONS[precision], flags), "qcoll_plan")
+        if kernel == "vhs":
+            if d != 2:
+                raise ValueError("variable hard spheres are 2D")
+            _check(LIB.qcoll_plan_vhs(ctypes.byref(h), N, float(L), float(gamma), float(b), M, K_r,
+                                      _PRECISIONS[precision], flags), "qcoll_plan_vhs")
+        else:
+            _check(LIB.qcoll_plan(ctypes.byref(h), d, N, float(L), _KERNELS[kernel], float(b), M, K_r,
+                                  _PRECISIONS[precision], flags), "qcoll_plan")
+        self.gamma, self.classical = float(gamma), classical
         self._h = h
         self.d, self.N, self.L, self.kernel, self.M = d, N, float(L), kernel, M
         self.precision, self.conserve, self.galerkin = precision, conserve, galerkin
@@ -230,7 +241,8 @@ class Plan:
     def key(self) -> str:
         """Identity of the plan's workload shape for the autotuning cache."""
         return (f"d{self.d}_N{self.N}_{self.kernel}_M{self.M}_{self.precision}_{'c' if self.conserve else 'n'}"
-                + ("_galerkin" if self.galerkin else ""))
+                + ("_galerkin" if self.galerkin else "") + ("_classical" if self.classical else "")
+                + (f"_g{self.gamma}" if self.kernel == "vhs" else ""))
 
     def launch(self) -> tuple[int, int]:
         w, b = ctypes.c_int(), ctypes.c_int64()

@@ -151,3 +151,45 @@ def test_galerkin_plan_host_tables_and_checks():
     assert np.abs(p.table(5, size=16) - Gi.reshape(-1)).max() <= 1e-10 * np.abs(Gi).max()
     p.close()
     plain.close()
+
+
+@pytest.mark.parametrize("kernel,separable", [("maxwell", False), ("hard_sphere", False), ("hard_sphere", True)])
+def test_classical_mode_table_matches_oracle(kernel, separable):
+    """The C++ plan's dense kernel-mode table (own Gauss-Legendre, own Jacobi
+    eigen-solver) equals the oracle's, exact or separable modes."""
+    from oracle import classical as cl
+    p = qc.Plan(2, 12, 5.0, kernel, 8, host_only=True, classical=True, separable_modes=separable)
+    beta = cl.beta_table(sp.Setup(d=2, N=12, L=5.0, kernel=kernel, M=8), separable=separable)
+    for m in range(0, 144, 7):
+        assert np.abs(p.table(6, m, size=144) - beta[:, m]).max() <= 1e-13 * np.abs(beta).max()
+    p.close()
+
+
+@pytest.mark.parametrize("gamma", [0.5, -0.5, 0.0])
+def test_vhs_plan_tables_match_oracle(gamma):
+    p = qc.Plan(2, 16, 8.0, "vhs", 8, gamma=gamma, host_only=True)
+    bank = sp.filter_bank(sp.Setup(d=2, N=16, L=8.0, kernel="vhs", gamma=gamma, M=8))
+    W = p.table(2, size=len(bank) + 8)
+    assert len(W) == len(bank)
+    scale = max(np.abs(a).max() for _, a, _ in bank)
+    for t, (w, a, ap) in enumerate(bank):
+        assert abs(W[t] - w) <= 1e-12 * abs(w) + 1e-15
+        assert np.abs(p.table(0, t) - a.reshape(-1)).max() <= 1e-12 * scale
+        assert np.abs(p.table(1, t) - ap.reshape(-1)).max() <= 1e-12 * scale
+    p.close()
+
+
+def test_vhs_and_classical_argument_checks():
+    h = ctypes.c_void_p()
+    assert qc.LIB.qcoll_plan_vhs(ctypes.byref(h), 16, 8.0, 1.5, 0.0, 8, 0, 4, qc.HOST_ONLY) == qc.EINVAL
+    assert qc.LIB.qcoll_plan_vhs(ctypes.byref(h), 16, 8.0, -1.2, 0.0, 8, 0, 4, qc.HOST_ONLY) == qc.EINVAL
+    assert qc.LIB.qcoll_plan(ctypes.byref(h), 2, 16, 8.0, qc.VHS, 0.0, 8, 0, 4, qc.HOST_ONLY) == qc.EINVAL
+    assert _plan(flags=qc.SEPARABLE_MODES | qc.HOST_ONLY)[0] == qc.EINVAL          # needs CLASSICAL
+    assert _plan(flags=qc.CLASSICAL | qc.GALERKIN | qc.HOST_ONLY)[0] == qc.EINVAL
+    assert _plan(d=3, N=8, prec=1, flags=qc.CLASSICAL | qc.HOST_ONLY)[0] == qc.EUNSUPPORTED
+    assert _plan(N=32, flags=qc.CLASSICAL | qc.SEPARABLE_MODES)[0] == qc.EUNSUPPORTED   # device: N <= 24
+    p = qc.Plan(2, 8, 4.0, "maxwell", 8, host_only=True, classical=True)
+    assert qc.LIB.qcoll_step(p._h, None, 4, 0.01, 1.0, 0, None, None) == qc.EUNSUPPORTED
+    with pytest.raises(qc.QcollError):
+        p.table(6, 64, size=64)
+    p.close()
