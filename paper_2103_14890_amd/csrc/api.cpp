@@ -8,6 +8,8 @@
 #include <thread>
 #include <vector>
 
+#include "classical_args.hpp"
+#include "galerkin_args.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
 #include "qcoll.h"

@@ -92,80 +92,6 @@ struct Args3 {
 };
 int launch_3d(const Args3& args, hipStream_t stream);
 
-// Dealiased (Galerkin) variant, 2D: trigonometric interpolation of f from the
-// n grid to the nf grid (interp [nf][n] FP64) and restriction of the fine-grid
-// Q back (restrict_ [n][nf]), with the FP64 projection (gram_inv, 4x4) when
-// conserve is set (Q stored as double), else Q as float.
-struct GalerkinArgs {
-  const float* f = nullptr;       // [cells][n][n]
-  float* f_fine = nullptr;        // [cells][nf][nf]
-  const double* q_fine = nullptr; // [cells][nf][nf]
-  void* q = nullptr;              // [cells][n][n] float, or double with the projection
-  int64_t cells = 0;
-  int n = 0, nf = 0;
-  const double* interp = nullptr;     // [nf][n]
-  const double* restrict_ = nullptr;  // [n][nf]
-  int conserve = 0;
-  double gram_inv[16] = {};       // inverse Gram matrix of (1, v1, v2, |v|^2) on the n grid
-  double L = 0, dv = 0;
-};
-int launch_galerkin_interp(const GalerkinArgs& args, hipStream_t stream);
-int launch_galerkin_restrict(const GalerkinArgs& args, hipStream_t stream);
-
-// Classical spectral method (section 3.3, eqs. (CF1)/(ode) summed directly):
-// FP64, one workgroup per group of cells. betaT[m][k] = beta((k - m) mod N, m)
-// over the full mode grid in FFT order (zero where l or m has a component equal
-// to -N/2); tw[j] = exp(-2 pi i j / N).
-struct ClassicalArgs {
-  const float* f = nullptr;     // [cells][N][N]
-  void* q = nullptr;            // [cells][N][N] float, or double with the projection
-  int64_t cells = 0;
-  int N = 0;
-  const double* betaT = nullptr;  // [n][n], n = N^2
-  const double* tw = nullptr;     // [N][re, im]
-  int conserve = 0;
-  double gram_inv[16] = {};
-  double L = 0, dv = 0;
-};
-int launch_classical(const ClassicalArgs& args, hipStream_t stream);
-
-// Transport on polygonal meshes: one record per cell for each kernel (FP32,
-// read with wave-uniform scalar loads straight from the cell index, so no
-// load waits on another table load).
-constexpr int kTrMaxFaces = 12;
-constexpr int kTrMaxStencil = 11;   // central stencil without the cell itself (degree 2)
-constexpr int kTrMaxK = 5;          // non-constant Taylor basis functions (degree 2)
-struct TrCell {                                 // reconstruction
-  int slot0 = 0, nf = 0, pad0 = 0, pad1 = 0;
-  int stencil[kTrMaxStencil + 1] = {};          // central stencil cells
-  int nbr[kTrMaxFaces] = {};                    // cell across face L
-  float pinv[kTrMaxK][kTrMaxStencil + 1] = {};  // least-squares operator of the optimal polynomial
-  float S[16] = {};                             // oscillation form, upper triangle row by row
-  float binv[kTrMaxFaces][4] = {};              // one-sided stencil (face L, face L+1): 2x2 inverse
-  float phi[kTrMaxFaces][kTrMaxK] = {};         // face averages of the Taylor basis functions
-  float pad2[12] = {};
-};
-struct TrFlux {                                 // fluxes
-  int slot0 = 0, nf = 0, pad0 = 0, pad1 = 0;
-  int twin[kTrMaxFaces] = {};                   // face L in the neighbour's list
-  float nx[kTrMaxFaces] = {}, ny[kTrMaxFaces] = {};  // outward unit normals
-  float coef[kTrMaxFaces] = {};                 // |face| / |P_i|
-};
-struct TransportArgs {
-  const TrCell* cells = nullptr;
-  const TrFlux* flux = nullptr;
-  const float* f = nullptr;     // [cells][V]
-  float* fv = nullptr;          // [faces][V] face averages of the reconstruction
-  float* out = nullptr;         // [cells][V]
-  int64_t ncells = 0;
-  int V = 0, N = 0;             // velocities, nodes per axis
-  float vh = 0;                 // v = (2 j - N) vh per axis (vh = L / N, exact at v = 0)
-  int degree = 2;
-  int step = 0;                 // 0: out = R, 1: out = f + dt R
-  float dt = 0;
-};
-int launch_transport(const TransportArgs& args, hipStream_t stream);
-
 // Single-plan launches (args.tile selects the 16x16 or 32x32 kernel family).
 int launch_2d16(const KernelArgs& args, hipStream_t stream);
 int launch_2d32(const KernelArgs& args, hipStream_t stream);

@@ -12,6 +12,7 @@
 
 #include <cstdint>
 
+#include "classical_args.hpp"
 #include "kernels_common.hpp"
 
 namespace qcoll {

@@ -10,6 +10,7 @@
 
 #include <cstdint>
 
+#include "galerkin_args.hpp"
 #include "kernels_common.hpp"
 
 namespace qcoll {

@@ -16,7 +16,7 @@
 
 #include <cstdint>
 
-#include "kernels.hpp"
+#include "transport_args.hpp"
 
 namespace qcoll {
 namespace {

@@ -18,7 +18,7 @@
 #include <tuple>
 #include <vector>
 
-#include "kernels.hpp"
+#include "transport_args.hpp"
 #include "qcoll.h"
 
 // Stencil ranking compares squared generator distances: no contraction into
