@@ -880,9 +880,17 @@ int qcoll_step_multi(const qcoll_plan_t* plans, int nplans, float* const* f, con
                       status, stream);
 }
 
+// Eight wavefronts per workgroup select the ping-pong variant of the FX16
+// 32x32 kernel (two wavefronts per SIMD in alternating matrix/vector phases).
+static bool pingpong_ok(const qcoll_plan_s* p) {
+  return p->on_device && p->hp.d == 2 && p->tile == 32 && p->precision == QCOLL_MIX_FX16 && !p->classical;
+}
+
 int qcoll_plan_set_launch(qcoll_plan_t p, int waves_per_block, int64_t max_blocks) {
   if (!p) return QCOLL_EINVAL;
-  if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4) return QCOLL_EINVAL;
+  if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4 &&
+      !(waves_per_block == 8 && pingpong_ok(p)))
+    return QCOLL_EINVAL;
   if (max_blocks < 1) return QCOLL_EINVAL;
   p->waves_per_block = waves_per_block;
   p->max_blocks = max_blocks;
@@ -904,7 +912,7 @@ int qcoll_plan_autotune(qcoll_plan_t p, const float* f, void* Q, int64_t cells, 
   if (!p->on_device || p->hp.d == 3 || p->galerkin || p->classical) return QCOLL_EUNSUPPORTED;  // one fixed launch shape
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return QCOLL_EDEVICE;
-  const int wpbs[3] = {1, 2, 4};
+  const int wpbs[4] = {1, 2, 4, 8};
   const int64_t caps[4] = {1, 2, 8, 1 << 30};  // multiples of the CU count; last = one wave per cell
   float best = 1e30f;
   int best_w = p->waves_per_block;
@@ -912,13 +920,14 @@ int qcoll_plan_autotune(qcoll_plan_t p, const float* f, void* Q, int64_t cells, 
   int rc = QCOLL_OK;
   for (int w : wpbs)
     for (int64_t c : caps) {
+      if (w == 8 && !pingpong_ok(p)) continue;
       qcoll::KernelArgs a = make_args(p);
       a.f = f;
       a.q = Q;
       a.cells = cells;
       a.out_kind = (p->flags & QCOLL_CONSERVE) ? 1 : 0;
       a.waves_per_block = w;
-      a.max_blocks = c >= (1 << 30) ? (int64_t{1} << 40) : c * p->cus * (4 / w);
+      a.max_blocks = c >= (1 << 30) ? (int64_t{1} << 40) : c * p->cus * (w >= 4 ? 1 : 4 / w);
       if (launch(a, stream)) { rc = QCOLL_EDEVICE; break; }  // warm-up
       hipEventRecord(e0, stream);
       for (int r = 0; r < reps; ++r) launch(a, stream);

@@ -302,6 +302,163 @@ __device__ __forceinline__ void fx16_t32_body(const KernelArgs& a, int64_t first
   }
 }
 
+// ------------------------------------------------------------ FX16 ping-pong
+//
+// The same computation with eight wavefronts per workgroup, two per SIMD, run
+// in alternating phases. A cell's work is a strict alternation of matrix-core
+// phases (a DFT pass: 12 or 48 MFMAs) and vector phases (slicing, spectrum
+// store and filtered split, gain update, epilogue); every phase ends at a
+// workgroup barrier. Wavefronts 4..7 start one phase late, so while the
+// wavefront of one pair on a SIMD runs a DFT pass the other runs the vector
+// phase before it: the matrix core and the vector ALU of each SIMD work at the
+// same time by construction instead of by chance. All wavefronts execute the
+// same number of barriers: `kmax` cells each (a wavefront with fewer cells
+// works on a clamped cell and stores nothing), one stagger barrier at the
+// start (late group) or the end (early group).
+
+__device__ __forceinline__ void pp_phase_end() {
+  __builtin_amdgcn_sched_barrier(0);
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int OUT>
+__device__ __forceinline__ void fx16_t32_body_pp(const KernelArgs& a, int64_t first, int64_t stride, int64_t kmax,
+                                                 bool late, double2* fh, const half8* eo) {
+  const int lane = threadIdx.x & 63;
+  Split2 E[3][2];
+  {
+    const half8* src = reinterpret_cast<const half8*>(a.econst) + lane * 18;
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        E[m][s].l = src[(m * 2 + s) * 3 + 0];
+        E[m][s].h = src[(m * 2 + s) * 3 + 1];
+      }
+  }
+  if (late) pp_phase_end();
+
+  for (int64_t k = 0; k < kmax; ++k) {
+    const int64_t want = first + k * stride;
+    const bool valid = want < a.cells;
+    const int64_t cell = valid ? want : a.cells - 1;
+    f32x16 r0{}, r1{}, i0{}, i1{};
+    Split3 A[4];
+    int s_fh;
+    // [matrix] forward pass 1 (real input, contraction over the first axis)
+    {
+      float fv[16];
+      load_cell<Lay32>(a, cell, lane, fv);
+      float fm = 0.0f;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) fm = fmaxf(fm, fabsf(fv[v]));
+      fm = wave_max(fm);
+      const int a0 = 9 - exp_above(fm);
+      const float cf = ldexpf(1.0f, a0);
+#pragma unroll
+      for (int v = 0; v < 16; v += 2)
+        put2(A[v >> 3], v & 7, split2_f64(static_cast<double>(fv[v] * cf), static_cast<double>(fv[v + 1] * cf)));
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        mma6_lo_lds(A[s], E[kEr][s], eo + (kEr * 2 + s) * 64 + lane, r0, r1);
+        mma6_lo_lds(A[s], E[kNEi][s], eo + (kNEi * 2 + s) * 64 + lane, i0, i1);
+      }
+      s_fh = -(a0 + 9);
+    }
+    pp_phase_end();
+    // [vector] slice
+    int a1;
+    {
+      a1 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
+      slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a1), A);
+    }
+    pp_phase_end();
+    // [matrix] forward pass 2 (complex, contraction over the second axis)
+    pass64_lo_lds(A, E, eo, kEr, kEi, kNEi, kEr, true, r0, r1, i0, i1);
+    s_fh -= a1 + 9;
+    pp_phase_end();
+    // [vector] spectrum to LDS (FP64, |f_hat| < 2^8), first filtered split
+    double gain[16];
+    {
+      float fhm = 0.0f;
+#pragma unroll
+      for (int v = 0; v < 16; ++v)
+        fhm = fmaxf(fhm, fmaxf(fabsf(r0[v] + r1[v]), fabsf(i0[v] + i1[v])));
+      fhm = wave_max(fhm * 1.0000002f);
+      const int bsh = 9 - (exp_above(fhm) + 1);
+#pragma unroll
+      for (int v = 0; v < 16; ++v)
+        fh[v * 64 + lane] = make_double2(ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), bsh),
+                                         ldexp(static_cast<double>(i0[v]) + static_cast<double>(i1[v]), bsh));
+      s_fh -= bsh;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) gain[v] = 0.0;
+      double2 mv[16];
+      const unsigned l16 = opaque_lane16(lane);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) mv[v] = load_filter_value(a.filt, 0, v, l16);
+      filtered_split(mv, fh, lane, A);
+    }
+    pp_phase_end();
+    int sd_loss = 0;
+    for (int q = 0; q <= a.P; ++q) {
+      // [matrix] inverse pass A
+      pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
+      pp_phase_end();
+      // [vector] slice
+      const int a2 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
+      slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a2), A);
+      pp_phase_end();
+      // [matrix] inverse pass B (the loss field needs only the real part)
+      const bool gain_q = q < a.P;
+      pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, gain_q, r0, r1, i0, i1);
+      const int sd = a.filt_exp[q] + s_fh - 9 - a2 - 9;
+      pp_phase_end();
+      // [vector] gain update and the next filtered split (after the last, loss,
+      // transform the epilogue below is the vector phase)
+      if (gain_q) {
+        // first half of the next filter in flight during the gain update, the
+        // second half once the accumulators are consumed
+        __builtin_amdgcn_sched_barrier(0);
+        double2 mv[16];
+        const unsigned l16 = opaque_lane16(lane);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) mv[v] = load_filter_value(a.filt, q + 1, v, l16);
+        __builtin_amdgcn_sched_barrier(0);
+        const double w = ldexp(1.0, 2 * sd);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const double re = static_cast<double>(r0[v]) + static_cast<double>(r1[v]);
+          const double im = static_cast<double>(i0[v]) + static_cast<double>(i1[v]);
+          gain[v] = fma(re * w, im, gain[v]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int v = 8; v < 16; ++v) mv[v] = load_filter_value(a.filt, q + 1, v, l16);
+        __builtin_amdgcn_sched_barrier(0);
+        filtered_split(mv, fh, lane, A);
+        pp_phase_end();
+      } else {
+        sd_loss = sd;
+      }
+    }
+    // [vector] epilogue: Q = gain - f * loss
+    {
+      float fv[16];
+      load_cell<Lay32>(a, cell, lane, fv);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const double lf = ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), sd_loss);
+        gain[v] = gain[v] - static_cast<double>(fv[v]) * lf;
+      }
+      if (valid) finish_cell<OUT, Lay32>(a, cell, fv, gain, lane);
+    }
+    pp_phase_end();
+  }
+  if (!late) pp_phase_end();
+}
+
 // ------------------------------------------------------------ FP32 variant
 
 __device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c) {

@@ -51,6 +51,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                      lds + (kEoLdsBytes + w * kFhatLdsBytes) / 16, eo);
 }
 
+// Ping-pong variant: eight wavefronts (two per SIMD) in alternating phases.
+// The two wavefronts that share a SIMD take opposite roles: each wavefront
+// reads its SIMD from the hardware-ID register, and the second of the
+// workgroup's wavefronts on a SIMD starts one phase late.
+template <int OUT>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void fx16_t32_pp_kernel(KernelArgs a) {
+  extern __shared__ double2 lds[];
+  __shared__ int wave_simd[8];
+  half8* eo = reinterpret_cast<half8*>(lds);
+  const int w = threadIdx.x >> 6;
+  const int simd = (__builtin_amdgcn_s_getreg((31 << 11) | 4) >> 4) & 3;   // HW_ID bits 5:4
+  if ((threadIdx.x & 63) == 0) wave_simd[w] = simd;
+  load_eo_table(a, eo);   // ends with a workgroup barrier
+  int rank = 0;
+  for (int j = 0; j < w; ++j) rank += wave_simd[j] == simd ? 1 : 0;
+  const int64_t first0 = static_cast<int64_t>(blockIdx.x) * 8;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * 8;
+  const int64_t kmax = (a.cells - first0 + stride - 1) / stride;   // cells of wavefront 0 (the most)
+  fx16_t32_body_pp<OUT>(a, first0 + w, stride, kmax, (rank & 1) != 0, lds + (kEoLdsBytes + w * kFhatLdsBytes) / 16,
+                        eo);
+}
+
 template <int OUT>
 __global__ __launch_bounds__(256) void fp32_t32_kernel(KernelArgs a) {
   const int wpb = blockDim.x >> 6;
@@ -66,7 +88,29 @@ int launch_2d32(const KernelArgs& args, hipStream_t stream) {
   int64_t blocks = (args.cells + wpb - 1) / wpb;
   if (blocks > args.max_blocks) blocks = args.max_blocks;
   dim3 grid(static_cast<unsigned>(blocks)), block(64 * wpb);
-  if (args.precision == 4) {
+  if (args.precision == 4 && wpb == 8) {
+    const unsigned lds = kEoLdsBytes + kFhatLdsBytes * 8;
+    static const bool attr_ok = [] {
+      bool ok = true;
+      ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t32_pp_kernel<0>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kEoLdsBytes + 8 * kFhatLdsBytes) == hipSuccess;
+      ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t32_pp_kernel<1>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kEoLdsBytes + 8 * kFhatLdsBytes) == hipSuccess;
+      ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t32_pp_kernel<2>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kEoLdsBytes + 8 * kFhatLdsBytes) == hipSuccess;
+      ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t32_pp_kernel<3>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kEoLdsBytes + 8 * kFhatLdsBytes) == hipSuccess;
+      ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t32_pp_kernel<4>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kEoLdsBytes + 8 * kFhatLdsBytes) == hipSuccess;
+      return ok;
+    }();
+    if (!attr_ok) return -3;
+    if (args.out_kind == 0) hipLaunchKernelGGL(fx16_t32_pp_kernel<0>, grid, block, lds, stream, args);
+    else if (args.out_kind == 1) hipLaunchKernelGGL(fx16_t32_pp_kernel<1>, grid, block, lds, stream, args);
+    else if (args.out_kind == 2) hipLaunchKernelGGL(fx16_t32_pp_kernel<2>, grid, block, lds, stream, args);
+    else if (args.out_kind == 3) hipLaunchKernelGGL(fx16_t32_pp_kernel<3>, grid, block, lds, stream, args);
+    else hipLaunchKernelGGL(fx16_t32_pp_kernel<4>, grid, block, lds, stream, args);
+  } else if (args.precision == 4) {
     const unsigned lds = kEoLdsBytes + kFhatLdsBytes * wpb;
     static const bool attr_set = [] {  // dynamic LDS above the 64 KB default (4 waves: 70 KB)
       const int mx = kEoLdsBytes + 4 * kFhatLdsBytes;
