@@ -144,8 +144,49 @@ __device__ __forceinline__ void pass_tiles(const Emat<T>& E, int w, Load load, S
   }
 }
 
+// The inverse passes along axes 1 and 2 of one plane i0 = t (tiles t = w,
+// w+4, ... of this wavefront) run back to back: the axis-1 result goes through
+// a T x T plane in this wavefront's LDS (its layout has the lines in registers,
+// the axis-2 pass needs them on the lanes) instead of through the scratch
+// field, so the field is read once and never written between the two passes.
+// load(t, xr, xi) fetches plane t's axis-1 inputs (the next plane's while the
+// current one computes); store(t, dr, di) disposes of the axis-2 outputs.
+template <int T, class Load, class Store>
+__device__ __forceinline__ void plane_passes(const Emat<T>& E, int w, float2* plane, Load load, Store store) {
+  using S = Sh<T>;
+  float ar[S::NS], ai[S::NS], br[S::NS], bi[S::NS];
+  load(w, ar, ai);
+#pragma unroll 1
+  for (int t = w; t < T; t += 4) {
+    if (t + 4 < T) load(t + 4, br, bi);
+    typename S::acc dr, di;
+    tile_dft<T, true, true, false>(E, ar, ai, dr, di);
+    {
+      OPAQUE_LANE();
+#pragma unroll
+      for (int v = 0; v < S::NR; ++v) plane[S::row(v, lane) * T + x] = make_float2(dr[v], di[v]);
+    }
+    {
+      OPAQUE_LANE();
+#pragma unroll
+      for (int s = 0; s < S::NS; ++s) {
+        const float2 z = plane[x * T + S::KS * s + jl];
+        ar[s] = z.x;
+        ai[s] = z.y;
+      }
+    }
+    tile_dft<T, false, true, false>(E, ar, ai, dr, di);
+    store(t, dr, di);
+#pragma unroll
+    for (int s = 0; s < S::NS; ++s) {
+      ar[s] = br[s];
+      ai[s] = bi[s];
+    }
+  }
+}
+
 template <int T>
-__device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red) {
+__device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red, float2* plane) {
   using S = Sh<T>;
   constexpr int T2 = T * T, T3 = T * T * T;
   const int w = threadIdx.x >> 6;
@@ -244,22 +285,11 @@ __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red
           for (int v = 0; v < S::NR; ++v) work[S::row(v, lane) * T2 + t * T + x] = make_float2(dr[v], di[v]);
         });
     __syncthreads();
-    // ---- inverse pass, axis 1 (tile t = i0), in place
-    pass_tiles<T, true, true, false>(E, w, load_axis1, store_axis1);
-    __syncthreads();
-    // ---- inverse pass, axis 2 (data as the left operand; tile t = i0, lines
-    // i1 = x on the lanes, output point (t, row, x)) and the gain
-    pass_tiles<T, false, true, false>(
-        E, w,
-        [&](int t, float* xr, float* xi) {
-          OPAQUE_LANE();
-#pragma unroll
-          for (int s = 0; s < S::NS; ++s) {
-            const float2 z = work[t * T2 + x * T + S::KS * s + jl];
-            xr[s] = z.x;
-            xi[s] = z.y;
-          }
-        },
+    // ---- inverse passes along axis 1 and axis 2 of each plane t = i0 (axis 2
+    // with the data as the left operand: lines i1 = x on the lanes, output
+    // point (t, row, x)) and the gain
+    plane_passes<T>(
+        E, w, plane, load_axis1,
         [&](int t, const typename S::acc& dr, const typename S::acc& di) {
           OPAQUE_LANE();
           if (q < a.P) {
@@ -425,6 +455,8 @@ __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red
 
 __global__ __launch_bounds__(256) void fp32_3d_kernel(Args3 A) {
   __shared__ double red[32];
+  __shared__ float2 plane_lds[4][32 * 32];   // one T x T plane per wavefront (8 KB at T = 32)
+  float2* plane = plane_lds[threadIdx.x >> 6];
   char* scratch = A.scratch + static_cast<int64_t>(blockIdx.x) * A.scratch_stride;
   const int64_t total = A.cell_start[A.nslots];
   for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
@@ -433,8 +465,8 @@ __global__ __launch_bounds__(256) void fp32_3d_kernel(Args3 A) {
     while (s + 1 < A.nslots && g >= A.cell_start[s + 1]) ++s;
     const Slot3& a = A.slot[s];
     const int64_t cell = g - A.cell_start[s];
-    if (a.T == 32) cell_3d<32>(a, cell, scratch, red);
-    else cell_3d<16>(a, cell, scratch, red);
+    if (a.T == 32) cell_3d<32>(a, cell, scratch, red, plane);
+    else cell_3d<16>(a, cell, scratch, red, plane);
   }
 }
 
