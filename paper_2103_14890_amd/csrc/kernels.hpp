@@ -86,8 +86,8 @@ struct Args3 {
   int nslots = 0;
   int64_t cell_start[kMaxSlots + 1] = {};
   Slot3 slot[kMaxSlots];
-  char* scratch = nullptr;      // per workgroup: spectrum, work field (complex FP32), gain (FP64)
-  int64_t scratch_stride = 0;   // bytes per workgroup (24 T^3 for the largest T)
+  char* scratch = nullptr;      // per workgroup: spectrum, two work fields (complex FP32), gain (FP64)
+  int64_t scratch_stride = 0;   // bytes per workgroup (32 T^3 for the largest T)
   int64_t blocks = 0;           // workgroups (at most the scratch capacity)
 };
 int launch_3d(const Args3& args, hipStream_t stream);

@@ -185,6 +185,50 @@ __device__ __forceinline__ void plane_passes(const Emat<T>& E, int w, float2* pl
   }
 }
 
+// Two transforms at once: plane t of both work fields through the axis-1 and
+// axis-2 passes, the second field's planes prefetched like the first's; store
+// receives both outputs (so the FP64 gain is read and written once per pair).
+template <int T, class Load0, class Load1, class Store>
+__device__ __forceinline__ void plane_passes_pair(const Emat<T>& E, int w, float2* plane, Load0 load0, Load1 load1,
+                                                  Store store) {
+  using S = Sh<T>;
+  float ar[S::NS], ai[S::NS], br[S::NS], bi[S::NS];
+  load0(w, ar, ai);
+#pragma unroll 1
+  for (int t = w; t < T; t += 4) {
+    typename S::acc dr0, di0, dr1, di1;
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      // prefetch: field 1 of this plane during field 0, field 0 of the next plane during field 1
+      if (f == 0) load1(t, br, bi);
+      else if (t + 4 < T) load0(t + 4, br, bi);
+      typename S::acc dr, di;
+      tile_dft<T, true, true, false>(E, ar, ai, dr, di);
+      {
+        OPAQUE_LANE();
+#pragma unroll
+        for (int v = 0; v < S::NR; ++v) plane[S::row(v, lane) * T + x] = make_float2(dr[v], di[v]);
+      }
+      {
+        OPAQUE_LANE();
+#pragma unroll
+        for (int s = 0; s < S::NS; ++s) {
+          const float2 z = plane[x * T + S::KS * s + jl];
+          ar[s] = z.x;
+          ai[s] = z.y;
+        }
+      }
+      tile_dft<T, false, true, false>(E, ar, ai, f == 0 ? dr0 : dr1, f == 0 ? di0 : di1);
+#pragma unroll
+      for (int s = 0; s < S::NS; ++s) {
+        ar[s] = br[s];
+        ai[s] = bi[s];
+      }
+    }
+    store(t, dr0, di0, dr1, di1);
+  }
+}
+
 template <int T>
 __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red, float2* plane) {
   using S = Sh<T>;
@@ -194,6 +238,7 @@ __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red
   float2* fh = reinterpret_cast<float2*>(scratch);
   float2* work = fh + T3;
   double* gain = reinterpret_cast<double*>(work + T3);
+  float2* work1 = reinterpret_cast<float2*>(gain + T3);   // second work field (transform pairs)
   const float* fc = a.f + cell * static_cast<int64_t>(n) * n * n;
 
   Emat<T> E;
@@ -264,7 +309,88 @@ __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red
   __syncthreads();
 
   double mom[5] = {0, 0, 0, 0, 0};
-  for (int q = 0; q <= a.P; ++q) {
+  // Gain transforms in pairs: one axis-0 pass reads the spectrum once for both
+  // (two work fields), one plane pass reads and writes the FP64 gain once for
+  // both. An odd last gain transform and the loss transform run alone below.
+  int q0 = 0;
+  for (; q0 + 1 < a.P; q0 += 2) {
+    const float2* m0 = reinterpret_cast<const float2*>(a.filt) + static_cast<int64_t>(q0) * T3;
+    const float2* m1 = m0 + T3;
+    {
+      // ---- inverse pass, axis 0, both transforms (tile t = k1)
+      float zr[S::NS], zi[S::NS];
+      auto load_z = [&](int t) {
+        OPAQUE_LANE();
+#pragma unroll
+        for (int s = 0; s < S::NS; ++s) {
+          const float2 z = fh[(S::KS * s + jl) * T2 + t * T + x];
+          zr[s] = z.x;
+          zi[s] = z.y;
+        }
+      };
+      load_z(w);
+#pragma unroll 1
+      for (int t = w; t < T; t += 4) {
+        float xr[S::NS], xi[S::NS];
+        float2 mb[S::NS];
+        {
+          OPAQUE_LANE();
+#pragma unroll
+          for (int s = 0; s < S::NS; ++s) {
+            const float2 m = m0[(S::KS * s + jl) * T2 + t * T + x];
+            xr[s] = m.x * zr[s] - m.y * zi[s];
+            xi[s] = m.x * zi[s] + m.y * zr[s];
+          }
+#pragma unroll
+          for (int s = 0; s < S::NS; ++s) mb[s] = m1[(S::KS * s + jl) * T2 + t * T + x];  // during the first DFT
+        }
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+          if (f == 1) {
+#pragma unroll
+            for (int s = 0; s < S::NS; ++s) {
+              xr[s] = mb[s].x * zr[s] - mb[s].y * zi[s];
+              xi[s] = mb[s].x * zi[s] + mb[s].y * zr[s];
+            }
+            if (t + 4 < T) load_z(t + 4);   // the next tile's spectrum during the second DFT
+          }
+          typename S::acc dr, di;
+          tile_dft<T, true, true, false>(E, xr, xi, dr, di);
+          {
+            OPAQUE_LANE();
+            float2* wf = f == 0 ? work : work1;
+#pragma unroll
+            for (int v = 0; v < S::NR; ++v) wf[S::row(v, lane) * T2 + t * T + x] = make_float2(dr[v], di[v]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // ---- axis-1 and axis-2 passes of each plane, both transforms, and the gain
+    auto load_axis1_w1 = [&](int t, float* xr, float* xi) {
+      OPAQUE_LANE();
+#pragma unroll
+      for (int s = 0; s < S::NS; ++s) {
+        const float2 z = work1[t * T2 + (S::KS * s + jl) * T + x];
+        xr[s] = z.x;
+        xi[s] = z.y;
+      }
+    };
+    plane_passes_pair<T>(E, w, plane, load_axis1, load_axis1_w1,
+                         [&](int t, const typename S::acc& dr0, const typename S::acc& di0,
+                             const typename S::acc& dr1, const typename S::acc& di1) {
+                           OPAQUE_LANE();
+#pragma unroll
+                           for (int v = 0; v < S::NR; ++v) {
+                             const int o = t * T2 + S::row(v, lane) * T + x;
+                             const double g = static_cast<double>(dr0[v]) * static_cast<double>(di0[v]) +
+                                              static_cast<double>(dr1[v]) * static_cast<double>(di1[v]);
+                             gain[o] = q0 == 0 ? g : gain[o] + g;
+                           }
+                         });
+    __syncthreads();
+  }
+  for (int q = q0; q <= a.P; ++q) {
     const float2* mq = reinterpret_cast<const float2*>(a.filt) + static_cast<int64_t>(q) * T3;
     // ---- inverse pass, axis 0: filter times spectrum on load (tile t = k1)
     pass_tiles<T, true, true, false>(
