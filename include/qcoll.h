@@ -196,7 +196,11 @@ int qcoll_step_multi(const qcoll_plan_t* plans, int nplans, float* const* f, con
                      double eps, int scheme, int32_t* const* status, hipStream_t stream);
 
 /* Launch shape of single-plan calls: cells per workgroup (1, 2 or 4) and the
- * grid cap in workgroups (each wavefront loops over cells beyond it). */
+ * grid cap in workgroups (each wavefront loops over cells beyond it). 2D
+ * FX16 device plans with N <= 32 (32x32 tile) also take 8: the ping-pong
+ * variant, eight cells per workgroup whose two wavefronts per SIMD alternate
+ * between matrix and vector phases; its results are bitwise equal to the
+ * other shapes. Other values, and 8 for other plans, return QCOLL_EINVAL. */
 int qcoll_plan_set_launch(qcoll_plan_t plan, int waves_per_block, int64_t max_blocks);
 int qcoll_plan_get_launch(qcoll_plan_t plan, int* waves_per_block, int64_t* max_blocks);
 
