@@ -41,8 +41,9 @@ extern "C" {
 typedef struct qcoll_plan_s* qcoll_plan_t;
 
 /* Collision kernel B of eq. (Boltzmann). Maxwell pseudo-molecules B = b
- * (section 2); hard spheres B = b |q|. Supported: 2D Maxwell, 2D and 3D hard
- * spheres. */
+ * (section 2); hard spheres B = b |q|; variable hard spheres B = b |q|^gamma
+ * (QCOLL_VHS, created through qcoll_plan_vhs only). Supported: 2D Maxwell, 2D
+ * variable hard spheres, 2D and 3D hard spheres. */
 enum { QCOLL_MAXWELL = 0, QCOLL_HARD_SPHERE = 1, QCOLL_VHS = 2 };
 
 /* Arithmetic of the velocity DFTs (all variants compute the same Q_h):
@@ -84,13 +85,14 @@ enum {
 /* Build a plan (section 3.3: directions, filters, loss multiplier; section
  * 3.1: grid). d in {2,3}; n_per_dim = N (even, 4..256); L > 0 half-width of
  * the velocity box; kernel QCOLL_MAXWELL or
- * QCOLL_HARD_SPHERE; b kernel constant (<= 0: default); M number of collision
+ * QCOLL_HARD_SPHERE (QCOLL_VHS is QCOLL_EINVAL here); b kernel constant (<= 0: default); M number of collision
  * directions (the paper's A; even in 2D); K_r radial rank of the 2D
  * hard-sphere expansion (0: smallest rank with eigenvalue ratio < 1e-4;
  * ignored otherwise); precision one of the QCOLL_FP32 / QCOLL_MIX_FX16 values;
  * flags a combination of QCOLL_* flags. The plan owns its host and device
  * tables; apart from its launch shape (qcoll_plan_set_launch, set before use)
- * it is immutable and may be used from several streams at once. On error *out
+ * it is immutable and may be used from several streams at once, except 3D
+ * plans, whose scratch area allows one call in flight at a time. On error *out
  * is set to NULL. Device plans: d = 2 with N <= 32 in either precision (grids
  * below 16 or 32 run zero-padded in a 16x16 or 32x32 tile) and 34 <= N <= 64
  * in QCOLL_MIX_FX16 (radix-2 split into 32-point tiles, one workgroup per

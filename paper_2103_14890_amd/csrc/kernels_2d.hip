@@ -112,21 +112,22 @@ int launch_2d32(const KernelArgs& args, hipStream_t stream) {
     else hipLaunchKernelGGL(fx16_t32_pp_kernel<4>, grid, block, lds, stream, args);
   } else if (args.precision == 4) {
     const unsigned lds = kEoLdsBytes + kFhatLdsBytes * wpb;
-    static const bool attr_set = [] {  // dynamic LDS above the 64 KB default (4 waves: 70 KB)
+    static const bool attr_ok = [] {  // dynamic LDS above the 64 KB default (4 waves: 70 KB)
       const int mx = kEoLdsBytes + 4 * kFhatLdsBytes;
-      hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t32_kernel<0>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-      hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t32_kernel<1>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-      hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t32_kernel<2>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-      hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t32_kernel<3>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-      hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t32_kernel<4>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-      return true;
+      bool ok = true;
+      ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t32_kernel<0>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, mx) == hipSuccess;
+      ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t32_kernel<1>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, mx) == hipSuccess;
+      ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t32_kernel<2>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, mx) == hipSuccess;
+      ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t32_kernel<3>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, mx) == hipSuccess;
+      ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t32_kernel<4>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, mx) == hipSuccess;
+      return ok;
     }();
-    (void)attr_set;
+    if (!attr_ok) return -3;
     if (args.out_kind == 0) hipLaunchKernelGGL(fx16_t32_kernel<0>, grid, block, lds, stream, args);
     else if (args.out_kind == 1) hipLaunchKernelGGL(fx16_t32_kernel<1>, grid, block, lds, stream, args);
     else if (args.out_kind == 2) hipLaunchKernelGGL(fx16_t32_kernel<2>, grid, block, lds, stream, args);

@@ -384,20 +384,21 @@ int launch_2d64(const KernelArgs& args, hipStream_t stream) {
   if (args.precision != 4) return -4;
   int64_t blocks = args.cells;
   if (blocks > args.max_blocks) blocks = args.max_blocks;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<0>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-    hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<1>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-    hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<2>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-    hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<3>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-    hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<4>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-    attr_set = true;
-  }
+  static const bool attr_ok = [] {  // 135 KB of dynamic LDS, above the 64 KB default
+    bool ok = true;
+    ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<0>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes) == hipSuccess;
+    ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<1>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes) == hipSuccess;
+    ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<2>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes) == hipSuccess;
+    ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<3>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes) == hipSuccess;
+    ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<4>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes) == hipSuccess;
+    return ok;
+  }();
+  if (!attr_ok) return -3;
   dim3 grid(static_cast<unsigned>(blocks)), block(256);
   if (args.out_kind == 0) hipLaunchKernelGGL(fx16_t64_kernel<0>, grid, block, kLdsBytes, stream, args);
   else if (args.out_kind == 1) hipLaunchKernelGGL(fx16_t64_kernel<1>, grid, block, kLdsBytes, stream, args);

@@ -119,12 +119,11 @@ int launch_galerkin_interp(const GalerkinArgs& args, hipStream_t stream) {
 int launch_galerkin_restrict(const GalerkinArgs& args, hipStream_t stream) {
   if (args.cells <= 0) return 0;
   const unsigned lds = static_cast<unsigned>((args.nf * args.nf + args.n * args.nf) * sizeof(double));
-  static const bool attr_set = [] {  // up to 63^2 + 42 x 63 doubles = 53 KB
-    hipFuncSetAttribute(reinterpret_cast<const void*>(galerkin_restrict_kernel),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
-    return true;
+  static const bool attr_ok = [] {  // up to 63^2 + 42 x 63 doubles = 53 KB
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(galerkin_restrict_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024) == hipSuccess;
   }();
-  (void)attr_set;
+  if (!attr_ok) return -3;
   int64_t blocks = args.cells < 4096 ? args.cells : 4096;
   hipLaunchKernelGGL(galerkin_restrict_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), lds, stream, args);
   return hipGetLastError() == hipSuccess ? 0 : -3;

@@ -43,12 +43,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
 int launch_multi(const MultiArgs& args, int waves_per_block, hipStream_t stream) {
   const int64_t blocks = args.block_start[args.nslots];
   if (blocks <= 0) return 0;
-  static const bool attr_set = [] {  // dynamic LDS above the 64 KB default (4 waves: 70 KB)
-    hipFuncSetAttribute(reinterpret_cast<const void*>(multi_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                        kEoLdsBytes + 4 * kFhatLdsBytes);
-    return true;
+  static const bool attr_ok = [] {  // dynamic LDS above the 64 KB default (4 waves: 70 KB)
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(multi_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               kEoLdsBytes + 4 * kFhatLdsBytes) == hipSuccess;
   }();
-  (void)attr_set;
+  if (!attr_ok) return -3;
   hipLaunchKernelGGL(multi_kernel, dim3(static_cast<unsigned>(blocks)), dim3(64 * waves_per_block),
                      kEoLdsBytes + kFhatLdsBytes * waves_per_block, stream, args);
   return hipGetLastError() == hipSuccess ? 0 : -3;
