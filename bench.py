@@ -13,6 +13,7 @@ workload for comparison. Prints ONE JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -38,10 +39,11 @@ WORKLOADS_3D = {
              "hemisphere directions (33 transforms), FP32 DFT-GEMMs, FP64 conservation projection, "
              "both resolutions in one launch"),
 }
-HBM_PEAK = 8.0e12
-FP32_VALU_PEAK = 157.3e12   # FP32 vector FLOP/s (256 CUs x 2.4 GHz x 256 flop/clk)          # B/s
-FP16_MFMA_PEAK = 2.5e15    # dense FLOP/s
-FP32_MFMA_PEAK = 157.3e12  # dense FLOP/s
+HBM_PEAK = 8.0e12           # B/s
+FP32_VALU_PEAK = 157.3e12   # FP32 vector FLOP/s (256 CUs x 2.4 GHz x 256 flop/clk)
+FP64_VALU_PEAK = 78.6e12    # FP64 vector FLOP/s (256 CUs x 2.4 GHz x 128 flop/clk)
+FP16_MFMA_PEAK = 2.5e15     # dense FLOP/s
+FP32_MFMA_PEAK = 157.3e12   # dense FLOP/s
 
 
 def mfma_flops_per_cell(precision: str, transforms: int, N: int = 32) -> float:
@@ -71,7 +73,8 @@ def mfma_flops_per_cell_3d(T: int, transforms: int) -> float:
 
 # Source file of the dominant kernel of each workload.
 KERNEL_SOURCE = {"hs2d_32": "kernels_2d.hip", "hs2d_64_noisy": "kernels_2d64.hip", "hs3d": "kernels_3d.hip",
-                 "explosion_16k": "kernels_transport.hip"}
+                 "explosion_16k": "kernels_transport.hip", "galerkin_32": "kernels_2d64.hip",
+                 "classical_16": "kernels_classical.hip", "vhs2d_32": "kernels_2d.hip"}
 
 # Transport workloads (CWENO reconstruction + Rusanov fluxes on a polygonal mesh).
 WORKLOADS_TRANSPORT = {
@@ -79,8 +82,18 @@ WORKLOADS_TRANSPORT = {
                      "generators, Morton order), 32x32 velocities on [-10,10]^2, third-order CWENO "
                      "(degree 2), explicit Euler transport step, circular explosion data",
 }
-HBM_PEAK = 8.0e12
-FP32_VALU_PEAK = 157.3e12   # FP32 vector FLOP/s (256 CUs x 2.4 GHz x 256 flop/clk)
+
+# Variants of the operator on 2D grids: the dealiased Galerkin form, the
+# classical O(N^4) method and variable hard spheres (name: description).
+WORKLOADS_VARIANT = {
+    "galerkin_32": "4096 cells (the hs2d_32 inputs), dealiased Galerkin variant: N=32 on [-8,8]^2, hard "
+                   "spheres, M=8 x K_r=5, operator on the 48x48 grid (3/2 rule) by the FX16 radix-2 kernel "
+                   "between FP64 interpolation and restriction, FP64 projection on the 32x32 grid",
+    "classical_16": "4096 cells, 2D 16x16 grid on [-8,8]^2, hard spheres, classical spectral method: direct "
+                    "O(N^4) FP64 sum over the exact kernel modes (dense 256 x 256 table), FP64 projection",
+    "vhs2d_32": "4096 cells (the hs2d_32 inputs), variable hard spheres B = |q|^0.5, 2D 32x32 on [-8,8]^2, "
+                "M=8 directions x the automatic radial rank, FX16, FP64 projection",
+}
 
 
 def kernel_source_hash(workload: str) -> str:
@@ -372,6 +385,108 @@ def bench_transport(args) -> int:
     plan.close()
     return 0
 
+def classical_flops_per_cell(N: int) -> float:
+    """Algorithmic FP64 flops of one cell of the classical method on an N x N grid
+    (FMA = 2): the double sum, n^2 terms of a complex product (6) scaled by the
+    real table entry and accumulated (4), and the four N-point DFT passes over
+    the n modes (real input 4 N, complex 8 N, complex 8 N, real output 4 N)."""
+    n = N * N
+    return 10.0 * n * n + 24.0 * n * N
+
+
+def bench_variant(args) -> int:
+    """The Galerkin, classical and variable-hard-sphere variants of the operator."""
+    import torch
+    import workloads as wl
+    from oracle import classical as ocl
+    from oracle import galerkin as og
+    from oracle import spectral as sp
+    from paper_2103_14890_amd import qcoll
+
+    name, dev = args.workload, torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    L = 8.0
+    if name == "classical_16":
+        N, cells, kern, M = 16, 4096, "hard_sphere", 8
+        f64 = wl.mixture_cells(2, N, L, cells, 1616)
+    else:
+        N, kern, M = 32, ("vhs" if name == "vhs2d_32" else "hard_sphere"), 8
+        f64 = wl.config_inputs("hs2d_32")
+        cells = f64.shape[0]
+    f = torch.tensor(f64, dtype=torch.float32, device=dev)
+    q = torch.empty(f.shape, dtype=torch.float64, device=dev)
+    if name == "galerkin_32":
+        plan = qcoll.Plan(2, N, L, kern, M, precision="fx16", conserve=True, galerkin=True)
+        work = torch.empty(plan.galerkin_work_bytes(cells), dtype=torch.uint8, device=dev)
+        call = lambda: plan.eval_galerkin(f, q, work=work)   # noqa: E731
+    elif name == "classical_16":
+        plan = qcoll.Plan(2, N, L, kern, M, precision="fp32", conserve=True, classical=True)
+        call = lambda: plan.eval(f, q)                        # noqa: E731
+    else:
+        plan = qcoll.Plan(2, N, L, kern, M, precision="fx16", conserve=True, gamma=0.5)
+        call = lambda: plan.eval(f, q)                        # noqa: E731
+    wall, per = time_launches(call, args.steps, args.warmup, stream)
+    copy_calibration(args.calibrate_copy, dev)
+    T_ = float(np.mean(per))
+    info = plan.info()
+
+    # the oracle on a bounded prefix of the same cells (tables built outside the clock)
+    s = sp.Setup(d=2, N=N, L=L, kernel=kern, M=M, gamma=0.5 if name == "vhs2d_32" else 1.0)
+    if name == "galerkin_32":
+        fine = og.galerkin_bank(s)
+        ref_fn = lambda c: og.q_galerkin(c, s, fine)          # noqa: E731
+    elif name == "classical_16":
+        beta = ocl.beta_table(s)
+        ref_fn = lambda c: ocl.q_classical(c, s, beta)        # noqa: E731
+    else:
+        s = dataclasses.replace(s, K_r=info["K_r"])
+        bank = sp.filter_bank(s)
+        ref_fn = lambda c: sp.q_fast(c, s, bank)               # noqa: E731
+    f32 = f64.astype(np.float32).astype(np.float64)
+    done, t_cpu, outs = 0, 0.0, []
+    while t_cpu < args.cpu_seconds and done < cells:
+        c = f32[done:done + 16]
+        t0 = time.perf_counter()
+        outs.append(sp.project_conservative(ref_fn(c), 2, L))
+        t_cpu += time.perf_counter() - t0
+        done += len(c)
+    ref = np.concatenate(outs)
+    got = q[:done].cpu().numpy()
+    rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+    if name == "classical_16":
+        flops = classical_flops_per_cell(N) * cells
+        roof = {"bound": "alu", "achieved": flops / T_ / 1e12, "peak": FP64_VALU_PEAK / 1e12, "unit": "TFLOP/s",
+                "frac": flops / T_ / FP64_VALU_PEAK, "traffic": measured_traffic(name)}
+        metric, dtype = "cell Q(f,f) evals/s, classical O(N^4) spectral method at N_v=16^2", "f64"
+    else:
+        # executed FP16 MFMA work of the dominant kernel (the 48x48 fine grid of the
+        # Galerkin plan runs on the radix-2 kernel's four 32-point tiles)
+        flops = mfma_flops_per_cell("fx16", info["transforms"], 48 if name == "galerkin_32" else N) * cells
+        roof = {"bound": "mfma", "achieved": flops / T_ / 1e12, "peak": FP16_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
+                "frac": flops / T_ / FP16_MFMA_PEAK, "traffic": measured_traffic(name)}
+        metric = ("cell Q(f,f) evals/s, dealiased Galerkin variant at N_v=32^2" if name == "galerkin_32"
+                  else "cell Q(f,f) evals/s, variable hard spheres (gamma=0.5) at N_v=32^2")
+        dtype = "f16x6+f64"
+    out = {
+        "metric": metric, "value": cells / T_, "unit": "cell-evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": T_ * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": {"workload": f"{name}: {WORKLOADS_VARIANT[name]}", "cells": cells, "N_v": f"{N}x{N}",
+                   "kernel": kern, "M": M, "K_r": info["K_r"], "transforms": info["transforms"]},
+        "roofline": roof,
+        "cpu_baseline": {"value": done / t_cpu, "unit": "cell-evals/s", "cores": 1, "kind": "oracle",
+                         "sample": f"first {done} cells of the same workload, FP64 numpy oracle + projection, "
+                                   f"{t_cpu:.1f} s"},
+        "rel_err_l2": rel,
+        "launch_ms": {"p5": float(np.percentile(per, 5) * 1e3), "p50": float(np.median(per) * 1e3),
+                      "p95": float(np.percentile(per, 95) * 1e3)},
+        "p99_latency_ms": None,
+    }
+    print(json.dumps(out))
+    plan.close()
+    return 0
+
 
 def main() -> int:
     ap = argparse.ArgumentParser()
@@ -380,7 +495,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", default="hs2d_32",
-                    choices=sorted(WORKLOADS) + sorted(WORKLOADS_3D) + sorted(WORKLOADS_TRANSPORT))
+                    choices=sorted(WORKLOADS) + sorted(WORKLOADS_3D) + sorted(WORKLOADS_TRANSPORT)
+                    + sorted(WORKLOADS_VARIANT))
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the open-loop serving run (Poisson arrivals at 200 requests/s) "
                          "behind p99_latency_ms; 0 skips it")
@@ -402,6 +518,8 @@ def main() -> int:
         return bench_3d(args)
     if args.workload in WORKLOADS_TRANSPORT:
         return bench_transport(args)
+    if args.workload in WORKLOADS_VARIANT:
+        return bench_variant(args)
     dev = torch.device("cuda:0")
     NN, LL, KERN, MM, DESC = WORKLOADS[args.workload]
     f64 = wl.config_inputs(args.workload)

@@ -3,8 +3,10 @@
 // nf = 3n/2 points per axis with the filters restricted to the active modes of
 // the n grid, between a trigonometric interpolation of f (n -> nf) and a
 // restriction of Q back to the active n-grid modes (nf -> n). Both are
-// separable real matrices (applied along each axis, FP64), one workgroup per
-// cell, the cell staged in LDS.
+// separable real matrices (applied along each axis, FP64). A workgroup stages
+// the matrix and its transpose in LDS once and then loops over cells, each
+// cell staged in LDS: every inner product reads one operand as a broadcast and
+// the other at consecutive addresses.
 
 #include <hip/hip_runtime.h>
 
@@ -20,16 +22,24 @@ namespace {
 __global__ __launch_bounds__(256) void galerkin_interp_kernel(GalerkinArgs a) {
   extern __shared__ double sh[];
   const int n = a.n, nf = a.nf;
-  double* fs = sh;           // [n][n]
-  double* t = sh + n * n;    // [nf][n]: t = I f
+  double* I = sh;              // [nf][n]
+  double* IT = I + nf * n;     // [n][nf]
+  double* fs = IT + n * nf;    // [n][n]
+  double* t = fs + n * n;      // [nf][n]: t = I f
+  for (int i = threadIdx.x; i < nf * n; i += blockDim.x) {
+    const int r = i / n, k = i - r * n;
+    I[i] = a.interp[i];
+    IT[k * nf + r] = a.interp[i];
+  }
   for (int64_t cell = blockIdx.x; cell < a.cells; cell += gridDim.x) {
+    __syncthreads();  // tables staged; fs and t free again
     const float* fc = a.f + cell * static_cast<int64_t>(n) * n;
     for (int i = threadIdx.x; i < n * n; i += blockDim.x) fs[i] = static_cast<double>(fc[i]);
     __syncthreads();
     for (int i = threadIdx.x; i < nf * n; i += blockDim.x) {
       const int r = i / n, c = i - r * n;
       double s = 0.0;
-      for (int k = 0; k < n; ++k) s += a.interp[r * n + k] * fs[k * n + c];
+      for (int k = 0; k < n; ++k) s += I[r * n + k] * fs[k * n + c];
       t[i] = s;
     }
     __syncthreads();
@@ -37,10 +47,9 @@ __global__ __launch_bounds__(256) void galerkin_interp_kernel(GalerkinArgs a) {
     for (int i = threadIdx.x; i < nf * nf; i += blockDim.x) {
       const int r = i / nf, c = i - r * nf;
       double s = 0.0;
-      for (int k = 0; k < n; ++k) s += t[r * n + k] * a.interp[c * n + k];
+      for (int k = 0; k < n; ++k) s += t[r * n + k] * IT[k * nf + c];
       ff[i] = static_cast<float>(s);
     }
-    __syncthreads();
   }
 }
 
@@ -50,17 +59,25 @@ __global__ __launch_bounds__(256) void galerkin_restrict_kernel(GalerkinArgs a) 
   extern __shared__ double sh[];
   __shared__ double red[4][4];
   const int n = a.n, nf = a.nf;
-  double* qs = sh;            // [nf][nf]
-  double* t = sh + nf * nf;   // [n][nf]: t = R Q_fine, reused as [n][n] for Q
+  double* R = sh;              // [n][nf]
+  double* RT = R + n * nf;     // [nf][n]
+  double* qs = RT + nf * n;    // [nf][nf], reused as [n][n] for Q
+  double* t = qs + nf * nf;    // [n][nf]: t = R Q_fine
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < n * nf; i += blockDim.x) {
+    const int r = i / nf, k = i - r * nf;
+    R[i] = a.restrict_[i];
+    RT[k * n + r] = a.restrict_[i];
+  }
   for (int64_t cell = blockIdx.x; cell < a.cells; cell += gridDim.x) {
+    __syncthreads();  // tables staged; qs, t and red free again
     const double* qc = a.q_fine + cell * static_cast<int64_t>(nf) * nf;
     for (int i = threadIdx.x; i < nf * nf; i += blockDim.x) qs[i] = qc[i];
     __syncthreads();
     for (int i = threadIdx.x; i < n * nf; i += blockDim.x) {
       const int r = i / nf, c = i - r * nf;
       double s = 0.0;
-      for (int k = 0; k < nf; ++k) s += a.restrict_[r * nf + k] * qs[k * nf + c];
+      for (int k = 0; k < nf; ++k) s += R[r * nf + k] * qs[k * nf + c];
       t[i] = s;
     }
     __syncthreads();
@@ -69,7 +86,7 @@ __global__ __launch_bounds__(256) void galerkin_restrict_kernel(GalerkinArgs a) 
     for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
       const int r = i / n, c = i - r * n;
       double s = 0.0;
-      for (int k = 0; k < nf; ++k) s += t[r * nf + k] * a.restrict_[c * nf + k];
+      for (int k = 0; k < nf; ++k) s += t[r * nf + k] * RT[k * n + c];
       qs[i] = s;             // qs is free again: Q on the n grid
       const double v1 = -a.L + a.dv * r, v2 = -a.L + a.dv * c;
       m[0] += s;
@@ -102,30 +119,42 @@ __global__ __launch_bounds__(256) void galerkin_restrict_kernel(GalerkinArgs a) 
         Qo[i] = qs[i] - (lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * (v1 * v1 + v2 * v2));
       }
     }
-    __syncthreads();  // qs, t and red are reused by the next cell
   }
 }
 
 }  // namespace
 
+// Dynamic LDS: the matrix, its transpose and the cell's two staging fields, at
+// most 3 x 60 x 40 + 60^2 doubles (86 KB) for the largest device grid (n = 40).
+constexpr int kGalerkinMaxLds = 96 * 1024;
+
 int launch_galerkin_interp(const GalerkinArgs& args, hipStream_t stream) {
   if (args.cells <= 0) return 0;
-  const unsigned lds = static_cast<unsigned>((args.n * args.n + args.nf * args.n) * sizeof(double));
-  int64_t blocks = args.cells < 4096 ? args.cells : 4096;
-  hipLaunchKernelGGL(galerkin_interp_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), lds, stream, args);
+  const size_t lds = (3 * static_cast<size_t>(args.nf) * args.n + static_cast<size_t>(args.n) * args.n) *
+                     sizeof(double);
+  if (lds > kGalerkinMaxLds) return -1;
+  static const bool attr_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(galerkin_interp_kernel),
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  kGalerkinMaxLds) == hipSuccess;
+  if (!attr_ok) return -3;
+  const int64_t blocks = args.cells < 2048 ? args.cells : 2048;
+  hipLaunchKernelGGL(galerkin_interp_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256),
+                     static_cast<unsigned>(lds), stream, args);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
 int launch_galerkin_restrict(const GalerkinArgs& args, hipStream_t stream) {
   if (args.cells <= 0) return 0;
-  const unsigned lds = static_cast<unsigned>((args.nf * args.nf + args.n * args.nf) * sizeof(double));
-  static const bool attr_ok = [] {  // up to 63^2 + 42 x 63 doubles = 53 KB
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(galerkin_restrict_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024) == hipSuccess;
-  }();
+  const size_t lds = (3 * static_cast<size_t>(args.nf) * args.n + static_cast<size_t>(args.nf) * args.nf) *
+                     sizeof(double);
+  if (lds > kGalerkinMaxLds) return -1;
+  static const bool attr_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(galerkin_restrict_kernel),
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  kGalerkinMaxLds) == hipSuccess;
   if (!attr_ok) return -3;
-  int64_t blocks = args.cells < 4096 ? args.cells : 4096;
-  hipLaunchKernelGGL(galerkin_restrict_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), lds, stream, args);
+  const int64_t blocks = args.cells < 2048 ? args.cells : 2048;
+  hipLaunchKernelGGL(galerkin_restrict_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256),
+                     static_cast<unsigned>(lds), stream, args);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
