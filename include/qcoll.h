@@ -97,7 +97,7 @@ enum {
  * below 16 or 32 run zero-padded in a 16x16 or 32x32 tile) and 34 <= N <= 64
  * in QCOLL_MIX_FX16 (radix-2 split into 32-point tiles, one workgroup per
  * cell); d = 3 hard spheres with N <= 32 in QCOLL_FP32 (zero-padded 16^3 or
- * 32^3 tiles, one workgroup per cell, a scratch area of 32 T^3 bytes per
+ * 32^3 tiles, one workgroup per cell, a scratch area of 144 T^3 bytes per
  * resident workgroup held by the plan). Other sizes and precisions are
  * QCOLL_EUNSUPPORTED on the device (their host tables build). */
 int qcoll_plan(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, double b,

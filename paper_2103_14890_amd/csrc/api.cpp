@@ -404,9 +404,10 @@ int build_device_3d(qcoll_plan_s* p) {
           }
         }
   if ((rc = upload(ft, &p->filt3, p->device_bytes))) return rc;
-  // scratch: complex spectrum and work field (8 T^3 bytes each) and the FP64
-  // gain (8 T^3 bytes) per workgroup; two workgroups per CU for 32^3 tiles
-  p->scratch_stride = 32 * T3;   // spectrum, two work fields (FP32 complex), gain (FP64)
+  // scratch per workgroup: the complex spectrum and one work field per
+  // transform of a group (8 T^3 bytes each) and the FP64 gain (8 T^3 bytes);
+  // two workgroups per CU for 32^3 tiles
+  p->scratch_stride = qcoll::scratch_3d_bytes(T);
   p->scratch_blocks = static_cast<int64_t>(p->cus) * (T == 32 ? 2 : 4);
   const size_t sb = static_cast<size_t>(p->scratch_stride) * p->scratch_blocks;
   if (hipMalloc(reinterpret_cast<void**>(&p->scratch), sb) != hipSuccess) return QCOLL_ENOMEM;

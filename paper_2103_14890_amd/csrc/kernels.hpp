@@ -82,12 +82,18 @@ struct Slot3 {
   int rk_scheme = 0;
   int rk_stage = 0;
 };
+// Gain transforms per group in the 3D kernel, and the scratch a 3D workgroup
+// needs on a T^3 tile: the spectrum and k3dGroup work fields (complex FP32)
+// and the gain (FP64).
+constexpr int k3dGroup = 16;
+constexpr int64_t scratch_3d_bytes(int T) { return (8 + 8 * k3dGroup + 8) * static_cast<int64_t>(T) * T * T; }
+
 struct Args3 {
   int nslots = 0;
   int64_t cell_start[kMaxSlots + 1] = {};
   Slot3 slot[kMaxSlots];
-  char* scratch = nullptr;      // per workgroup: spectrum, two work fields (complex FP32), gain (FP64)
-  int64_t scratch_stride = 0;   // bytes per workgroup (32 T^3 for the largest T)
+  char* scratch = nullptr;      // per workgroup: spectrum, k3dGroup work fields, gain
+  int64_t scratch_stride = 0;   // bytes per workgroup (scratch_3d_bytes of the largest T)
   int64_t blocks = 0;           // workgroups (at most the scratch capacity)
 };
 int launch_3d(const Args3& args, hipStream_t stream);

@@ -8,7 +8,7 @@
 // The 3D DFT is three passes, one per axis, each a batch of 1-D complex DFTs
 // done as FP32 MFMA GEMMs over tiles of T lines (section 3.3: the kernel modes
 // become A products in Fourier space, each evaluated by FFT-sized transforms).
-// A cell's complex spectrum, the work field between passes and the FP64 gain
+// A cell's complex spectrum, the work fields between passes and the FP64 gain
 // live in a per-workgroup scratch area (global memory, cached in L2/MALL):
 // a 32^3 complex field is 256 KB, more than the LDS of a CU.
 //
@@ -19,11 +19,12 @@
 // registers and the transformed index on the lanes (coalesced stores). The
 // per-lane DFT-matrix values are the same in both roles since E is symmetric.
 //
-// Per cell: forward passes axis 2, 1, 0 -> spectrum; for each packed transform q
-// the inverse passes axis 0 (multiplying the spectrum by the filter on load),
-// 1, 2 (accumulating Re * Im into the gain, FP64); the last transform is the
-// loss multiplier, whose real field gives Q = gain - f * loss. Then the FP64
-// conservation projection or the stage update, as in the 2D kernels.
+// Per cell: forward passes axis 2, 1, 0 -> spectrum; for each group of packed
+// transforms the inverse passes axis 0 (multiplying the spectrum by each
+// filter on load), then 1 and 2 plane by plane (accumulating Re * Im into the
+// gain, FP64); the last transform is the loss multiplier, whose real field
+// gives Q = gain - f * loss. Then the FP64 conservation projection or the
+// stage update, as in the 2D kernels.
 
 #include <hip/hip_runtime.h>
 
@@ -185,23 +186,26 @@ __device__ __forceinline__ void plane_passes(const Emat<T>& E, int w, float2* pl
   }
 }
 
-// Two transforms at once: plane t of both work fields through the axis-1 and
-// axis-2 passes, the second field's planes prefetched like the first's; store
-// receives both outputs (so the FP64 gain is read and written once per pair).
-template <int T, class Load0, class Load1, class Store>
-__device__ __forceinline__ void plane_passes_pair(const Emat<T>& E, int w, float2* plane, Load0 load0, Load1 load1,
-                                                  Store store) {
+// Up to k3dGroup transforms at once: plane t of each work field in turn through
+// the axis-1 and axis-2 passes (the next field's plane, or the next plane's
+// first field, prefetched during the current one), the products Re * Im of
+// the group summed in FP64 registers; store(t, g) receives the plane's sum, so
+// the FP64 gain is read and written once per group.
+template <int T, class Load, class Store>
+__device__ __forceinline__ void plane_passes_group(const Emat<T>& E, int w, float2* plane, int g, Load load,
+                                                   Store store) {
   using S = Sh<T>;
   float ar[S::NS], ai[S::NS], br[S::NS], bi[S::NS];
-  load0(w, ar, ai);
+  load(0, w, ar, ai);
 #pragma unroll 1
   for (int t = w; t < T; t += 4) {
-    typename S::acc dr0, di0, dr1, di1;
+    double acc[S::NR];
 #pragma unroll
-    for (int f = 0; f < 2; ++f) {
-      // prefetch: field 1 of this plane during field 0, field 0 of the next plane during field 1
-      if (f == 0) load1(t, br, bi);
-      else if (t + 4 < T) load0(t + 4, br, bi);
+    for (int v = 0; v < S::NR; ++v) acc[v] = 0.0;
+#pragma unroll 1
+    for (int f = 0; f < g; ++f) {
+      if (f + 1 < g) load(f + 1, t, br, bi);
+      else if (t + 4 < T) load(0, t + 4, br, bi);
       typename S::acc dr, di;
       tile_dft<T, true, true, false>(E, ar, ai, dr, di);
       {
@@ -218,14 +222,16 @@ __device__ __forceinline__ void plane_passes_pair(const Emat<T>& E, int w, float
           ai[s] = z.y;
         }
       }
-      tile_dft<T, false, true, false>(E, ar, ai, f == 0 ? dr0 : dr1, f == 0 ? di0 : di1);
+      tile_dft<T, false, true, false>(E, ar, ai, dr, di);
+#pragma unroll
+      for (int v = 0; v < S::NR; ++v) acc[v] += static_cast<double>(dr[v]) * static_cast<double>(di[v]);
 #pragma unroll
       for (int s = 0; s < S::NS; ++s) {
         ar[s] = br[s];
         ai[s] = bi[s];
       }
     }
-    store(t, dr0, di0, dr1, di1);
+    store(t, acc);
   }
 }
 
@@ -238,7 +244,9 @@ __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red
   float2* fh = reinterpret_cast<float2*>(scratch);
   float2* work = fh + T3;
   double* gain = reinterpret_cast<double*>(work + T3);
-  float2* work1 = reinterpret_cast<float2*>(gain + T3);   // second work field (transform pairs)
+  float2* work_g = reinterpret_cast<float2*>(gain + T3);  // further work fields of a transform group
+  // work field f of a group: f = 0 is `work`, f >= 1 follow the gain
+  auto wfield = [&](int f) { return f == 0 ? work : work_g + static_cast<int64_t>(f - 1) * T3; };
   const float* fc = a.f + cell * static_cast<int64_t>(n) * n * n;
 
   Emat<T> E;
@@ -309,16 +317,18 @@ __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red
   __syncthreads();
 
   double mom[5] = {0, 0, 0, 0, 0};
-  // Gain transforms in pairs: one axis-0 pass reads the spectrum once for both
-  // (two work fields), one plane pass reads and writes the FP64 gain once for
-  // both. An odd last gain transform and the loss transform run alone below.
+  // Gain transforms in groups of up to k3dGroup: one axis-0 pass reads the
+  // spectrum once for the whole group (one work field per transform), one plane
+  // pass reads and writes the FP64 gain once for the group. The loss transform
+  // runs alone below.
   int q0 = 0;
-  for (; q0 + 1 < a.P; q0 += 2) {
-    const float2* m0 = reinterpret_cast<const float2*>(a.filt) + static_cast<int64_t>(q0) * T3;
-    const float2* m1 = m0 + T3;
+  for (; q0 < a.P; q0 += k3dGroup) {
+    const int g = a.P - q0 < k3dGroup ? a.P - q0 : k3dGroup;
+    const float2* mg = reinterpret_cast<const float2*>(a.filt) + static_cast<int64_t>(q0) * T3;
     {
-      // ---- inverse pass, axis 0, both transforms (tile t = k1)
+      // ---- inverse pass, axis 0, every transform of the group (tile t = k1)
       float zr[S::NS], zi[S::NS];
+      float2 mb[S::NS];
       auto load_z = [&](int t) {
         OPAQUE_LANE();
 #pragma unroll
@@ -328,37 +338,37 @@ __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red
           zi[s] = z.y;
         }
       };
+      auto load_m = [&](int f, int t) {
+        OPAQUE_LANE();
+        const float2* m = mg + static_cast<int64_t>(f) * T3;
+#pragma unroll
+        for (int s = 0; s < S::NS; ++s) mb[s] = m[(S::KS * s + jl) * T2 + t * T + x];
+      };
       load_z(w);
+      load_m(0, w);
 #pragma unroll 1
       for (int t = w; t < T; t += 4) {
-        float xr[S::NS], xi[S::NS];
-        float2 mb[S::NS];
-        {
-          OPAQUE_LANE();
+#pragma unroll 1
+        for (int f = 0; f < g; ++f) {
+          float xr[S::NS], xi[S::NS];
 #pragma unroll
           for (int s = 0; s < S::NS; ++s) {
-            const float2 m = m0[(S::KS * s + jl) * T2 + t * T + x];
-            xr[s] = m.x * zr[s] - m.y * zi[s];
-            xi[s] = m.x * zi[s] + m.y * zr[s];
+            xr[s] = mb[s].x * zr[s] - mb[s].y * zi[s];
+            xi[s] = mb[s].x * zi[s] + mb[s].y * zr[s];
           }
-#pragma unroll
-          for (int s = 0; s < S::NS; ++s) mb[s] = m1[(S::KS * s + jl) * T2 + t * T + x];  // during the first DFT
-        }
-#pragma unroll
-        for (int f = 0; f < 2; ++f) {
-          if (f == 1) {
-#pragma unroll
-            for (int s = 0; s < S::NS; ++s) {
-              xr[s] = mb[s].x * zr[s] - mb[s].y * zi[s];
-              xi[s] = mb[s].x * zi[s] + mb[s].y * zr[s];
-            }
-            if (t + 4 < T) load_z(t + 4);   // the next tile's spectrum during the second DFT
+          // during this DFT: the next transform's filter tile, or the next tile's
+          // spectrum and first filter
+          if (f + 1 < g) {
+            load_m(f + 1, t);
+          } else if (t + 4 < T) {
+            load_z(t + 4);
+            load_m(0, t + 4);
           }
           typename S::acc dr, di;
           tile_dft<T, true, true, false>(E, xr, xi, dr, di);
           {
             OPAQUE_LANE();
-            float2* wf = f == 0 ? work : work1;
+            float2* wf = wfield(f);
 #pragma unroll
             for (int v = 0; v < S::NR; ++v) wf[S::row(v, lane) * T2 + t * T + x] = make_float2(dr[v], di[v]);
           }
@@ -366,33 +376,32 @@ __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red
       }
     }
     __syncthreads();
-    // ---- axis-1 and axis-2 passes of each plane, both transforms, and the gain
-    auto load_axis1_w1 = [&](int t, float* xr, float* xi) {
-      OPAQUE_LANE();
+    // ---- axis-1 and axis-2 passes of each plane, every transform of the group, and the gain
+    plane_passes_group<T>(E, w, plane, g,
+                          [&](int f, int t, float* xr, float* xi) {
+                            OPAQUE_LANE();
+                            const float2* wf = wfield(f);
 #pragma unroll
-      for (int s = 0; s < S::NS; ++s) {
-        const float2 z = work1[t * T2 + (S::KS * s + jl) * T + x];
-        xr[s] = z.x;
-        xi[s] = z.y;
-      }
-    };
-    plane_passes_pair<T>(E, w, plane, load_axis1, load_axis1_w1,
-                         [&](int t, const typename S::acc& dr0, const typename S::acc& di0,
-                             const typename S::acc& dr1, const typename S::acc& di1) {
-                           OPAQUE_LANE();
+                            for (int s = 0; s < S::NS; ++s) {
+                              const float2 z = wf[t * T2 + (S::KS * s + jl) * T + x];
+                              xr[s] = z.x;
+                              xi[s] = z.y;
+                            }
+                          },
+                          [&](int t, const double* acc) {
+                            OPAQUE_LANE();
 #pragma unroll
-                           for (int v = 0; v < S::NR; ++v) {
-                             const int o = t * T2 + S::row(v, lane) * T + x;
-                             const double g = static_cast<double>(dr0[v]) * static_cast<double>(di0[v]) +
-                                              static_cast<double>(dr1[v]) * static_cast<double>(di1[v]);
-                             gain[o] = q0 == 0 ? g : gain[o] + g;
-                           }
-                         });
+                            for (int v = 0; v < S::NR; ++v) {
+                              const int o = t * T2 + S::row(v, lane) * T + x;
+                              gain[o] = q0 == 0 ? acc[v] : gain[o] + acc[v];
+                            }
+                          });
     __syncthreads();
   }
-  for (int q = q0; q <= a.P; ++q) {
-    const float2* mq = reinterpret_cast<const float2*>(a.filt) + static_cast<int64_t>(q) * T3;
-    // ---- inverse pass, axis 0: filter times spectrum on load (tile t = k1)
+  {
+    // ---- the loss transform (entry P of the table): inverse pass along axis 0
+    // with the filter times the spectrum on load (tile t = k1)
+    const float2* mq = reinterpret_cast<const float2*>(a.filt) + static_cast<int64_t>(a.P) * T3;
     pass_tiles<T, true, true, false>(
         E, w,
         [&](int t, float* xr, float* xi) {
@@ -413,37 +422,28 @@ __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red
     __syncthreads();
     // ---- inverse passes along axis 1 and axis 2 of each plane t = i0 (axis 2
     // with the data as the left operand: lines i1 = x on the lanes, output
-    // point (t, row, x)) and the gain
+    // point (t, row, x)); the real loss field gives Q = gain - f * loss on the
+    // grid points, zero elsewhere
     plane_passes<T>(
         E, w, plane, load_axis1,
         [&](int t, const typename S::acc& dr, const typename S::acc& di) {
           OPAQUE_LANE();
-          if (q < a.P) {
 #pragma unroll
-            for (int v = 0; v < S::NR; ++v) {
-              const int o = t * T2 + S::row(v, lane) * T + x;
-              const double g = static_cast<double>(dr[v]) * static_cast<double>(di[v]);
-              gain[o] = q == 0 ? g : gain[o] + g;
+          for (int v = 0; v < S::NR; ++v) {
+            const int r = S::row(v, lane);
+            const int o = t * T2 + r * T + x;
+            double Q = 0.0;
+            if (t < n && r < n && x < n) {
+              const double fv = static_cast<double>(fc[(t * n + r) * n + x]);
+              Q = (a.P > 0 ? gain[o] : 0.0) - fv * static_cast<double>(dr[v]);
+              const double v0 = -a.L + a.dv * t, v1 = -a.L + a.dv * r, v2 = -a.L + a.dv * x;
+              mom[0] += Q;
+              mom[1] += v0 * Q;
+              mom[2] += v1 * Q;
+              mom[3] += v2 * Q;
+              mom[4] += (v0 * v0 + v1 * v1 + v2 * v2) * Q;
             }
-          } else {
-            // loss field: Q = gain - f * loss on the grid points, zero elsewhere
-#pragma unroll
-            for (int v = 0; v < S::NR; ++v) {
-              const int r = S::row(v, lane);
-              const int o = t * T2 + r * T + x;
-              double Q = 0.0;
-              if (t < n && r < n && x < n) {
-                const double fv = static_cast<double>(fc[(t * n + r) * n + x]);
-                Q = (a.P > 0 ? gain[o] : 0.0) - fv * static_cast<double>(dr[v]);
-                const double v0 = -a.L + a.dv * t, v1 = -a.L + a.dv * r, v2 = -a.L + a.dv * x;
-                mom[0] += Q;
-                mom[1] += v0 * Q;
-                mom[2] += v1 * Q;
-                mom[3] += v2 * Q;
-                mom[4] += (v0 * v0 + v1 * v1 + v2 * v2) * Q;
-              }
-              gain[o] = Q;
-            }
+            gain[o] = Q;
           }
         });
     __syncthreads();
