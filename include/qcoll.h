@@ -188,8 +188,12 @@ int qcoll_step_rk(qcoll_plan_t plan, float* f, int64_t cells, double dt, double 
  * on one device; slots with cells[i] == 0 are skipped. status may be NULL.
  * 2D plans with N <= 32 share one launch per 8 such slots; 2D plans with
  * N > 32 (a workgroup per cell) get one launch each; 3D plans (all slots 3D)
- * share one launch per 8 slots; all launches of a call are queued on the same
- * stream. 2D and 3D plans cannot be mixed in
+ * share one launch per 8 slots. When a 2D call has several launches they run
+ * concurrently, the first on `stream` and the others on up to three side
+ * streams of the library (default priority) that wait for `stream` before
+ * they start and that `stream` waits for afterwards, so the call as a whole is
+ * ordered on `stream`; while `stream` is being captured into a graph they are
+ * queued on `stream` one after another. 2D and 3D plans cannot be mixed in
  * one call (QCOLL_EUNSUPPORTED). 3D plans hold a scratch area: calls that use
  * the same 3D plan must not run concurrently on different streams. */
 int qcoll_eval_multi(const qcoll_plan_t* plans, int nplans, const float* const* f, void* const* Q,

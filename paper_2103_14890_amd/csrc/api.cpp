@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <vector>
@@ -613,16 +614,28 @@ static int plan_create(qcoll_plan_t* out, int d, int n_per_dim, double L, int ke
   return QCOLL_OK;
 }
 
+// Host allocations of the plan builder and the batched calls may throw; no
+// exception crosses the C ABI (a failed allocation is QCOLL_ENOMEM).
+static int plan_create_nothrow(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, double gamma, double b,
+                               int M, int K_r, int precision, unsigned flags) {
+  try {
+    return plan_create(out, d, n_per_dim, L, kernel, gamma, b, M, K_r, precision, flags);
+  } catch (const std::bad_alloc&) {
+    if (out) *out = nullptr;
+    return QCOLL_ENOMEM;
+  }
+}
+
 int qcoll_plan(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, double b, int M,
                int K_r, int precision, unsigned flags) {
   if (kernel == QCOLL_VHS) return QCOLL_EINVAL;   // needs its exponent: qcoll_plan_vhs
-  return plan_create(out, d, n_per_dim, L, kernel, 1.0, b, M, K_r, precision, flags);
+  return plan_create_nothrow(out, d, n_per_dim, L, kernel, 1.0, b, M, K_r, precision, flags);
 }
 
 int qcoll_plan_vhs(qcoll_plan_t* out, int n_per_dim, double L, double gamma, double b, int M, int K_r,
                    int precision, unsigned flags) {
   if (!(gamma >= -1.0 && gamma <= 1.0)) return QCOLL_EINVAL;
-  return plan_create(out, 2, n_per_dim, L, QCOLL_VHS, gamma, b, M, K_r, precision, flags);
+  return plan_create_nothrow(out, 2, n_per_dim, L, QCOLL_VHS, gamma, b, M, K_r, precision, flags);
 }
 
 int qcoll_eval(qcoll_plan_t p, const float* f, void* Q, int64_t cells, hipStream_t stream) {
@@ -785,6 +798,84 @@ int qcoll_step_rk(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps
   return QCOLL_OK;
 }
 
+// Side streams of a device (default priority, created on first use and kept
+// until the process ends) for the independent launches of one batched call.
+constexpr int kSideStreams = 3;
+constexpr int kMaxDevices = 64;
+
+static hipStream_t side_stream(int dev, int k) {
+  static std::mutex mu;
+  static hipStream_t pool[kMaxDevices][kSideStreams] = {};
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!pool[dev][k]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess) pool[dev][k] = s;
+    if (cur != dev) hipSetDevice(cur);
+  }
+  return pool[dev][k];
+}
+
+// One launch of a batched 2D call: a tile-64 plan (a workgroup per cell) or a
+// slot table of plans with N <= 32.
+struct MultiJob {
+  bool tile64 = false;
+  qcoll::KernelArgs a;
+  qcoll::MultiArgs m;
+};
+
+// Run the launches of a batched call. They write disjoint outputs, so when
+// there are several they run concurrently: the first on the caller's stream,
+// the others on side streams that wait for the caller's stream and are waited
+// for by it (so the call is still ordered on the caller's stream as a whole).
+// Under graph capture they run one after another on the caller's stream.
+static int run_jobs(const std::vector<MultiJob>& jobs, int wpb, int dev, hipStream_t stream) {
+  auto run = [&](const MultiJob& j, hipStream_t s) {
+    return j.tile64 ? qcoll::launch_2d64(j.a, s) : qcoll::launch_multi(j.m, wpb, s);
+  };
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const bool fork = jobs.size() > 1 && hipStreamIsCapturing(stream, &cs) == hipSuccess &&
+                    cs == hipStreamCaptureStatusNone;
+  hipStream_t side[kSideStreams] = {};
+  int nside = 0;
+  if (fork) {
+    for (; nside < kSideStreams && nside + 1 < static_cast<int>(jobs.size()); ++nside) {
+      side[nside] = side_stream(dev, nside);
+      if (!side[nside]) break;
+    }
+  }
+  if (nside == 0) {
+    for (const MultiJob& j : jobs)
+      if (run(j, stream)) return QCOLL_EDEVICE;
+    return QCOLL_OK;
+  }
+  hipEvent_t start = nullptr;
+  if (hipEventCreateWithFlags(&start, hipEventDisableTiming) != hipSuccess) return QCOLL_EDEVICE;
+  int rc = hipEventRecord(start, stream) == hipSuccess ? QCOLL_OK : QCOLL_EDEVICE;
+  for (int k = 0; k < nside && rc == QCOLL_OK; ++k)
+    if (hipStreamWaitEvent(side[k], start, 0) != hipSuccess) rc = QCOLL_EDEVICE;
+  // job 0 and every (nside + 1)-th job after it on the caller's stream, the others round-robin
+  for (size_t i = 0; i < jobs.size() && rc == QCOLL_OK; ++i) {
+    const int lane = static_cast<int>(i % (nside + 1));
+    if (run(jobs[i], lane == 0 ? stream : side[lane - 1])) rc = QCOLL_EDEVICE;
+  }
+  for (int k = 0; k < nside; ++k) {  // join (also after an error, so no side work is left unordered)
+    hipEvent_t done = nullptr;
+    if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) {
+      rc = QCOLL_EDEVICE;
+      continue;
+    }
+    if (hipEventRecord(done, side[k]) != hipSuccess || hipStreamWaitEvent(stream, done, 0) != hipSuccess)
+      rc = QCOLL_EDEVICE;
+    hipEventDestroy(done);
+  }
+  hipEventDestroy(start);
+  return rc;
+}
+
 // Shared by qcoll_eval_multi and qcoll_step_multi: validate the slot list and
 // build the batched launch (one workgroup per waves_per_block cells of a slot).
 static int multi_launch(const qcoll_plan_t* plans, int nplans, const float* const* f, void* const* Q,
@@ -835,6 +926,7 @@ static int multi_launch(const qcoll_plan_t* plans, int nplans, const float* cons
     if (ns == 0) return QCOLL_OK;
     return launch3(pl, sl, ns, cs, stream) ? QCOLL_EDEVICE : QCOLL_OK;
   }
+  std::vector<MultiJob> jobs;
   for (int i = 0; i < nplans; ++i) {
     if (cells[i] == 0) continue;
     const qcoll_plan_s* p = plans[i];
@@ -850,13 +942,16 @@ static int multi_launch(const qcoll_plan_t* plans, int nplans, const float* cons
       a.q = Q[i];
       a.out_kind = (p->flags & QCOLL_CONSERVE) ? 1 : 0;
     }
-    if (p->tile == 64) {  // one workgroup per cell: a launch of its own on the same stream
-      if (qcoll::launch_2d64(a, stream)) return QCOLL_EDEVICE;
+    if (p->tile == 64) {  // one workgroup per cell: a launch of its own
+      jobs.emplace_back();
+      jobs.back().tile64 = true;
+      jobs.back().a = a;
       continue;
     }
-    if (m.nslots == qcoll::kMaxSlots) {  // slot table full: launch it and start the next
+    if (m.nslots == qcoll::kMaxSlots) {  // slot table full: queue it and start the next
       m.block_start[m.nslots] = blocks;
-      if (qcoll::launch_multi(m, wpb, stream)) return QCOLL_EDEVICE;
+      jobs.emplace_back();
+      jobs.back().m = m;
       m = qcoll::MultiArgs();
       blocks = 0;
     }
@@ -866,19 +961,31 @@ static int multi_launch(const qcoll_plan_t* plans, int nplans, const float* cons
     ++m.nslots;
   }
   m.block_start[m.nslots] = blocks;
-  if (m.nslots == 0) return QCOLL_OK;
-  return qcoll::launch_multi(m, wpb, stream) ? QCOLL_EDEVICE : QCOLL_OK;
+  if (m.nslots > 0) {
+    jobs.emplace_back();
+    jobs.back().m = m;
+  }
+  if (jobs.empty()) return QCOLL_OK;
+  return run_jobs(jobs, wpb, dev, stream);
 }
 
 int qcoll_eval_multi(const qcoll_plan_t* plans, int nplans, const float* const* f, void* const* Q,
                      const int64_t* cells, hipStream_t stream) {
-  return multi_launch(plans, nplans, f, Q, cells, false, 0.0, 0.0, 0, nullptr, stream);
+  try {
+    return multi_launch(plans, nplans, f, Q, cells, false, 0.0, 0.0, 0, nullptr, stream);
+  } catch (const std::bad_alloc&) {
+    return QCOLL_ENOMEM;
+  }
 }
 
 int qcoll_step_multi(const qcoll_plan_t* plans, int nplans, float* const* f, const int64_t* cells, double dt,
                      double eps, int scheme, int32_t* const* status, hipStream_t stream) {
-  return multi_launch(plans, nplans, const_cast<const float* const*>(f), nullptr, cells, true, dt, eps, scheme,
-                      status, stream);
+  try {
+    return multi_launch(plans, nplans, const_cast<const float* const*>(f), nullptr, cells, true, dt, eps, scheme,
+                        status, stream);
+  } catch (const std::bad_alloc&) {
+    return QCOLL_ENOMEM;
+  }
 }
 
 // Eight wavefronts per workgroup select the ping-pong variant of the FX16

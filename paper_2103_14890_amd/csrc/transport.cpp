@@ -364,9 +364,25 @@ void release(qcoll_transport_s* t) {
 
 extern "C" {
 
+static int transport_plan_create(qcoll_transport_t* out, int64_t cells, const int64_t* cell_ptr,
+                                 const double* verts, const int64_t* nbr, const double* shift, const int64_t* twin,
+                                 const double* gen, int degree, int n_per_dim, double L, unsigned flags);
+
+// No exception crosses the C ABI: a failed host allocation is QCOLL_ENOMEM.
 int qcoll_transport_plan(qcoll_transport_t* out, int64_t cells, const int64_t* cell_ptr, const double* verts,
                          const int64_t* nbr, const double* shift, const int64_t* twin, const double* gen,
                          int degree, int n_per_dim, double L, unsigned flags) {
+  try {
+    return transport_plan_create(out, cells, cell_ptr, verts, nbr, shift, twin, gen, degree, n_per_dim, L, flags);
+  } catch (const std::bad_alloc&) {
+    if (out) *out = nullptr;
+    return QCOLL_ENOMEM;
+  }
+}
+
+static int transport_plan_create(qcoll_transport_t* out, int64_t cells, const int64_t* cell_ptr,
+                                 const double* verts, const int64_t* nbr, const double* shift, const int64_t* twin,
+                                 const double* gen, int degree, int n_per_dim, double L, unsigned flags) {
   if (!out) return QCOLL_EINVAL;
   *out = nullptr;
   if (cells < 1 || cells > (int64_t(1) << 30) || !cell_ptr || !verts || !nbr || !shift || !twin || !gen)

@@ -12,7 +12,9 @@ by side on one GPU:
     device pool (one plan per group); f stays on the device between steps;
   * scheduling: every tick advances every live request by one step in ONE
     batched launch over all groups (qcoll_step_multi), then retires finished
-    requests (copy to host, compaction of the pool) and admits waiting ones;
+    requests (copy to pinned host memory, compaction of the pool) and admits
+    waiting ones; the host work of tick k + 1 overlaps the device work of
+    tick k (flags and results are read one tick later);
   * faults: a cell whose update became non-finite is flagged by the kernel
     and evicted without affecting the others.
 
@@ -96,6 +98,7 @@ class Server:
         self.peak_bytes = 0
         self.ticks = 0
         self.cell_steps = 0
+        self._pending = None               # the previous tick, completed by the next tick or flush()
         self._admit_time: dict[int, float] = {}
 
     # ----------------------------------------------------------- admission
@@ -131,43 +134,88 @@ class Server:
             self.results[req.rid] = Result(req.rid, None, req.arrival, now, float("nan"))
 
     # ---------------------------------------------------------------- tick
+    def _compact(self, g: _Group, gone: list[int]) -> None:
+        """Free slots `gone` of group g: move the last live slots into the holes
+        (device copies, ordered on the stream after everything queued so far)."""
+        for i in sorted(gone, reverse=True):
+            last = len(g.live) - 1
+            if i != last:
+                g.pool[i].copy_(g.pool[last])
+                g.live[i], g.left[i] = g.live[last], g.left[last]
+            g.live.pop()
+            g.left.pop()
+            self.bytes_live -= 4 * g.N * g.N
+
     def tick(self, clock) -> int:
-        """One batched step of every live request; returns the number retired."""
+        """One batched step of every live request. The step's status flags and
+        the results of the requests it finishes are copied to pinned host
+        memory asynchronously and handed out by the next tick (or flush()), so
+        the host prepares tick k + 1 while the device runs tick k. Returns the
+        number of requests retired by the previous tick."""
         import torch
         groups = [g for g in self.groups.values() if g.live]
-        if not groups:
+        new = None
+        if groups:
+            plans = [g.plan for g in groups]
+            fs = [g.pool[:len(g.live)] for g in groups]
+            st = [g.status[:len(g.live)] for g in groups]
+            qcoll.step_multi(plans, fs, self.dt, self.eps, self.scheme, st)
+            self.ticks += 1
+            self.cell_steps += sum(len(g.live) for g in groups)
+            allf = torch.cat(st)
+            flags = torch.empty(allf.shape, dtype=torch.int32, pin_memory=True)
+            flags.copy_(allf, non_blocking=True)
+            slots = [(g, list(g.live)) for g in groups]   # request of each slot in this step
+            finished = []
+            for g in groups:
+                for i in range(len(g.live)):
+                    g.left[i] -= 1
+                done = [i for i in range(len(g.live)) if g.left[i] <= 0]
+                if not done:
+                    continue
+                host = torch.empty((len(done), g.N, g.N), dtype=torch.float32, pin_memory=True)
+                for j, i in enumerate(done):
+                    host[j].copy_(g.pool[i], non_blocking=True)
+                    finished.append((g.live[i], host, j))
+                self._compact(g, done)
+            ev = torch.cuda.Event()
+            ev.record()
+            new = (ev, flags, slots, finished)
+        retired = self.flush(clock)
+        self._pending = new
+        return retired
+
+    def flush(self, clock) -> int:
+        """Complete the previous tick: wait for it, hand out the results of the
+        requests it finished and evict live requests that its status flags mark
+        non-finite (a non-finite cell stays non-finite, so a request that
+        finished since is flagged again by its own last step). Returns the number
+        of requests retired."""
+        p, self._pending = self._pending, None
+        if p is None:
             return 0
-        plans = [g.plan for g in groups]
-        fs = [g.pool[:len(g.live)] for g in groups]
-        st = [g.status[:len(g.live)] for g in groups]
-        qcoll.step_multi(plans, fs, self.dt, self.eps, self.scheme, st)
-        self.ticks += 1
-        self.cell_steps += sum(len(g.live) for g in groups)
-        flags = [s.cpu().numpy() for s in st]   # synchronises with the step
-        retired = 0
-        for g, fl in zip(groups, flags):
-            done = [i for i in range(len(g.live)) if g.left[i] <= 1 or fl[i] != 0]
-            for i in range(len(g.live)):
-                g.left[i] -= 1
-            if not done:
-                continue
-            host = g.pool[:len(g.live)][torch.tensor(done, device=g.pool.device)].cpu().numpy()
-            now = clock()
-            for j, i in enumerate(done):
+        ev, flags, slots, finished = p
+        ev.synchronize()
+        now = clock()
+        fl = flags.numpy()
+        bad, k = set(), 0
+        for g, rids in slots:
+            bad.update(rid for i, rid in enumerate(rids) if fl[k + i] != 0)
+            k += len(rids)
+        for rid, host, j in finished:
+            r = self.results[rid]
+            r.failed = rid in bad
+            r.f = None if r.failed else host[j].numpy().copy()
+            r.done = now
+        retired = len(finished)
+        for g, rids in slots:
+            gone = [g.live.index(rid) for rid in rids if rid in bad and rid in g.live]
+            for i in gone:
                 r = self.results[g.live[i]]
-                r.failed = bool(fl[i] != 0)
-                r.f = None if r.failed else host[j]
-                r.done = now
-            # compaction: move the last live slots into the holes
-            for i in sorted(done, reverse=True):
-                last = len(g.live) - 1
-                if i != last:
-                    g.pool[i].copy_(g.pool[last])
-                    g.live[i], g.left[i] = g.live[last], g.left[last]
-                g.live.pop()
-                g.left.pop()
-                self.bytes_live -= 4 * g.N * g.N
-                retired += 1
+                r.failed, r.f, r.done = True, None, now
+            if gone:
+                self._compact(g, gone)
+                retired += len(gone)
         return retired
 
     # ----------------------------------------------------------------- run
@@ -188,7 +236,7 @@ class Server:
                 self.submit(reqs[i])
                 i += 1
             self._try_admit(now)
-            if any(g.live for g in self.groups.values()):
+            if any(g.live for g in self.groups.values()) or self._pending is not None:
                 ts = time.monotonic()
                 pending -= self.tick(clock if realtime else (lambda: vclock[0]))
                 if not realtime:

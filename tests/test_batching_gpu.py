@@ -48,6 +48,31 @@ def test_eval_multi_bitwise_equals_single_launches(qc):
         p.close()
 
 
+def test_concurrent_launches_stay_ordered_on_the_callers_stream(qc):
+    """Six launches in one call (five tile-64 plans and one slot table) run on
+    the caller's stream and side streams; work queued on the caller's stream
+    after the call (no host synchronisation in between) sees every result."""
+    cfg = [(64, 8.0, "hard_sphere", 8, 3), (48, 8.0, "maxwell", 8, 2), (64, 10.0, "maxwell", 16, 2),
+           (40, 8.0, "hard_sphere", 8, 1), (48, 6.0, "hard_sphere", 8, 3), (32, 8.0, "hard_sphere", 8, 70)]
+    plans, fs = [], []
+    for i, (N, L, kern, M, cells) in enumerate(cfg):
+        plans.append(qc.Plan(2, N, L, kern, M, precision="fx16"))
+        fs.append(torch.tensor(wl.mixture_cells(2, N, L, cells, 300 + i), dtype=torch.float32, device="cuda"))
+    singles = [p.eval(f) for p, f in zip(plans, fs)]
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        outs = [torch.full_like(x, float("nan")) for x in singles]
+        qc.eval_multi(plans, fs, outs, stream=side)
+        copies = [o.clone() for o in outs]          # queued behind the call on the same stream
+    torch.cuda.synchronize()
+    for a, b in zip(singles, copies):
+        assert torch.equal(a, b)
+    for p in plans:
+        p.close()
+
+
 @pytest.mark.parametrize("scheme", ["explicit", "imex"])
 def test_step_multi_bitwise_equals_single_launches(qc, scheme):
     plans, fs = _setup(qc, seed=7)
