@@ -34,10 +34,15 @@ WORKLOADS = {
 }
 # 3D workload: two resolutions in one launch (FP32 MFMA, FP64 projection)
 WORKLOADS_3D = {
-    "hs3d": (("hs3d_32", 32), ("hs3d_16", 16), 8.0, "hard_sphere", 32,
+    # name: ((input, N, precision), (input, N, precision), L, kernel, M, description)
+    "hs3d": (("hs3d_32", 32, "fp32"), ("hs3d_16", 16, "fp32"), 8.0, "hard_sphere", 32,
              "8192 cells on a 32^3 grid + 8192 cells on a 16^3 grid, [-8,8]^3, hard spheres, M=32 "
              "hemisphere directions (33 transforms), FP32 DFT-GEMMs, FP64 conservation projection, "
              "both resolutions in one launch"),
+    "hs3d_fx16": (("hs3d_32", 32, "fx16"), ("hs3d_16", 16, "fp32"), 8.0, "hard_sphere", 32,
+                  "the hs3d cells (8192 x 32^3 + 8192 x 16^3, hard spheres, M=32) in one call, the 32^3 "
+                  "cells with split-FP16 (FX16) DFT-GEMMs, the 16^3 cells with FP32 ones, FP64 "
+                  "conservation projection"),
 }
 HBM_PEAK = 8.0e12           # B/s
 FP32_VALU_PEAK = 157.3e12   # FP32 vector FLOP/s (256 CUs x 2.4 GHz x 256 flop/clk)
@@ -73,6 +78,7 @@ def mfma_flops_per_cell_3d(T: int, transforms: int) -> float:
 
 # Source file of the dominant kernel of each workload.
 KERNEL_SOURCE = {"hs2d_32": "kernels_2d.hip", "hs2d_64_noisy": "kernels_2d64.hip", "hs3d": "kernels_3d.hip",
+                 "hs3d_fx16": "kernels_3d.hip",
                  "explosion_16k": "kernels_transport.hip", "galerkin_32": "kernels_2d64.hip",
                  "classical_16": "kernels_classical.hip", "vhs2d_32": "kernels_2d.hip"}
 
@@ -215,13 +221,13 @@ def bench_3d(args) -> int:
     from oracle import spectral as sp
     from paper_2103_14890_amd import qcoll
 
-    (name_a, Na), (name_b, Nb), L, kern, M, desc = WORKLOADS_3D[args.workload]
+    (name_a, Na, prec_a), (name_b, Nb, prec_b), L, kern, M, desc = WORKLOADS_3D[args.workload]
     dev = torch.device("cuda:0")
     fa64, fb64 = wl.config_inputs(name_a), wl.config_inputs(name_b)
     fa = torch.tensor(fa64, dtype=torch.float32, device=dev)
     fb = torch.tensor(fb64, dtype=torch.float32, device=dev)
-    pa = qcoll.Plan(3, Na, L, kern, M, precision="fp32", conserve=True)
-    pb = qcoll.Plan(3, Nb, L, kern, M, precision="fp32", conserve=True)
+    pa = qcoll.Plan(3, Na, L, kern, M, precision=prec_a, conserve=True)
+    pb = qcoll.Plan(3, Nb, L, kern, M, precision=prec_b, conserve=True)
     qa = torch.empty(fa.shape, dtype=torch.float64, device=dev)
     qb = torch.empty(fb.shape, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
@@ -246,7 +252,17 @@ def bench_3d(args) -> int:
     del ga, gb
     copy_calibration(args.calibrate_copy, dev)
     tr = pa.info()["transforms"]
-    flops = (mfma_flops_per_cell_3d(32, tr) * fa.shape[0] + mfma_flops_per_cell_3d(16, tr) * fb.shape[0])
+    if prec_a == "fx16":
+        # the FX16 kernel (the 32^3 cells, a launch of its own) timed alone; six
+        # FP16 products per FP32-equivalent one
+        _, per_a = time_launches(lambda: pa.eval(fa, qa), max(2, args.steps // 2), 1, stream)
+        T_roof = float(np.mean(per_a))
+        flops = 6 * mfma_flops_per_cell_3d(32, tr) * fa.shape[0]
+        peak = FP16_MFMA_PEAK
+    else:
+        T_roof = T_
+        flops = (mfma_flops_per_cell_3d(32, tr) * fa.shape[0] + mfma_flops_per_cell_3d(16, tr) * fb.shape[0])
+        peak = FP32_MFMA_PEAK
 
     # oracle on a bounded sample: equal numbers of cells of both resolutions
     sa, sb = sp.Setup(d=3, N=Na, L=L, kernel=kern, M=M), sp.Setup(d=3, N=Nb, L=L, kernel=kern, M=M)
@@ -265,7 +281,7 @@ def bench_3d(args) -> int:
     qa_h = qa.cpu().numpy()
     mass = float((np.abs(qa_h.sum(axis=(1, 2, 3))) / np.abs(qa_h).sum(axis=(1, 2, 3))).max())
     out = {
-        "metric": "cell Q(f,f) evals/s, 3D hard spheres, 32^3 and 16^3 cells in one launch",
+        "metric": "cell Q(f,f) evals/s, 3D hard spheres, 32^3 and 16^3 cells in one call",
         "value": cells / T_,
         "unit": "cell-evals/s",
         "n_gpus": 1,
@@ -275,12 +291,12 @@ def bench_3d(args) -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f16x6+f32+f64" if prec_a == "fx16" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "cells": cells, "N_v": [f"{Na}^3", f"{Nb}^3"],
                    "kernel": kern, "M": M},
-        "roofline": {"bound": "mfma", "achieved": flops / T_ / 1e12, "peak": FP32_MFMA_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": flops / T_ / FP32_MFMA_PEAK,
+        "roofline": {"bound": "mfma", "achieved": flops / T_roof / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": flops / T_roof / peak,
                      "traffic": measured_traffic(args.workload)},
         "cpu_baseline": {"value": 2 * done / t_cpu, "unit": "cell-evals/s", "cores": 1, "kind": "oracle",
                          "sample": f"first {done} cells of each resolution, FP64 numpy FFT oracle + projection, "

@@ -369,26 +369,49 @@ int build_device_3d(qcoll_plan_s* p) {
   const auto& hp = p->hp;
   const int n = hp.N, T = p->tile, KS = 64 / T, NS = T / KS;
   const int P = static_cast<int>(hp.packed.size());
-  std::vector<float> ec(static_cast<size_t>(64) * 3 * NS);
-  for (int lane = 0; lane < 64; ++lane) {
-    const int x = lane % T, jl = lane / T;
-    for (int st = 0; st < NS; ++st) {
-      const int j = KS * st + jl;
-      double c = 0.0, sn = 0.0;
-      if (x < n && j < n) {
-        const double ang = 2.0 * kPi * static_cast<double>((x * j) % n) / n;
-        c = std::cos(ang);
-        sn = std::sin(ang);
-      }
-      ec[(lane * 3 + 0) * NS + st] = static_cast<float>(c);
-      ec[(lane * 3 + 1) * NS + st] = static_cast<float>(sn);
-      ec[(lane * 3 + 2) * NS + st] = static_cast<float>(-sn);
+  // DFT-matrix value e(x, j) for matrix m (cos, sin, -sin of 2 pi x j / n), zero
+  // outside the n x n grid
+  auto emat = [&](int m, int x, int j) -> double {
+    if (x >= n || j >= n) return 0.0;
+    const double ang = 2.0 * kPi * static_cast<double>((x * j) % n) / n;
+    return m == 0 ? std::cos(ang) : (m == 1 ? std::sin(ang) : -std::sin(ang));
+  };
+  int rc;
+  if (p->precision == QCOLL_MIX_FX16) {
+    // [m][K half i][part: lead, hi, lo][lane][slot]: 2^9 e(x, j) split into an
+    // integer lead and the FP16 hi and lo of the remainder, x = lane % 32,
+    // j = 2 (8 i + slot) + lane / 32 (T = 32)
+    std::vector<_Float16> et(static_cast<size_t>(3) * 2 * 3 * 64 * 8);
+    for (int m = 0; m < 3; ++m)
+      for (int i = 0; i < 2; ++i)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int sl = 0; sl < 8; ++sl) {
+            const double y = 512.0 * emat(m, lane % 32, 2 * (8 * i + sl) + lane / 32);
+            const double lead = std::nearbyint(y);
+            const float r = static_cast<float>(y - lead);
+            const _Float16 hi = static_cast<_Float16>(r);
+            const _Float16 lo = static_cast<_Float16>(r - static_cast<float>(hi));
+            const size_t base = ((static_cast<size_t>(m) * 2 + i) * 3 * 64 + lane) * 8 + sl;
+            et[base] = static_cast<_Float16>(static_cast<float>(lead));
+            et[base + 64 * 8] = hi;
+            et[base + 2 * 64 * 8] = lo;
+          }
+    _Float16* d = nullptr;
+    rc = upload(et, &d, p->device_bytes);
+    p->econst = d;
+    if (rc) return rc;
+  } else {
+    std::vector<float> ec(static_cast<size_t>(64) * 3 * NS);
+    for (int lane = 0; lane < 64; ++lane) {
+      const int x = lane % T, jl = lane / T;
+      for (int st = 0; st < NS; ++st)
+        for (int m = 0; m < 3; ++m) ec[(lane * 3 + m) * NS + st] = static_cast<float>(emat(m, x, KS * st + jl));
     }
+    float* d = nullptr;
+    rc = upload(ec, &d, p->device_bytes);
+    p->econst = d;
+    if (rc) return rc;
   }
-  float* d = nullptr;
-  int rc = upload(ec, &d, p->device_bytes);
-  p->econst = d;
-  if (rc) return rc;
   const int64_t T3 = static_cast<int64_t>(T) * T * T;
   std::vector<float> ft(static_cast<size_t>(P + 1) * T3 * 2, 0.0f);
   for (int q = 0; q <= P; ++q)
@@ -421,7 +444,12 @@ qcoll::Slot3 make_slot3(const qcoll_plan_s* p) {
   a.n = p->hp.N;
   a.T = p->tile;
   a.P = static_cast<int>(p->hp.packed.size());
-  a.econst = static_cast<const float*>(p->econst);
+  if (p->precision == QCOLL_MIX_FX16) {
+    a.fx16 = 1;
+    a.etab16 = p->econst;
+  } else {
+    a.econst = static_cast<const float*>(p->econst);
+  }
   a.filt = p->filt3;
   for (int i = 0; i < 25 && i < static_cast<int>(p->hp.gram_inv.size()); ++i) a.gram_inv[i] = p->hp.gram_inv[i];
   a.L = p->hp.L;
@@ -506,7 +534,7 @@ void classical_table(const qcoll::HostPlan& src, std::vector<double>& beta) {
 }
 
 bool device_supported(const qcoll::HostPlan& hp, int precision) {
-  if (hp.d == 3) return hp.N <= 32 && precision == QCOLL_FP32;
+  if (hp.d == 3) return hp.N <= 32 && (precision == QCOLL_FP32 || (precision == QCOLL_MIX_FX16 && hp.N > 16));
   if (hp.d != 2) return false;
   if (hp.N <= 32) return true;
   return hp.N <= 64 && precision == QCOLL_MIX_FX16;

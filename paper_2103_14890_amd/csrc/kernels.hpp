@@ -62,7 +62,9 @@ struct Slot3 {
   int n = 0;                    // grid points per axis (<= T)
   int T = 32;                   // tile edge: 16 or 32 (zero padding up to T)
   int P = 0;                    // gain transforms; entry P of filt is the loss multiplier
-  const float* econst = nullptr;  // [64 lanes][cos, sin, -sin][T/(64/T) steps]
+  const float* econst = nullptr;  // FP32: [64 lanes][cos, sin, -sin][T/(64/T) steps]
+  int fx16 = 0;                   // 1: FX16 DFT-GEMMs (T = 32) with the table etab16
+  const void* etab16 = nullptr;   // FX16: [cos, sin, -sin][K half][lead, hi, lo][64 lanes][8] FP16
   const float* filt = nullptr;    // [P+1][T^3][re, im], modes in FFT order per axis
   double gram_inv[25] = {};     // inverse Gram matrix of (1, v1, v2, v3, |v|^2)
   double L = 0, dv = 0;

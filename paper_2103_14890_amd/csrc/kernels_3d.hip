@@ -97,6 +97,114 @@ __device__ __forceinline__ void tile_dft(const Emat<T>& E, const float* xr, cons
   }
 }
 
+// ---- FX16 variant of a 32 x 32 tile pass. The DFT-matrix operands are held
+// as three-part FP16 splits of 2^9 e (a lead on the integer grid, hi and lo of
+// the remainder) in a workgroup LDS table [cos, sin, -sin][K half][part][lane];
+// the tile's data are scaled by a power of two so that |x| < 2^9 and split the
+// same way. Six products per operand pair on v_mfma_f32_32x32x16_f16: the lead
+// products, exact in FP32, in one accumulator, the five corrections in a
+// second. Slot j of K half i on lane l carries the point 2 (8 i + j) + l / 32,
+// i.e. step s = 8 i + j of the FP32 layout, so the data arrays of that layout
+// are packed without moving between lanes, and the result tile has the FP32
+// kernel's layout.
+constexpr int kEtabHalf8 = 3 * 2 * 3 * 64;   // 18 KB of LDS
+
+struct EmatFx {
+  const half8* tab;   // the LDS table
+};
+
+template <int T, bool FX>
+struct EmatOf {
+  typedef Emat<T> type;
+};
+template <>
+struct EmatOf<32, true> {
+  typedef EmatFx type;
+};
+
+__device__ __forceinline__ f32x16 mfma_h(half8 a, half8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+
+// acc0 += a.l b.l (exact); acc1 += the five remaining products.
+__device__ __forceinline__ void mma6_3d(const Split3& a, const Split3& b, f32x16& acc0, f32x16& acc1) {
+  acc0 = mfma_h(a.l, b.l, acc0);
+  acc1 = mfma_h(a.l, b.h, acc1);
+  acc1 = mfma_h(a.h, b.l, acc1);
+  acc1 = mfma_h(a.l, b.o, acc1);
+  acc1 = mfma_h(a.h, b.h, acc1);
+  acc1 = mfma_h(a.o, b.l, acc1);
+}
+
+__device__ __forceinline__ Split3 etab_load(const EmatFx& E, int m, int i, int lane) {
+  const half8* q = E.tab + ((m * 2 + i) * 3) * 64 + lane;
+  Split3 r;
+  r.l = q[0];
+  r.h = q[64];
+  r.o = q[128];
+  return r;
+}
+
+// ya, yb scaled so that |y| < 2^9 (FP32 inputs: the split is exact).
+__device__ __forceinline__ P3 split2_f32(float ya, float yb) {
+  const float na = __builtin_rintf(ya), nb = __builtin_rintf(yb);
+  return finish_pair(na, nb, ya - na, yb - nb);
+}
+
+template <int T, bool DB, bool INV, bool REAL_IN>
+__device__ __forceinline__ void tile_dft(const EmatFx& E, const float* xr, const float* xi, f32x16& dr,
+                                         f32x16& di) {
+  static_assert(T == 32, "the FX16 tile pass is 32 x 32");
+  float m = 0.0f;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    m = fmaxf(m, fabsf(xr[s]));
+    if (!REAL_IN) m = fmaxf(m, fabsf(xi[s]));
+  }
+  m = wave_max(m);
+  const int sa = 9 - exp_above(m);
+  const float c = ldexpf(1.0f, sa);
+  Split3 Xr[2], Xi[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; j += 2) {
+      put2(Xr[i], j, split2_f32(xr[8 * i + j] * c, xr[8 * i + j + 1] * c));
+      if (!REAL_IN) put2(Xi[i], j, split2_f32(xi[8 * i + j] * c, xi[8 * i + j + 1] * c));
+    }
+  int lane = threadIdx.x & 63;
+  asm volatile("" : "+v"(lane));
+  f32x16 r0{}, r1{}, i0{}, i1{};
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const Split3 C = etab_load(E, 0, i, lane);
+    const Split3 Si = etab_load(E, INV ? 1 : 2, i, lane);  // multiplies xr in the imaginary part
+    if (DB) {
+      mma6_3d(C, Xr[i], r0, r1);
+      mma6_3d(Si, Xr[i], i0, i1);
+    } else {
+      mma6_3d(Xr[i], C, r0, r1);
+      mma6_3d(Xr[i], Si, i0, i1);
+    }
+    if (!REAL_IN) {
+      const Split3 Sr = etab_load(E, INV ? 2 : 1, i, lane);  // multiplies xi in the real part
+      if (DB) {
+        mma6_3d(Sr, Xi[i], r0, r1);
+        mma6_3d(C, Xi[i], i0, i1);
+      } else {
+        mma6_3d(Xi[i], Sr, r0, r1);
+        mma6_3d(Xi[i], C, i0, i1);
+      }
+    }
+  }
+  const float inv = ldexpf(1.0f, -(sa + 9));
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    dr[v] = (r0[v] + r1[v]) * inv;
+    di[v] = (i0[v] + i1[v]) * inv;
+  }
+}
+
 // Sum over the workgroup (four wavefronts) of K values per thread.
 template <int K>
 __device__ __forceinline__ void block_sum(double* x, double* red) {
@@ -126,8 +234,8 @@ __device__ __forceinline__ void block_sum(double* x, double* red) {
 // tile's inputs loaded while the current tile's MFMAs run. load(t, xr, xi)
 // fetches a tile's inputs, store(t, dr, di) disposes of its outputs; tiles of
 // one wavefront touch disjoint lines, so prefetching ahead of the stores is safe.
-template <int T, bool DB, bool INV, bool REAL_IN, class Load, class Store>
-__device__ __forceinline__ void pass_tiles(const Emat<T>& E, int w, Load load, Store store) {
+template <int T, bool DB, bool INV, bool REAL_IN, class EM, class Load, class Store>
+__device__ __forceinline__ void pass_tiles(const EM& E, int w, Load load, Store store) {
   using S = Sh<T>;
   float ar[S::NS], ai[S::NS], br[S::NS], bi[S::NS];
   load(w, ar, ai);
@@ -152,8 +260,8 @@ __device__ __forceinline__ void pass_tiles(const Emat<T>& E, int w, Load load, S
 // field, so the field is read once and never written between the two passes.
 // load(t, xr, xi) fetches plane t's axis-1 inputs (the next plane's while the
 // current one computes); store(t, dr, di) disposes of the axis-2 outputs.
-template <int T, class Load, class Store>
-__device__ __forceinline__ void plane_passes(const Emat<T>& E, int w, float2* plane, Load load, Store store) {
+template <int T, class EM, class Load, class Store>
+__device__ __forceinline__ void plane_passes(const EM& E, int w, float2* plane, Load load, Store store) {
   using S = Sh<T>;
   float ar[S::NS], ai[S::NS], br[S::NS], bi[S::NS];
   load(w, ar, ai);
@@ -191,8 +299,8 @@ __device__ __forceinline__ void plane_passes(const Emat<T>& E, int w, float2* pl
 // first field, prefetched during the current one), the products Re * Im of
 // the group summed in FP64 registers; store(t, g) receives the plane's sum, so
 // the FP64 gain is read and written once per group.
-template <int T, class Load, class Store>
-__device__ __forceinline__ void plane_passes_group(const Emat<T>& E, int w, float2* plane, int g, Load load,
+template <int T, class EM, class Load, class Store>
+__device__ __forceinline__ void plane_passes_group(const EM& E, int w, float2* plane, int g, Load load,
                                                    Store store) {
   using S = Sh<T>;
   float ar[S::NS], ai[S::NS], br[S::NS], bi[S::NS];
@@ -235,8 +343,9 @@ __device__ __forceinline__ void plane_passes_group(const Emat<T>& E, int w, floa
   }
 }
 
-template <int T>
-__device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red, float2* plane) {
+template <int T, bool FX>
+__device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red, float2* plane,
+                        const half8* etab) {
   using S = Sh<T>;
   constexpr int T2 = T * T, T3 = T * T * T;
   const int w = threadIdx.x >> 6;
@@ -249,8 +358,11 @@ __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red
   auto wfield = [&](int f) { return f == 0 ? work : work_g + static_cast<int64_t>(f - 1) * T3; };
   const float* fc = a.f + cell * static_cast<int64_t>(n) * n * n;
 
-  Emat<T> E;
-  {
+  typename EmatOf<T, FX>::type E;
+  if constexpr (FX) {
+    E.tab = etab;
+  } else {
+    (void)etab;
     const int lane = threadIdx.x & 63;
     const float* src = a.econst + lane * 3 * S::NS;
 #pragma unroll
@@ -591,19 +703,64 @@ __global__ __launch_bounds__(256) void fp32_3d_kernel(Args3 A) {
     while (s + 1 < A.nslots && g >= A.cell_start[s + 1]) ++s;
     const Slot3& a = A.slot[s];
     const int64_t cell = g - A.cell_start[s];
-    if (a.T == 32) cell_3d<32>(a, cell, scratch, red, plane);
-    else cell_3d<16>(a, cell, scratch, red, plane);
+    if (a.T == 32) cell_3d<32, false>(a, cell, scratch, red, plane, nullptr);
+    else cell_3d<16, false>(a, cell, scratch, red, plane, nullptr);
+  }
+}
+
+// FX16 slots (32^3 tiles): the LDS table of DFT-matrix splits is reloaded when
+// a workgroup moves to a slot of another plan.
+__global__ __launch_bounds__(256) void fx16_3d_kernel(Args3 A) {
+  __shared__ double red[32];
+  __shared__ float2 plane_lds[4][32 * 32];
+  __shared__ half8 etab_lds[kEtabHalf8];
+  float2* plane = plane_lds[threadIdx.x >> 6];
+  char* scratch = A.scratch + static_cast<int64_t>(blockIdx.x) * A.scratch_stride;
+  const int64_t total = A.cell_start[A.nslots];
+  const void* loaded = nullptr;
+  for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    int s = 0;
+#pragma unroll 1
+    while (s + 1 < A.nslots && g >= A.cell_start[s + 1]) ++s;
+    const Slot3& a = A.slot[s];
+    const int64_t cell = g - A.cell_start[s];
+    if (a.etab16 != loaded) {  // the previous cell ended with a workgroup barrier
+      const half8* src = static_cast<const half8*>(a.etab16);
+      for (int i = threadIdx.x; i < kEtabHalf8; i += blockDim.x) etab_lds[i] = src[i];
+      __syncthreads();
+      loaded = a.etab16;
+    }
+    cell_3d<32, true>(a, cell, scratch, red, plane, etab_lds);
   }
 }
 
 }  // namespace
 
+// FP32 and FX16 slots go to their own kernels, one launch each (in that order,
+// on the same stream: they share the scratch area).
 int launch_3d(const Args3& args, hipStream_t stream) {
-  const int64_t total = args.cell_start[args.nslots];
-  if (total <= 0) return 0;
-  int64_t blocks = total < args.blocks ? total : args.blocks;
-  hipLaunchKernelGGL(fp32_3d_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, args);
-  return hipGetLastError() == hipSuccess ? 0 : -3;
+  for (int fx = 0; fx < 2; ++fx) {
+    Args3 sub;
+    sub.scratch = args.scratch;
+    sub.scratch_stride = args.scratch_stride;
+    sub.blocks = args.blocks;
+    for (int i = 0; i < args.nslots; ++i) {
+      if ((args.slot[i].fx16 != 0) != (fx != 0)) continue;
+      sub.slot[sub.nslots] = args.slot[i];
+      sub.cell_start[sub.nslots + 1] =
+          sub.cell_start[sub.nslots] + (args.cell_start[i + 1] - args.cell_start[i]);
+      ++sub.nslots;
+    }
+    const int64_t total = sub.cell_start[sub.nslots];
+    if (total <= 0) continue;
+    const int64_t blocks = total < sub.blocks ? total : sub.blocks;
+    if (fx)
+      hipLaunchKernelGGL(fx16_3d_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, sub);
+    else
+      hipLaunchKernelGGL(fp32_3d_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, sub);
+    if (hipGetLastError() != hipSuccess) return -3;
+  }
+  return 0;
 }
 
 }  // namespace qcoll

@@ -5,7 +5,9 @@ batched launch of the 3D workload (32^3 and 16^3 cells in one launch).
 
 Tolerance: the plain-FP32 bound of the 2D tests (relative L2 2e-4 over the
 batch, 1e-3 per cell); the projection leaves mass, momentum and energy at FP64
-rounding (1e-12 relative).
+rounding (1e-12 relative). The FX16 variant of the 32^3 tiles (split-FP16
+DFT-GEMMs; spectrum, work fields and filters still stored in FP32, which sets
+its error floor near 1e-5): 2e-5 over the batch, 1e-4 per cell.
 """
 
 import numpy as np
@@ -19,6 +21,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL, CELL_TOL = 2e-4, 1e-3
+FX_TOL, FX_CELL_TOL = 2e-5, 1e-4
 
 
 @pytest.fixture(scope="module")
@@ -60,6 +63,57 @@ def test_parity_3d(qc, N, L, M, cells):
     print(f"3D N={N} M={M}: rel L2 {err:.3e}, worst cell {cerr:.3e}")
     assert err < TOL and cerr < CELL_TOL
     plan.close()
+
+
+@pytest.mark.parametrize("N,M,cells", [(32, 8, 3), (24, 8, 3), (20, 8, 2), (32, 32, 2)])
+def test_parity_3d_fx16(qc, N, M, cells):
+    f = wl.mixture_cells(3, N, 8.0, cells, 40 + N)
+    plan = qc.Plan(3, N, 8.0, "hard_sphere", M, precision="fx16")
+    q = _eval(plan, f)
+    ref = _ref(f, N, 8.0, M)
+    err, cerr = _rel(q, ref), _cell_rel(q, ref)
+    print(f"3D FX16 N={N} M={M}: rel L2 {err:.3e}, worst cell {cerr:.3e}")
+    assert err < FX_TOL and cerr < FX_CELL_TOL
+    plan.close()
+
+
+def test_fx16_3d_needs_32_tiles(qc):
+    with pytest.raises(qc.QcollError):
+        qc.Plan(3, 16, 8.0, "hard_sphere", 8, precision="fx16")
+
+
+def test_fx16_and_fp32_slots_in_one_call(qc):
+    """An FX16 32^3 plan, an FX16 24^3 plan and an FP32 16^3 plan in one batched
+    call equal their single-plan calls bitwise (eval with the projection, the
+    IMEX step), and two FX16 plans of different grids in one call use their own
+    DFT tables."""
+    fa = wl.mixture_cells(3, 32, 8.0, 3, 81)
+    fc = wl.mixture_cells(3, 24, 8.0, 4, 82)
+    fb = wl.mixture_cells(3, 16, 8.0, 5, 83)
+    pa = qc.Plan(3, 32, 8.0, "hard_sphere", 8, precision="fx16", conserve=True)
+    pc = qc.Plan(3, 24, 8.0, "hard_sphere", 8, precision="fx16", conserve=True)
+    pb = qc.Plan(3, 16, 8.0, "hard_sphere", 8, precision="fp32", conserve=True)
+    xs = [torch.tensor(x, dtype=torch.float32, device="cuda") for x in (fa, fc, fb)]
+    qs = [torch.empty(x.shape, dtype=torch.float64, device="cuda") for x in xs]
+    qc.eval_multi([pa, pc, pb], xs, qs)
+    singles = [p.eval(x) for p, x in zip((pa, pc, pb), xs)]
+    torch.cuda.synchronize()
+    for a, b in zip(qs, singles):
+        assert torch.equal(a, b)
+    ys = [x.clone() for x in xs]
+    qc.step_multi([pa, pc, pb], xs, 0.01, 1.0, "imex")
+    for p, y in zip((pa, pc, pb), ys):
+        p.step(y, 0.01, 1.0, "imex")
+    torch.cuda.synchronize()
+    for a, b in zip(xs, ys):
+        assert torch.equal(a, b)
+    for q, f, N in ((qs[0], fa, 32), (qs[1], fc, 24)):
+        ref = sp.project_conservative(_ref(f, N, 8.0, 8), 3, 8.0)
+        err = _rel(q.cpu().numpy(), ref)
+        print(f"mixed call: FX16 {N}^3 rel L2 {err:.3e}")
+        assert err < FX_TOL
+    for p in (pa, pc, pb):
+        p.close()
 
 
 @pytest.mark.parametrize("N", [16, 32])
@@ -145,12 +199,13 @@ def test_two_resolutions_one_launch(qc):
     p16.close()
 
 
-def test_3d_workload_sampled_cells(qc):
+@pytest.mark.parametrize("precision", ["fp32", "fx16"])
+def test_3d_workload_sampled_cells(qc, precision):
     """The 32^3 half of the 3D workload at 1024 cells in the launch shape of the
     benchmark; 3 sampled cells against the oracle, and the projection's moments
     on all cells."""
     f = wl.config_inputs("hs3d_32", cells=1024)
-    plan = qc.Plan(3, 32, 8.0, "hard_sphere", 32, precision="fp32", conserve=True)
+    plan = qc.Plan(3, 32, 8.0, "hard_sphere", 32, precision=precision, conserve=True)
     ft = torch.tensor(f, dtype=torch.float32, device="cuda")
     q = plan.eval(ft)
     torch.cuda.synchronize()
@@ -158,8 +213,8 @@ def test_3d_workload_sampled_cells(qc):
     got = q[idx].cpu().numpy()
     ref = sp.project_conservative(_ref(f[idx], 32, 8.0, 32), 3, 8.0)
     err = _rel(got, ref)
-    print(f"hs3d_32 1024 cells: sampled rel L2 {err:.3e}")
-    assert err < TOL
+    print(f"hs3d_32 1024 cells ({precision}): sampled rel L2 {err:.3e}")
+    assert err < (FX_TOL if precision == "fx16" else TOL)
     qa = q.cpu().numpy()
     mass = np.abs(qa.sum(axis=(1, 2, 3))) / np.abs(qa).sum(axis=(1, 2, 3))
     assert mass.max() <= 1e-12
@@ -196,13 +251,14 @@ def test_3d_stage_graph_replay(qc):
     p16.close()
 
 
-@pytest.mark.parametrize("scheme", ["ars222", "bpr343"])
-def test_step_rk_3d(qc, scheme):
-    """Multi-stage penalised IMEX step on a 16^3 grid against the oracle's stage
+@pytest.mark.parametrize("scheme,N,precision", [("ars222", 16, "fp32"), ("bpr343", 16, "fp32"),
+                                                ("bpr343", 24, "fx16")])
+def test_step_rk_3d(qc, scheme, N, precision):
+    """Multi-stage penalised IMEX step on a 3D grid against the oracle's stage
     recursion with the FP64 operator."""
-    N, L, cells, dt, eps = 16, 8.0, 3, 0.05, 0.5
+    L, cells, dt, eps = 8.0, 3, 0.05, 0.5
     f0 = wl.mixture_cells(3, N, L, cells, 71)
-    plan = qc.Plan(3, N, L, "hard_sphere", 8, precision="fp32")
+    plan = qc.Plan(3, N, L, "hard_sphere", 8, precision=precision)
     f = torch.tensor(f0, dtype=torch.float32, device="cuda")
     status = torch.full((cells,), -1, dtype=torch.int32, device="cuda")
     plan.step_rk(f, dt, eps, scheme, status)
@@ -213,7 +269,7 @@ def test_step_rk_3d(qc, scheme):
                                       lambda F: sp.q_fast(F, s, bank), dt, eps, 3, L, scheme)
     got = f.cpu().double().numpy()
     err = np.abs(got - want).max() / np.abs(want).max()
-    print(f"3D step_rk {scheme}: max rel {err:.3e}")
+    print(f"3D step_rk {scheme} N={N} {precision}: max rel {err:.3e}")
     assert err <= 3e-5
     assert (status.cpu().numpy() == 0).all()
     plan.close()
