@@ -96,8 +96,8 @@ enum {
  * is set to NULL. Device plans: d = 2 with N <= 32 in either precision (grids
  * below 16 or 32 run zero-padded in a 16x16 or 32x32 tile) and 34 <= N <= 64
  * in QCOLL_MIX_FX16 (radix-2 split into 32-point tiles, one workgroup per
- * cell); d = 3 hard spheres with N <= 32 in QCOLL_FP32 and with 16 < N <= 32
- * in QCOLL_MIX_FX16 (zero-padded 16^3 or 32^3 tiles, one workgroup per cell,
+ * cell); d = 3 hard spheres with N <= 32 in either precision (zero-padded
+ * 16^3 or 32^3 tiles, one workgroup per cell,
  * a scratch area of 144 T^3 bytes per resident workgroup held by the plan; the
  * 3D FX16 variant splits the DFT-GEMM operands as in 2D but keeps spectra,
  * filters and work fields in FP32). Other sizes and precisions are

@@ -378,24 +378,40 @@ int build_device_3d(qcoll_plan_s* p) {
   };
   int rc;
   if (p->precision == QCOLL_MIX_FX16) {
-    // [m][K half i][part: lead, hi, lo][lane][slot]: 2^9 e(x, j) split into an
-    // integer lead and the FP16 hi and lo of the remainder, x = lane % 32,
-    // j = 2 (8 i + slot) + lane / 32 (T = 32)
-    std::vector<_Float16> et(static_cast<size_t>(3) * 2 * 3 * 64 * 8);
-    for (int m = 0; m < 3; ++m)
-      for (int i = 0; i < 2; ++i)
+    // 2^9 e split into an integer lead and the FP16 hi and lo of the remainder,
+    // stored at et[base], et[base + 64 * 8], et[base + 2 * 64 * 8]
+    auto put = [](std::vector<_Float16>& et, size_t base, double e) {
+      const double y = 512.0 * e;
+      const double lead = std::nearbyint(y);
+      const float r = static_cast<float>(y - lead);
+      const _Float16 hi = static_cast<_Float16>(r);
+      et[base] = static_cast<_Float16>(static_cast<float>(lead));
+      et[base + 64 * 8] = hi;
+      et[base + 2 * 64 * 8] = static_cast<_Float16>(r - static_cast<float>(hi));
+    };
+    std::vector<_Float16> et;
+    if (T == 32) {
+      // [m][K half i][part][lane][slot]: e_m(x, j), x = lane % 32, j = 2 (8 i + slot) + lane / 32
+      et.assign(static_cast<size_t>(3) * 2 * 3 * 64 * 8, static_cast<_Float16>(0.0f));
+      for (int m = 0; m < 3; ++m)
+        for (int i = 0; i < 2; ++i)
+          for (int lane = 0; lane < 64; ++lane)
+            for (int sl = 0; sl < 8; ++sl)
+              put(et, ((static_cast<size_t>(m) * 2 + i) * 3 * 64 + lane) * 8 + sl,
+                  emat(m, lane % 32, 2 * (8 * i + sl) + lane / 32));
+    } else {
+      // [row r: dr fwd, dr inv, di fwd, di inv][part][lane][slot], x = lane % 16,
+      // point 4 (slot % 4) + lane / 16; slots 0-3 multiply the real parts, 4-7
+      // the imaginary parts: dr = C xr + S_r xi, di = S_i xr + C xi with
+      // S_r = S (forward) or -S (inverse), S_i = -S (forward) or S (inverse)
+      const int mats[4][2] = {{0, 1}, {0, 2}, {2, 0}, {1, 0}};   // (matrix of slots 0-3, of slots 4-7)
+      et.assign(static_cast<size_t>(4) * 3 * 64 * 8, static_cast<_Float16>(0.0f));
+      for (int r = 0; r < 4; ++r)
         for (int lane = 0; lane < 64; ++lane)
-          for (int sl = 0; sl < 8; ++sl) {
-            const double y = 512.0 * emat(m, lane % 32, 2 * (8 * i + sl) + lane / 32);
-            const double lead = std::nearbyint(y);
-            const float r = static_cast<float>(y - lead);
-            const _Float16 hi = static_cast<_Float16>(r);
-            const _Float16 lo = static_cast<_Float16>(r - static_cast<float>(hi));
-            const size_t base = ((static_cast<size_t>(m) * 2 + i) * 3 * 64 + lane) * 8 + sl;
-            et[base] = static_cast<_Float16>(static_cast<float>(lead));
-            et[base + 64 * 8] = hi;
-            et[base + 2 * 64 * 8] = lo;
-          }
+          for (int sl = 0; sl < 8; ++sl)
+            put(et, (static_cast<size_t>(r) * 3 * 64 + lane) * 8 + sl,
+                emat(mats[r][sl / 4], lane % 16, 4 * (sl % 4) + lane / 16));
+    }
     _Float16* d = nullptr;
     rc = upload(et, &d, p->device_bytes);
     p->econst = d;
@@ -534,7 +550,7 @@ void classical_table(const qcoll::HostPlan& src, std::vector<double>& beta) {
 }
 
 bool device_supported(const qcoll::HostPlan& hp, int precision) {
-  if (hp.d == 3) return hp.N <= 32 && (precision == QCOLL_FP32 || (precision == QCOLL_MIX_FX16 && hp.N > 16));
+  if (hp.d == 3) return hp.N <= 32 && (precision == QCOLL_FP32 || precision == QCOLL_MIX_FX16);
   if (hp.d != 2) return false;
   if (hp.N <= 32) return true;
   return hp.N <= 64 && precision == QCOLL_MIX_FX16;

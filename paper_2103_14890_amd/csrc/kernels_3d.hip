@@ -6,8 +6,9 @@
 // cell; cells of several plans (grids) share one launch through a slot table.
 //
 // The 3D DFT is three passes, one per axis, each a batch of 1-D complex DFTs
-// done as FP32 MFMA GEMMs over tiles of T lines (section 3.3: the kernel modes
-// become A products in Fourier space, each evaluated by FFT-sized transforms).
+// done as MFMA GEMMs over tiles of T lines (section 3.3: the kernel modes
+// become A products in Fourier space, each evaluated by FFT-sized transforms):
+// FP32 MFMA, or in the FX16 variant split-FP16 MFMA with the FP32 data layout.
 // A cell's complex spectrum, the work fields between passes and the FP64 gain
 // live in a per-workgroup scratch area (global memory, cached in L2/MALL):
 // a 32^3 complex field is 256 KB, more than the LDS of a CU.
@@ -113,6 +114,19 @@ struct EmatFx {
   const half8* tab;   // the LDS table
 };
 
+// 16 x 16 tiles: one v_mfma_f32_16x16x32_f16 contracts a line's real and
+// imaginary parts together. On lane l (x = l % 16, g = l / 16), K slot j < 4
+// carries the real part of point 4 j + g and slot 4 + j its imaginary part:
+// the FP32 layout's steps, so again no data move between lanes. The LDS table
+// holds, per lane, the matching operand rows [C | S_r] of the real output and
+// [S_i | C] of the imaginary output, forward and inverse:
+// [dr fwd, dr inv, di fwd, di inv][part][lane].
+constexpr int kEtab16Half8 = 4 * 3 * 64;   // 12 KB of LDS
+
+struct EmatFx16 {
+  const half8* tab;
+};
+
 template <int T, bool FX>
 struct EmatOf {
   typedef Emat<T> type;
@@ -121,6 +135,23 @@ template <>
 struct EmatOf<32, true> {
   typedef EmatFx type;
 };
+template <>
+struct EmatOf<16, true> {
+  typedef EmatFx16 type;
+};
+
+__device__ __forceinline__ f32x4 mfma_h16(half8 a, half8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void mma6_3d16(const Split3& a, const Split3& b, f32x4& acc0, f32x4& acc1) {
+  acc0 = mfma_h16(a.l, b.l, acc0);
+  acc1 = mfma_h16(a.l, b.h, acc1);
+  acc1 = mfma_h16(a.h, b.l, acc1);
+  acc1 = mfma_h16(a.l, b.o, acc1);
+  acc1 = mfma_h16(a.h, b.h, acc1);
+  acc1 = mfma_h16(a.o, b.l, acc1);
+}
 
 __device__ __forceinline__ f32x16 mfma_h(half8 a, half8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
@@ -200,6 +231,56 @@ __device__ __forceinline__ void tile_dft(const EmatFx& E, const float* xr, const
   const float inv = ldexpf(1.0f, -(sa + 9));
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
+    dr[v] = (r0[v] + r1[v]) * inv;
+    di[v] = (i0[v] + i1[v]) * inv;
+  }
+}
+
+template <int T, bool DB, bool INV, bool REAL_IN>
+__device__ __forceinline__ void tile_dft(const EmatFx16& E, const float* xr, const float* xi, f32x4& dr,
+                                         f32x4& di) {
+  static_assert(T == 16, "the 16-point FX16 tile pass");
+  float m = 0.0f;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    m = fmaxf(m, fabsf(xr[s]));
+    if (!REAL_IN) m = fmaxf(m, fabsf(xi[s]));
+  }
+  m = wave_max(m);
+  const int sa = 9 - exp_above(m);
+  const float c = ldexpf(1.0f, sa);
+  Split3 X;
+  put2(X, 0, split2_f32(xr[0] * c, xr[1] * c));
+  put2(X, 2, split2_f32(xr[2] * c, xr[3] * c));
+  if (REAL_IN) {
+    put2(X, 4, split2_f32(0.0f, 0.0f));
+    put2(X, 6, split2_f32(0.0f, 0.0f));
+  } else {
+    put2(X, 4, split2_f32(xi[0] * c, xi[1] * c));
+    put2(X, 6, split2_f32(xi[2] * c, xi[3] * c));
+  }
+  int lane = threadIdx.x & 63;
+  asm volatile("" : "+v"(lane));
+  auto row = [&](int k) {
+    const half8* q = E.tab + (k * 3) * 64 + lane;
+    Split3 r;
+    r.l = q[0];
+    r.h = q[64];
+    r.o = q[128];
+    return r;
+  };
+  const Split3 Er = row(INV ? 1 : 0), Ei = row(INV ? 3 : 2);
+  f32x4 r0{}, r1{}, i0{}, i1{};
+  if (DB) {
+    mma6_3d16(Er, X, r0, r1);
+    mma6_3d16(Ei, X, i0, i1);
+  } else {
+    mma6_3d16(X, Er, r0, r1);
+    mma6_3d16(X, Ei, i0, i1);
+  }
+  const float inv = ldexpf(1.0f, -(sa + 9));
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
     dr[v] = (r0[v] + r1[v]) * inv;
     di[v] = (i0[v] + i1[v]) * inv;
   }
@@ -708,12 +789,12 @@ __global__ __launch_bounds__(256) void fp32_3d_kernel(Args3 A) {
   }
 }
 
-// FX16 slots (32^3 tiles): the LDS table of DFT-matrix splits is reloaded when
-// a workgroup moves to a slot of another plan.
+// FX16 slots (16^3 and 32^3 tiles): the LDS table of DFT-matrix splits is
+// reloaded when a workgroup moves to a slot of another plan.
 __global__ __launch_bounds__(256) void fx16_3d_kernel(Args3 A) {
   __shared__ double red[32];
   __shared__ float2 plane_lds[4][32 * 32];
-  __shared__ half8 etab_lds[kEtabHalf8];
+  __shared__ half8 etab_lds[kEtabHalf8];   // the 32x32 table (the 16x16 one is smaller)
   float2* plane = plane_lds[threadIdx.x >> 6];
   char* scratch = A.scratch + static_cast<int64_t>(blockIdx.x) * A.scratch_stride;
   const int64_t total = A.cell_start[A.nslots];
@@ -726,11 +807,13 @@ __global__ __launch_bounds__(256) void fx16_3d_kernel(Args3 A) {
     const int64_t cell = g - A.cell_start[s];
     if (a.etab16 != loaded) {  // the previous cell ended with a workgroup barrier
       const half8* src = static_cast<const half8*>(a.etab16);
-      for (int i = threadIdx.x; i < kEtabHalf8; i += blockDim.x) etab_lds[i] = src[i];
+      const int len = a.T == 32 ? kEtabHalf8 : kEtab16Half8;
+      for (int i = threadIdx.x; i < len; i += blockDim.x) etab_lds[i] = src[i];
       __syncthreads();
       loaded = a.etab16;
     }
-    cell_3d<32, true>(a, cell, scratch, red, plane, etab_lds);
+    if (a.T == 32) cell_3d<32, true>(a, cell, scratch, red, plane, etab_lds);
+    else cell_3d<16, true>(a, cell, scratch, red, plane, etab_lds);
   }
 }
 

@@ -5,8 +5,8 @@ batched launch of the 3D workload (32^3 and 16^3 cells in one launch).
 
 Tolerance: the plain-FP32 bound of the 2D tests (relative L2 2e-4 over the
 batch, 1e-3 per cell); the projection leaves mass, momentum and energy at FP64
-rounding (1e-12 relative). The FX16 variant of the 32^3 tiles (split-FP16
-DFT-GEMMs; spectrum, work fields and filters still stored in FP32, which sets
+rounding (1e-12 relative). The FX16 variant (split-FP16 DFT-GEMMs on 16^3 and
+32^3 tiles; spectrum, work fields and filters still stored in FP32, which sets
 its error floor near 1e-5): 2e-5 over the batch, 1e-4 per cell.
 """
 
@@ -65,7 +65,8 @@ def test_parity_3d(qc, N, L, M, cells):
     plan.close()
 
 
-@pytest.mark.parametrize("N,M,cells", [(32, 8, 3), (24, 8, 3), (20, 8, 2), (32, 32, 2)])
+@pytest.mark.parametrize("N,M,cells", [(32, 8, 3), (24, 8, 3), (20, 8, 2), (32, 32, 2), (16, 8, 6), (16, 32, 5),
+                                       (12, 8, 5), (8, 8, 7)])
 def test_parity_3d_fx16(qc, N, M, cells):
     f = wl.mixture_cells(3, N, 8.0, cells, 40 + N)
     plan = qc.Plan(3, N, 8.0, "hard_sphere", M, precision="fx16")
@@ -77,42 +78,40 @@ def test_parity_3d_fx16(qc, N, M, cells):
     plan.close()
 
 
-def test_fx16_3d_needs_32_tiles(qc):
-    with pytest.raises(qc.QcollError):
-        qc.Plan(3, 16, 8.0, "hard_sphere", 8, precision="fx16")
-
-
 def test_fx16_and_fp32_slots_in_one_call(qc):
-    """An FX16 32^3 plan, an FX16 24^3 plan and an FP32 16^3 plan in one batched
+    """FX16 plans of 32^3, 24^3 and 16^3 and an FP32 16^3 plan in one batched
     call equal their single-plan calls bitwise (eval with the projection, the
-    IMEX step), and two FX16 plans of different grids in one call use their own
-    DFT tables."""
+    IMEX step); FX16 plans of different grids in one launch use their own DFT
+    tables."""
     fa = wl.mixture_cells(3, 32, 8.0, 3, 81)
     fc = wl.mixture_cells(3, 24, 8.0, 4, 82)
+    fd = wl.mixture_cells(3, 16, 8.0, 6, 84)
     fb = wl.mixture_cells(3, 16, 8.0, 5, 83)
     pa = qc.Plan(3, 32, 8.0, "hard_sphere", 8, precision="fx16", conserve=True)
     pc = qc.Plan(3, 24, 8.0, "hard_sphere", 8, precision="fx16", conserve=True)
+    pd = qc.Plan(3, 16, 8.0, "hard_sphere", 8, precision="fx16", conserve=True)
     pb = qc.Plan(3, 16, 8.0, "hard_sphere", 8, precision="fp32", conserve=True)
-    xs = [torch.tensor(x, dtype=torch.float32, device="cuda") for x in (fa, fc, fb)]
+    plans = (pa, pc, pd, pb)
+    xs = [torch.tensor(x, dtype=torch.float32, device="cuda") for x in (fa, fc, fd, fb)]
     qs = [torch.empty(x.shape, dtype=torch.float64, device="cuda") for x in xs]
-    qc.eval_multi([pa, pc, pb], xs, qs)
-    singles = [p.eval(x) for p, x in zip((pa, pc, pb), xs)]
+    qc.eval_multi(list(plans), xs, qs)
+    singles = [p.eval(x) for p, x in zip(plans, xs)]
     torch.cuda.synchronize()
     for a, b in zip(qs, singles):
         assert torch.equal(a, b)
     ys = [x.clone() for x in xs]
-    qc.step_multi([pa, pc, pb], xs, 0.01, 1.0, "imex")
-    for p, y in zip((pa, pc, pb), ys):
+    qc.step_multi(list(plans), xs, 0.01, 1.0, "imex")
+    for p, y in zip(plans, ys):
         p.step(y, 0.01, 1.0, "imex")
     torch.cuda.synchronize()
     for a, b in zip(xs, ys):
         assert torch.equal(a, b)
-    for q, f, N in ((qs[0], fa, 32), (qs[1], fc, 24)):
+    for q, f, N in ((qs[0], fa, 32), (qs[1], fc, 24), (qs[2], fd, 16)):
         ref = sp.project_conservative(_ref(f, N, 8.0, 8), 3, 8.0)
         err = _rel(q.cpu().numpy(), ref)
         print(f"mixed call: FX16 {N}^3 rel L2 {err:.3e}")
         assert err < FX_TOL
-    for p in (pa, pc, pb):
+    for p in plans:
         p.close()
 
 
