@@ -47,8 +47,8 @@ def test_unsupported_and_host_only_paths():
     assert _plan(d=3, kernel=0, M=8)[0] == qc.EUNSUPPORTED
     assert _plan(N=64, prec=1, flags=0)[0] == qc.EUNSUPPORTED   # 64x64 runs in FX16 only
     assert _plan(N=80, flags=0)[0] == qc.EUNSUPPORTED           # beyond the 64x64 tile
-    assert _plan(d=3, N=16, flags=0)[0] == qc.EUNSUPPORTED      # 3D runs in FP32 only
-    assert _plan(d=3, N=40, prec=1, flags=0)[0] == qc.EUNSUPPORTED  # 3D up to 32^3
+    assert _plan(d=3, N=40, prec=1, flags=0)[0] == qc.EUNSUPPORTED  # 3D up to 32^3 (FP32 or FX16)
+    assert _plan(d=3, N=40, flags=0)[0] == qc.EUNSUPPORTED
     p = qc.Plan(2, 32, 8.0, "hard_sphere", 8, host_only=True)
     # a host-only plan refuses device work before touching any pointer
     assert qc.LIB.qcoll_eval(p._h, None, None, 4, None) == qc.EUNSUPPORTED
