@@ -7,9 +7,10 @@
 //  2. fluxes: the Rusanov flux of every face (linear in the two face states,
 //     so the face integral needs only the face averages) and the update of
 //     eq. (finite_vol5).
-// One workgroup = 256 (flux: 1024) consecutive velocities of one cell (four
-// wavefronts); the cell tables are wave-uniform and come through scalar
-// loads. Blocks are dealt to the XCDs in contiguous ranges of cells, so that
+// One workgroup = 512 (reconstruction: two per thread, both velocities' row
+// gathers issued before either is used) or 1024 (fluxes: four per thread)
+// consecutive velocities of one cell (four wavefronts); the cell tables are
+// wave-uniform and come through scalar loads. Blocks are dealt to the XCDs in contiguous ranges of cells, so that
 // neighbouring cells (numbered along a space-filling curve) share an XCD's L2.
 
 #include <hip/hip_runtime.h>
@@ -65,21 +66,44 @@ __device__ inline float& at(float* base, unsigned byte_off) {
 // The face count of a cell is a template parameter (the kernels branch once on
 // it): every loop below is then fully unrolled and free of branches, so the
 // scalar loads of the cell's tables are issued together, not one per face.
+
+// The row values one velocity's reconstruction reads: its own cell, the
+// central stencil and the face neighbours.
 template <int DEG, int NF>
-__device__ __forceinline__ void recon_cell(const float* __restrict__ f, const TrCell* __restrict__ cells,
+struct Gath {
+  float fi, d[DEG == 2 ? 11 : 5], dn[NF];
+};
+
+template <int DEG, int NF>
+__device__ __forceinline__ Gath<DEG, NF> recon_load(const float* __restrict__ f, const TrCell* __restrict__ cells,
+                                                    int V, const Block& blk) {
+  constexpr int NS = DEG == 2 ? 11 : 5;
+  const unsigned vb = 4u * static_cast<unsigned>(blk.v < V ? blk.v : V - 1);
+  const TrCell& C = cells[blk.cell];
+  Gath<DEG, NF> g;
+  g.fi = at(f + blk.cell * V, vb);
+#pragma unroll
+  for (int j = 0; j < NS; ++j) g.d[j] = at(f + static_cast<int64_t>(C.stencil[j]) * V, vb);
+#pragma unroll
+  for (int L = 0; L < NF; ++L) g.dn[L] = at(f + static_cast<int64_t>(C.nbr[L]) * V, vb);
+  return g;
+}
+
+// The reconstruction of one velocity from its gathered values, written out as
+// face averages.
+template <int DEG, int NF>
+__device__ __forceinline__ void recon_cell(const Gath<DEG, NF>& g, const TrCell* __restrict__ cells,
                                            float* __restrict__ fv, int V, const Block& blk) {
   constexpr int K = DEG == 2 ? 5 : 2;
   constexpr int NS = DEG == 2 ? 11 : 5;
   const unsigned vb = 4u * static_cast<unsigned>(blk.v < V ? blk.v : V - 1);  // byte offset in a row
   const TrCell& C = cells[blk.cell];
-  const float fi = at(f + blk.cell * V, vb);
-
-  // all loads of the cell's data at once: the central stencil and the face neighbours
+  const float fi = g.fi;
   float d[NS], dn[NF];
 #pragma unroll
-  for (int j = 0; j < NS; ++j) d[j] = at(f + static_cast<int64_t>(C.stencil[j]) * V, vb);
+  for (int j = 0; j < NS; ++j) d[j] = g.d[j];
 #pragma unroll
-  for (int L = 0; L < NF; ++L) dn[L] = at(f + static_cast<int64_t>(C.nbr[L]) * V, vb);
+  for (int L = 0; L < NF; ++L) dn[L] = g.dn[L];
   // optimal polynomial (least squares over the central stencil)
   float copt[K];
 #pragma unroll
@@ -211,9 +235,17 @@ template <int DEG>
 __global__ __launch_bounds__(256) void transport_recon_kernel(const float* __restrict__ f,
                                                               const TrCell* __restrict__ cells,
                                                               float* __restrict__ fv, int64_t ncells, int V) {
-  const Block blk = map_block<1>(ncells, V);
+  const Block blk = map_block<2>(ncells, V);
   if (!blk.valid) return;
-#define QCOLL_RECON(n) recon_cell<DEG, n>(f, cells, fv, V, blk)
+  Block b2 = blk;
+  b2.v += 256;
+#define QCOLL_RECON(n)                                          \
+  {                                                             \
+    const Gath<DEG, n> g1 = recon_load<DEG, n>(f, cells, V, blk); \
+    const Gath<DEG, n> g2 = recon_load<DEG, n>(f, cells, V, b2);  \
+    recon_cell<DEG, n>(g1, cells, fv, V, blk);                  \
+    recon_cell<DEG, n>(g2, cells, fv, V, b2);                   \
+  }
   QCOLL_TR_SWITCH(cells[blk.cell].nf, QCOLL_RECON)
 #undef QCOLL_RECON
 }
@@ -240,11 +272,12 @@ int launch_transport(const TransportArgs& args, hipStream_t stream) {
   };
   const int64_t g1 = grid_of(1);
   if (g1 > 0x7fffffff) return -1;
+  const int64_t g2 = grid_of(2);
   if (args.degree == 2)
-    hipLaunchKernelGGL(transport_recon_kernel<2>, dim3(static_cast<unsigned>(g1)), dim3(256), 0, stream, args.f,
+    hipLaunchKernelGGL(transport_recon_kernel<2>, dim3(static_cast<unsigned>(g2)), dim3(256), 0, stream, args.f,
                        args.cells, args.fv, args.ncells, args.V);
   else
-    hipLaunchKernelGGL(transport_recon_kernel<1>, dim3(static_cast<unsigned>(g1)), dim3(256), 0, stream, args.f,
+    hipLaunchKernelGGL(transport_recon_kernel<1>, dim3(static_cast<unsigned>(g2)), dim3(256), 0, stream, args.f,
                        args.cells, args.fv, args.ncells, args.V);
   if (hipGetLastError() != hipSuccess) return -3;
   if (args.V >= 1024)
