@@ -863,6 +863,20 @@ static hipStream_t side_stream(int dev, int k) {
   return pool[dev][k];
 }
 
+// Fork/join events of a device (created on first use, kept until the process
+// ends) and the lock that serialises their use: [0] marks the caller's stream
+// at the fork, [1 + k] side stream k at the join.
+struct ForkJoin {
+  std::mutex mu;
+  hipEvent_t ev[1 + kSideStreams] = {};
+};
+
+static ForkJoin* fork_join(int dev) {
+  static ForkJoin pool[kMaxDevices];
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  return &pool[dev];
+}
+
 // One launch of a batched 2D call: a tile-64 plan (a workgroup per cell) or a
 // slot table of plans with N <= 32.
 struct MultiJob {
@@ -891,32 +905,38 @@ static int run_jobs(const std::vector<MultiJob>& jobs, int wpb, int dev, hipStre
       if (!side[nside]) break;
     }
   }
-  if (nside == 0) {
+  ForkJoin* fj = nside > 0 ? fork_join(dev) : nullptr;
+  std::unique_lock<std::mutex> lock;
+  if (fj) {
+    lock = std::unique_lock<std::mutex>(fj->mu);
+    int cur = -1;
+    const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+    if (have_cur && cur != dev) hipSetDevice(dev);   // events belong to the plans' device
+    for (int k = 0; k <= nside && fj; ++k)
+      if (!fj->ev[k] && hipEventCreateWithFlags(&fj->ev[k], hipEventDisableTiming) != hipSuccess) {
+        fj->ev[k] = nullptr;
+        fj = nullptr;   // no events: run the jobs one after another
+      }
+    if (have_cur && cur != dev) hipSetDevice(cur);
+  }
+  if (!fj) {
     for (const MultiJob& j : jobs)
       if (run(j, stream)) return QCOLL_EDEVICE;
     return QCOLL_OK;
   }
-  hipEvent_t start = nullptr;
-  if (hipEventCreateWithFlags(&start, hipEventDisableTiming) != hipSuccess) return QCOLL_EDEVICE;
-  int rc = hipEventRecord(start, stream) == hipSuccess ? QCOLL_OK : QCOLL_EDEVICE;
+  // a wait takes the event's most recent record at the time of the call, so
+  // the events can be recorded again by the next call once its waits are queued
+  int rc = hipEventRecord(fj->ev[0], stream) == hipSuccess ? QCOLL_OK : QCOLL_EDEVICE;
   for (int k = 0; k < nside && rc == QCOLL_OK; ++k)
-    if (hipStreamWaitEvent(side[k], start, 0) != hipSuccess) rc = QCOLL_EDEVICE;
+    if (hipStreamWaitEvent(side[k], fj->ev[0], 0) != hipSuccess) rc = QCOLL_EDEVICE;
   // job 0 and every (nside + 1)-th job after it on the caller's stream, the others round-robin
   for (size_t i = 0; i < jobs.size() && rc == QCOLL_OK; ++i) {
     const int lane = static_cast<int>(i % (nside + 1));
     if (run(jobs[i], lane == 0 ? stream : side[lane - 1])) rc = QCOLL_EDEVICE;
   }
-  for (int k = 0; k < nside; ++k) {  // join (also after an error, so no side work is left unordered)
-    hipEvent_t done = nullptr;
-    if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) {
+  for (int k = 0; k < nside; ++k)  // join (also after an error, so no side work is left unordered)
+    if (hipEventRecord(fj->ev[1 + k], side[k]) != hipSuccess || hipStreamWaitEvent(stream, fj->ev[1 + k], 0) != hipSuccess)
       rc = QCOLL_EDEVICE;
-      continue;
-    }
-    if (hipEventRecord(done, side[k]) != hipSuccess || hipStreamWaitEvent(stream, done, 0) != hipSuccess)
-      rc = QCOLL_EDEVICE;
-    hipEventDestroy(done);
-  }
-  hipEventDestroy(start);
   return rc;
 }
 
