@@ -36,7 +36,10 @@ namespace {
 constexpr int kZSlot = 16 * 64;                      // complex values per slot
 constexpr int kLdsBytes = (4 * kZSlot + 2 * 32 + 8 * 4 + 4 * kZSlot) * 16 + kEoLdsBytes;
 
-struct Cd {
+// 16-byte aligned, so that a lane's complex value is one ds_read_b128 /
+// ds_write_b128 (two 8-byte halves with a 16-byte lane stride conflict in
+// the LDS banks)
+struct alignas(16) Cd {
   double x, y;
 };
 
@@ -60,7 +63,8 @@ __device__ __forceinline__ void load_subgrid(const KernelArgs& a, int64_t cell, 
 
 template <int OUT>
 __global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
-  extern __shared__ double lds[];
+  extern __shared__ double2 lds_raw[];   // 16-byte aligned base
+  double* lds = reinterpret_cast<double*>(lds_raw);
   Cd* zs = reinterpret_cast<Cd*>(lds);                 // [4][16][64]
   Cd* tw = zs + 4 * kZSlot;                            // [2][32]
   double* red = reinterpret_cast<double*>(tw + 64);    // [4 waves][4]
