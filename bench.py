@@ -594,7 +594,8 @@ def main() -> int:
         flops32 = mfma_flops_per_cell("fp32", fp32["info"]["transforms"], NN) * cells
     threads = 1   # the oracle's numpy FFTs run on one core
     out = {
-        "metric": "cell Q(f,f) evals/s at N_v=32^2, mixed vs FP32 at rel.err<=1e-5; p99 latency",
+        "metric": ("cell Q(f,f) evals/s at N_v=32^2, mixed vs FP32 at rel.err<=1e-5; p99 latency" if NN == 32 else
+                   f"cell Q(f,f) evals/s at N_v={NN}^2, mixed (FX16) precision against the FP64 oracle"),
         "value": value,
         "unit": "cell-evals/s",
         "n_gpus": 1,
