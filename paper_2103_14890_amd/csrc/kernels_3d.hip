@@ -334,6 +334,12 @@ __device__ __forceinline__ void pass_tiles(const EM& E, int w, Load load, Store 
   }
 }
 
+// A plane in LDS has rows of T + 1 values: the axis-2 pass reads it by
+// columns (lane x takes row x), and with a row stride of T values the lanes of
+// a half-wavefront would all fall on the same two LDS banks; with T + 1 they
+// fall on distinct ones, while the row-wise writes stay contiguous.
+constexpr int kPlaneLds = 32 * 33;
+
 // The inverse passes along axes 1 and 2 of one plane i0 = t (tiles t = w,
 // w+4, ... of this wavefront) run back to back: the axis-1 result goes through
 // a T x T plane in this wavefront's LDS (its layout has the lines in registers,
@@ -354,13 +360,13 @@ __device__ __forceinline__ void plane_passes(const EM& E, int w, float2* plane, 
     {
       OPAQUE_LANE();
 #pragma unroll
-      for (int v = 0; v < S::NR; ++v) plane[S::row(v, lane) * T + x] = make_float2(dr[v], di[v]);
+      for (int v = 0; v < S::NR; ++v) plane[S::row(v, lane) * (T + 1) + x] = make_float2(dr[v], di[v]);
     }
     {
       OPAQUE_LANE();
 #pragma unroll
       for (int s = 0; s < S::NS; ++s) {
-        const float2 z = plane[x * T + S::KS * s + jl];
+        const float2 z = plane[x * (T + 1) + S::KS * s + jl];
         ar[s] = z.x;
         ai[s] = z.y;
       }
@@ -400,13 +406,13 @@ __device__ __forceinline__ void plane_passes_group(const EM& E, int w, float2* p
       {
         OPAQUE_LANE();
 #pragma unroll
-        for (int v = 0; v < S::NR; ++v) plane[S::row(v, lane) * T + x] = make_float2(dr[v], di[v]);
+        for (int v = 0; v < S::NR; ++v) plane[S::row(v, lane) * (T + 1) + x] = make_float2(dr[v], di[v]);
       }
       {
         OPAQUE_LANE();
 #pragma unroll
         for (int s = 0; s < S::NS; ++s) {
-          const float2 z = plane[x * T + S::KS * s + jl];
+          const float2 z = plane[x * (T + 1) + S::KS * s + jl];
           ar[s] = z.x;
           ai[s] = z.y;
         }
@@ -774,7 +780,7 @@ __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red
 
 __global__ __launch_bounds__(256) void fp32_3d_kernel(Args3 A) {
   __shared__ double red[32];
-  __shared__ float2 plane_lds[4][32 * 32];   // one T x T plane per wavefront (8 KB at T = 32)
+  __shared__ float2 plane_lds[4][kPlaneLds];   // one T x T plane per wavefront
   float2* plane = plane_lds[threadIdx.x >> 6];
   char* scratch = A.scratch + static_cast<int64_t>(blockIdx.x) * A.scratch_stride;
   const int64_t total = A.cell_start[A.nslots];
@@ -793,7 +799,7 @@ __global__ __launch_bounds__(256) void fp32_3d_kernel(Args3 A) {
 // reloaded when a workgroup moves to a slot of another plan.
 __global__ __launch_bounds__(256) void fx16_3d_kernel(Args3 A) {
   __shared__ double red[32];
-  __shared__ float2 plane_lds[4][32 * 32];
+  __shared__ float2 plane_lds[4][kPlaneLds];
   __shared__ half8 etab_lds[kEtabHalf8];   // the 32x32 table (the 16x16 one is smaller)
   float2* plane = plane_lds[threadIdx.x >> 6];
   char* scratch = A.scratch + static_cast<int64_t>(blockIdx.x) * A.scratch_stride;
