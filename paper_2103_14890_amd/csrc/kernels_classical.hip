@@ -21,12 +21,14 @@ namespace {
 constexpr int kCb = 4;          // cells per workgroup
 constexpr int kMaxOut = 3;      // output modes per thread (n <= 768)
 
-struct cplx {
+// 16-byte aligned, so that a lane's complex value is one 128-bit LDS access
+// (two 8-byte halves with a 16-byte lane stride conflict in the LDS banks)
+struct alignas(16) cplx {
   double re, im;
 };
 
 __global__ __launch_bounds__(256) void classical_kernel(ClassicalArgs a) {
-  extern __shared__ double sh[];
+  extern __shared__ double2 sh[];   // 16-byte aligned base
   const int N = a.N, n = N * N;
   cplx* fh = reinterpret_cast<cplx*>(sh);          // [kCb][n]
   cplx* tmp = fh + kCb * n;                         // [kCb][n]
