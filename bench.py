@@ -13,7 +13,6 @@ workload for comparison. Prints ONE JSON line.
 from __future__ import annotations
 
 import argparse
-import dataclasses
 import json
 import math
 import os
@@ -73,6 +72,131 @@ def mfma_flops_per_cell_3d(T: int, transforms: int) -> float:
     per_mfma = 2 * (32 * 32 * 2 if T == 32 else 16 * 16 * 4)
     per_pass = T * (T * T // 64) * 4 * per_mfma
     return (2.5 + 3 * transforms) * per_pass
+
+
+def alg_flops_per_cell(d: int, N: int, gain_transforms: int) -> float:
+    """Algorithmic work of one cell evaluation: the FFT form of the method
+    (section 3.3, O(A N^d log N^d)). Radix-2 count 5 n log2 n per complex FFT
+    (half of it for the real-input forward transform), P = gain_transforms
+    packed inverse transforms plus the loss transform, and the pointwise work:
+    6 flops per mode per packed filter and 2 for the loss filter, 3 per point
+    per packed pair for the gain, 2 per point for gain - f * loss."""
+    n = N ** d
+    lg = math.log2(n)
+    P = gain_transforms
+    return 2.5 * n * lg + (P + 1) * 5.0 * n * lg + (9 * P + 4) * n
+
+
+# ---------------------------------------------------------------- CPU baseline
+# The FP64 oracle as it stands, run over cell chunks by a pool of worker
+# processes on the host cores (the oracle itself is single-threaded NumPy).
+_ORACLE_FN = None
+_THREAD_VARS = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+
+
+def _oracle_init(kind: str, kw: dict) -> None:
+    global _ORACLE_FN
+    from oracle import spectral as sp
+    if kind == "transport":
+        from oracle import transport as tr
+        from workloads import mesh as wm
+        mesh, _, N, L = wm.transport_case(kw["name"])
+        T = tr.Transport(mesh, 2)
+        vel = tr.velocity_pairs(N, L)
+        f = kw["f"]
+        _ORACLE_FN = lambda cells: T.step(f, vel, kw["dt"], cells)   # noqa: E731
+        return
+    s = sp.Setup(**kw)
+    if kind == "galerkin":
+        from oracle import galerkin as og
+        fine = og.galerkin_bank(s)
+        fn = lambda c: og.q_galerkin(c, s, fine)                       # noqa: E731
+    elif kind == "classical":
+        from oracle import classical as ocl
+        beta = ocl.beta_table(s)
+        fn = lambda c: ocl.q_classical(c, s, beta)                     # noqa: E731
+    else:
+        bank = sp.filter_bank(s)
+        fn = lambda c: sp.q_fast(c, s, bank)                           # noqa: E731
+    _ORACLE_FN = lambda c: sp.project_conservative(fn(c), s.d, s.L)   # noqa: E731
+
+
+def _oracle_call(item):
+    return _ORACLE_FN(item)
+
+
+def cpu_workers() -> int:
+    """Host cores the baseline uses: the process's CPU affinity, at most 16
+    (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_oracle_baseline(kind: str, kw: dict, items: list, units, target_s: float, runs: int = 3,
+                        init_kw: dict | None = None) -> dict:
+    """Time the oracle on a bounded prefix of `items` (work items in workload
+    order; units(item) = cell evaluations or updates in it) with one worker
+    process per host core: after a warm-up that starts the workers and builds
+    their tables, the prefix is sized so that `runs` timed passes take about
+    target_s together; returns the median rate and the last pass's outputs."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    workers = min(cpu_workers(), max(1, len(items)))
+    saved = {k: os.environ.get(k) for k in _THREAD_VARS}
+    for k in _THREAD_VARS:
+        os.environ[k] = "1"
+    try:
+        ctx = mp.get_context("spawn")
+        with cf.ProcessPoolExecutor(workers, mp_context=ctx, initializer=_oracle_init,
+                                    initargs=(kind, dict(kw, **(init_kw or {})))) as ex:
+            probe = items[:workers]
+            list(ex.map(_oracle_call, probe))               # start the workers, build their tables
+            t0 = time.perf_counter()
+            list(ex.map(_oracle_call, probe))
+            t_probe = time.perf_counter() - t0
+            per_pass = max(1, int(len(probe) * (target_s / runs) / max(t_probe, 1e-6)))
+            sample = items[:max(len(probe), min(len(items), per_pass))]
+            times, outs = [], None
+            for _ in range(runs):
+                t0 = time.perf_counter()
+                outs = list(ex.map(_oracle_call, sample))
+                times.append(time.perf_counter() - t0)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    n_units = sum(units(it) for it in sample)
+    t_med = float(np.median(times))
+    return {"value": n_units / t_med, "cores": workers, "items": len(sample), "units": n_units,
+            "runs_s": [round(t, 4) for t in times], "median_s": t_med, "outputs": outs, "cpu_model": cpu_model()}
+
+
+def baseline_line(b: dict, unit: str, what: str) -> dict:
+    return {"value": b["value"], "unit": unit, "cores": b["cores"], "kind": "oracle",
+            "sample": f"{what}: {b['units']} units, FP64 numpy oracle, {b['cores']} worker processes, median of "
+                      f"{len(b['runs_s'])} passes ({', '.join(f'{t:.2f}' for t in b['runs_s'])} s)",
+            "cpu_model": b["cpu_model"], "statistic": f"median of {len(b['runs_s'])}"}
+
+
+def chunks(f: np.ndarray, size: int) -> list:
+    return [f[i:i + size] for i in range(0, len(f), size)]
 
 
 # Source file of the dominant kernel of each workload.
@@ -165,23 +289,6 @@ def time_launches(fn, steps: int, warmup: int, stream):
     return wall, per
 
 
-def cpu_baseline(f64: np.ndarray, target_s: float, N: int, L: float, kernel: str, M: int):
-    """The FP64 oracle on a bounded prefix of the same cells (single-threaded FFTs)."""
-    from oracle import spectral as sp
-    s = sp.Setup(d=2, N=N, L=L, kernel=kernel, M=M)
-    bank = sp.filter_bank(s)
-    done, t_used, chunk = 0, 0.0, 16
-    outs = []
-    while t_used < target_s and done < len(f64):
-        c = f64[done:done + chunk]
-        t0 = time.perf_counter()
-        q = sp.project_conservative(sp.q_fast(c, s, bank), 2, L)
-        t_used += time.perf_counter() - t0
-        outs.append(q)
-        done += len(c)
-    return done, t_used, np.concatenate(outs)
-
-
 def copy_calibration(mib: int, dev) -> None:
     """One device-to-device copy of `mib` MiB (a plain copy kernel of known size)
     after the timed region, for scaling hardware byte counters."""
@@ -196,28 +303,33 @@ def copy_calibration(mib: int, dev) -> None:
     del src, dst
 
 
-def serve_run(seconds: float, rate: float = 200.0, warm: float = 2.0) -> dict:
+def serve_run(seconds: float, rate: float = 200.0, warm: float = 2.0, budget_bytes: int = 256 << 20,
+              seed: int = 1003) -> dict:
     """Open-loop serving of homogeneous relaxation requests (continuous batching):
     Poisson arrivals, N in {16, 24, 32, 48, 64}, Maxwell or hard spheres, 50-400
-    explicit Euler steps of dt = 0.01; latencies of requests arriving in the
-    first `warm` seconds are discarded."""
+    explicit Euler steps of dt = 0.01, admission within an HBM budget; latencies
+    of requests arriving in the first `warm` seconds are discarded."""
     from paper_2103_14890_amd import serving as sv
-    reqs = sv.poisson_requests(int(seconds * rate), rate=rate, seed=1003, L=8.0)
-    server = sv.Server(L=8.0, M=8, precision="fx16", dt=0.01, eps=1.0, scheme="explicit")
+    reqs = sv.poisson_requests(int(seconds * rate), rate=rate, seed=seed, L=8.0)
+    server = sv.Server(L=8.0, M=8, precision="fx16", dt=0.01, eps=1.0, scheme="explicit",
+                       budget_bytes=budget_bytes)
     stats = server.run(reqs, realtime=True)
-    lat = np.array([r.latency for r in server.results.values() if not r.failed and r.arrival >= warm])
+    kept = [r for r in server.results.values() if not r.failed and r.arrival >= warm]
+    lat = np.array([r.latency for r in kept])
+    waits = np.array([r.admitted - r.arrival for r in kept])
     server.close()
     return {"requests": stats["requests"], "failed": stats["failed"], "rate_req_s": rate,
+            "budget_bytes": budget_bytes, "peak_pool_bytes": stats["peak_bytes"],
+            "waited": stats["waited"], "queue_wait_p99_ms": float(np.percentile(waits, 99) * 1e3),
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "throughput_req_s": stats["throughput_req_s"], "cell_steps_s": stats["cell_steps_s"],
-            "ticks": stats["ticks"], "wall_s": stats["wall_s"],
+            "ticks": stats["ticks"], "wall_s": stats["wall_s"], "discarded_first_s": warm,
             "mix": "N in {16,24,32,48,64}, Maxwell/hard spheres, 50-400 steps, M=8, FX16"}
 
 
 def bench_3d(args) -> int:
     import torch
     import workloads as wl
-    from oracle import spectral as sp
     from paper_2103_14890_amd import qcoll
 
     (name_a, Na, prec_a), (name_b, Nb, prec_b), L, kern, M, desc = WORKLOADS_3D[args.workload]
@@ -259,20 +371,24 @@ def bench_3d(args) -> int:
         peak = FP32_MFMA_PEAK
     T_roof = T_
 
-    # oracle on a bounded sample: equal numbers of cells of both resolutions
-    sa, sb = sp.Setup(d=3, N=Na, L=L, kernel=kern, M=M), sp.Setup(d=3, N=Nb, L=L, kernel=kern, M=M)
-    ba, bb = sp.filter_bank(sa), sp.filter_bank(sb)
-    done, t_cpu, errs = 0, 0.0, []
-    while t_cpu < args.cpu_seconds and done < 512:
-        i = done
-        t0 = time.perf_counter()
-        ra = sp.project_conservative(sp.q_fast(fa64[i:i + 1].astype(np.float32).astype(np.float64), sa, ba), 3, L)
-        rb = sp.project_conservative(sp.q_fast(fb64[i:i + 1].astype(np.float32).astype(np.float64), sb, bb), 3, L)
-        t_cpu += time.perf_counter() - t0
-        done += 1
-        errs.append((qa[i:i + 1].cpu().numpy(), ra, qb[i:i + 1].cpu().numpy(), rb))
-    num = sum(np.linalg.norm(x - y) ** 2 + np.linalg.norm(z - w) ** 2 for x, y, z, w in errs)
-    den = sum(np.linalg.norm(y) ** 2 + np.linalg.norm(w) ** 2 for x, y, z, w in errs)
+    # oracle on the host cores, a bounded prefix of each resolution's cells
+    ba = cpu_oracle_baseline("q_fast", dict(d=3, N=Na, L=L, kernel=kern, M=M),
+                             chunks(fa64.astype(np.float32).astype(np.float64), 1), len, args.cpu_seconds / 2)
+    bb = cpu_oracle_baseline("q_fast", dict(d=3, N=Nb, L=L, kernel=kern, M=M),
+                             chunks(fb64.astype(np.float32).astype(np.float64), 1), len, args.cpu_seconds / 2)
+    ra, rb = np.concatenate(ba.pop("outputs")), np.concatenate(bb.pop("outputs"))
+    ga, gb = qa[:len(ra)].cpu().numpy(), qb[:len(rb)].cpu().numpy()
+    num = np.linalg.norm(ga - ra) ** 2 + np.linalg.norm(gb - rb) ** 2
+    den = np.linalg.norm(ra) ** 2 + np.linalg.norm(rb) ** 2
+    worst = max(float((np.linalg.norm((g - r).reshape(len(r), -1), axis=1)
+                       / np.linalg.norm(r.reshape(len(r), -1), axis=1)).max()) for g, r in ((ga, ra), (gb, rb)))
+    # combined rate: the time of one cell of each resolution, as in the workload's 1:1 mix
+    t_pair = ba["median_s"] / ba["units"] + bb["median_s"] / bb["units"]
+    base = {"value": 2.0 / t_pair, "unit": "cell-evals/s", "cores": ba["cores"], "kind": "oracle",
+            "sample": f"first {ba['units']} cells at {Na}^3 and {bb['units']} at {Nb}^3, FP64 numpy oracle + "
+                      f"projection, {ba['cores']} worker processes, median of 3 passes each "
+                      f"({ba['median_s']:.2f} s, {bb['median_s']:.2f} s); rate of the 1:1 mix",
+            "cpu_model": ba["cpu_model"], "statistic": "median of 3"}
     qa_h = qa.cpu().numpy()
     mass = float((np.abs(qa_h.sum(axis=(1, 2, 3))) / np.abs(qa_h).sum(axis=(1, 2, 3))).max())
     out = {
@@ -293,10 +409,10 @@ def bench_3d(args) -> int:
         "roofline": {"bound": "mfma", "achieved": flops / T_roof / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": flops / T_roof / peak,
                      "traffic": measured_traffic(args.workload)},
-        "cpu_baseline": {"value": 2 * done / t_cpu, "unit": "cell-evals/s", "cores": 1, "kind": "oracle",
-                         "sample": f"first {done} cells of each resolution, FP64 numpy FFT oracle + projection, "
-                                   f"{t_cpu:.1f} s"},
+        "cpu_baseline": base,
         "rel_err_l2": float(math.sqrt(num / den)),
+        "worst_cell_rel": worst,
+        "parity_cells": [len(ra), len(rb)],
         "mass_defect_max": mass,
         "launch_ms": {"p5": float(np.percentile(per, 5) * 1e3), "p50": float(np.median(per) * 1e3),
                       "p95": float(np.percentile(per, 95) * 1e3)},
@@ -340,7 +456,6 @@ def transport_run(name: str, steps: int, warmup: int, stream):
 
 def bench_transport(args) -> int:
     import torch
-    from oracle import transport as tr
     stream = torch.cuda.current_stream()
     mesh, f64, N, L, plan, f, out, dt, per = transport_run(args.workload, args.steps, args.warmup, stream)
     copy_calibration(args.calibrate_copy, torch.device("cuda:0"))
@@ -349,21 +464,17 @@ def bench_transport(args) -> int:
     units = mesh.n * V
     alg_bytes = 8.0 * units            # f read once, the updated f written once
     flops = transport_flops(mesh, V)   # 53 flop per byte: above the FP32 ridge, an ALU-bound path
-    # the oracle on a bounded sample of cells (its tables built lazily for them)
-    T = tr.Transport(mesh, 2)
-    vel = tr.velocity_pairs(N, L)
+    # the oracle on the host cores: random cells (its tables are built lazily
+    # for them), in batches of 8
     f32 = f64.reshape(mesh.n, V).astype(np.float32).astype(np.float64)
     og = out.cpu().double().numpy().reshape(mesh.n, V)
-    rng = np.random.default_rng(11)
-    order = rng.permutation(mesh.n)
-    done, t_cpu, errs = 0, 0.0, []
-    while t_cpu < args.cpu_seconds and done < mesh.n:
-        c = order[done:done + 8]
-        t0 = time.perf_counter()
-        ref = T.step(f32, vel, dt, c)
-        t_cpu += time.perf_counter() - t0
-        errs.append(np.abs(og[c] - ref).max(axis=0))
-        done += len(c)
+    order = np.random.default_rng(11).permutation(mesh.n)
+    items = [order[i:i + 8] for i in range(0, mesh.n, 8)]
+    base = cpu_oracle_baseline("transport", {"name": args.workload, "dt": dt}, items, lambda c: len(c) * V,
+                               args.cpu_seconds, init_kw={"f": f32})
+    outs = base.pop("outputs")
+    done = sum(len(c) for c in items[:len(outs)])
+    errs = [np.abs(og[c] - r).max(axis=0) for c, r in zip(items, outs)]
     scale = np.maximum(np.abs(f32).max(axis=0), 1e-30)
     err = float((np.max(errs, axis=0) / scale).max())
     out_line = {
@@ -385,8 +496,7 @@ def bench_transport(args) -> int:
                      "unit": "TFLOP/s", "frac": flops / T_ / FP32_VALU_PEAK,
                      "traffic": measured_traffic(args.workload)},
         "hbm": {"algorithmic_bytes": alg_bytes, "achieved_GBs": alg_bytes / T_ / 1e9, "frac": alg_bytes / T_ / HBM_PEAK},
-        "cpu_baseline": {"value": done * V / t_cpu, "unit": "cell-velocity updates/s", "cores": 1, "kind": "oracle",
-                         "sample": f"{done} random cells x {V} velocities, FP64 numpy oracle step, {t_cpu:.1f} s"},
+        "cpu_baseline": baseline_line(base, "cell-velocity updates/s", f"{done} random cells x {V} velocities"),
         "max_err_scaled": err,
         "launch_ms": {"p5": float(np.percentile(per, 5) * 1e3), "p50": float(np.median(per) * 1e3),
                       "p95": float(np.percentile(per, 95) * 1e3)},
@@ -409,9 +519,6 @@ def bench_variant(args) -> int:
     """The Galerkin, classical and variable-hard-sphere variants of the operator."""
     import torch
     import workloads as wl
-    from oracle import classical as ocl
-    from oracle import galerkin as og
-    from oracle import spectral as sp
     from paper_2103_14890_amd import qcoll
 
     name, dev = args.workload, torch.device("cuda:0")
@@ -441,27 +548,16 @@ def bench_variant(args) -> int:
     T_ = float(np.mean(per))
     info = plan.info()
 
-    # the oracle on a bounded prefix of the same cells (tables built outside the clock)
-    s = sp.Setup(d=2, N=N, L=L, kernel=kern, M=M, gamma=0.5 if name == "vhs2d_32" else 1.0)
-    if name == "galerkin_32":
-        fine = og.galerkin_bank(s)
-        ref_fn = lambda c: og.q_galerkin(c, s, fine)          # noqa: E731
-    elif name == "classical_16":
-        beta = ocl.beta_table(s)
-        ref_fn = lambda c: ocl.q_classical(c, s, beta)        # noqa: E731
-    else:
-        s = dataclasses.replace(s, K_r=info["K_r"])
-        bank = sp.filter_bank(s)
-        ref_fn = lambda c: sp.q_fast(c, s, bank)               # noqa: E731
+    # the oracle on the host cores, a bounded prefix of the same cells (tables
+    # built outside the clock)
+    kw = dict(d=2, N=N, L=L, kernel=kern, M=M)
+    if name == "vhs2d_32":
+        kw.update(gamma=0.5, K_r=info["K_r"])
+    kind = {"galerkin_32": "galerkin", "classical_16": "classical"}.get(name, "q_fast")
     f32 = f64.astype(np.float32).astype(np.float64)
-    done, t_cpu, outs = 0, 0.0, []
-    while t_cpu < args.cpu_seconds and done < cells:
-        c = f32[done:done + 16]
-        t0 = time.perf_counter()
-        outs.append(sp.project_conservative(ref_fn(c), 2, L))
-        t_cpu += time.perf_counter() - t0
-        done += len(c)
-    ref = np.concatenate(outs)
+    base = cpu_oracle_baseline(kind, kw, chunks(f32, 16), len, args.cpu_seconds)
+    ref = np.concatenate(base.pop("outputs"))
+    done = ref.shape[0]
     got = q[:done].cpu().numpy()
     rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
 
@@ -486,9 +582,7 @@ def bench_variant(args) -> int:
         "config": {"workload": f"{name}: {WORKLOADS_VARIANT[name]}", "cells": cells, "N_v": f"{N}x{N}",
                    "kernel": kern, "M": M, "K_r": info["K_r"], "transforms": info["transforms"]},
         "roofline": roof,
-        "cpu_baseline": {"value": done / t_cpu, "unit": "cell-evals/s", "cores": 1, "kind": "oracle",
-                         "sample": f"first {done} cells of the same workload, FP64 numpy oracle + projection, "
-                                   f"{t_cpu:.1f} s"},
+        "cpu_baseline": baseline_line(base, "cell-evals/s", f"first {done} cells of the same workload"),
         "rel_err_l2": rel,
         "launch_ms": {"p5": float(np.percentile(per, 5) * 1e3), "p50": float(np.median(per) * 1e3),
                       "p95": float(np.percentile(per, 95) * 1e3)},
@@ -499,18 +593,59 @@ def bench_variant(args) -> int:
     return 0
 
 
+def graph_of(fn):
+    """Capture fn (queued on the current stream) into a graph after one eager
+    call on a side stream; returns the graph, whose replay repeats fn."""
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    torch.cuda.synchronize()
+    return g
+
+
+def roofline_2d(cells: int, T: float, transforms: int, N: int, precision: str, traffic) -> tuple[dict, dict]:
+    """Main roofline (algorithmic FFT flops against the peak of the DFT-GEMM
+    dtype) and the other counting conventions of the same launch."""
+    peak = FP16_MFMA_PEAK if precision == "fx16" else FP32_MFMA_PEAK
+    alg = alg_flops_per_cell(2, N, transforms - 1)
+    gemm = mfma_flops_per_cell("fp32", transforms, N)     # FP32-equivalent DFT-GEMM work as executed
+    main = {"bound": "mfma", "achieved": alg * cells / T / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": alg * cells / T / peak, "traffic": traffic,
+            "flops_per_cell": alg, "basis": "algorithmic: the method's FFT and pointwise work per cell"}
+    conv = {"gemm_fp32_equiv": {"flops_per_cell": gemm, "achieved_tflops": gemm * cells / T / 1e12,
+                                "frac": gemm * cells / T / peak}}
+    if precision == "fx16":
+        conv["gemm_x3"] = {"flops_per_cell": 3 * gemm, "achieved_tflops": 3 * gemm * cells / T / 1e12,
+                           "frac": 3 * gemm * cells / T / peak,
+                           "basis": "split-precision convention: three FP16 products per DFT-GEMM"}
+        conv["executed_fx16_x6"] = {"flops_per_cell": 6 * gemm, "achieved_tflops": 6 * gemm * cells / T / 1e12,
+                                    "frac": 6 * gemm * cells / T / peak,
+                                    "basis": "the six FP16 products this kernel issues per DFT-GEMM"}
+    return main, conv
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="host time for the three timed passes of the oracle baseline together")
     ap.add_argument("--workload", default="hs2d_32",
                     choices=sorted(WORKLOADS) + sorted(WORKLOADS_3D) + sorted(WORKLOADS_TRANSPORT)
                     + sorted(WORKLOADS_VARIANT))
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
-                    help="length of the open-loop serving run (Poisson arrivals at 200 requests/s) "
-                         "behind p99_latency_ms; 0 skips it")
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="length of the open-loop serving run (Poisson arrivals at 200 requests/s, 256 MB "
+                         "budget) behind p99_latency_ms; 0 skips it and the stress run")
+    ap.add_argument("--stress-seconds", type=float, default=10.0,
+                    help="length of each serving run under a small budget (1 MB, then 128 KB)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, copy a buffer of this many MiB once (a plain copy kernel of "
                          "known size, for scaling hardware byte counters)")
@@ -539,25 +674,53 @@ def main() -> int:
     stream = torch.cuda.current_stream()
 
     res = {}
-    precs = ("fx16", "fp32") if NN <= 32 else ("fx16",)
+    precs = ("fx16", "fp32")
     for prec in precs:
-        plan = qcoll.Plan(2, NN, LL, KERN, MM, precision=prec, conserve=True)
+        try:
+            plan = qcoll.Plan(2, NN, LL, KERN, MM, precision=prec, conserve=True)
+        except qcoll.QcollError as e:
+            if e.code != qcoll.EUNSUPPORTED:
+                raise
+            continue
         q = torch.empty((cells, NN, NN), dtype=torch.float64, device=dev)
-        wall, per = time_launches(lambda: plan.eval(f, q), args.steps, args.warmup, stream)
-        info = plan.info()
-        res[prec] = dict(plan=plan, q=q, wall=wall, per=per, info=info)
+        # eager calls with the default launch shape
+        _, per = time_launches(lambda: plan.eval(f, q), args.steps, args.warmup, stream)
+        res[prec] = dict(plan=plan, q=q, per=per, info=plan.info(), eager_default=float(np.mean(per)),
+                         default_shape=plan.launch())
+        # the spec form: launch shape from the autotuner, the call captured in a graph
+        res[prec]["tuned_shape"] = plan.autotune(f, reps=3)
+        _, per_e = time_launches(lambda: plan.eval(f, q), args.steps, args.warmup, stream)
+        g = graph_of(lambda: plan.eval(f, q))
+        _, per_g = time_launches(g.replay, args.steps, args.warmup, stream)
+        res[prec].update(per=per_g, graph=g, eager_tuned=float(np.mean(per_e)))
 
     copy_calibration(args.calibrate_copy, dev)
 
-    # accuracy on a sample, against the oracle (also the CPU-baseline run)
-    ncpu, t_cpu, q_ref = cpu_baseline(f64.astype(np.float32).astype(np.float64), args.cpu_seconds, NN, LL, KERN, MM)
+    # the oracle on the host cores (the CPU baseline) and the accuracy of both paths against it
+    f32 = f64.astype(np.float32).astype(np.float64)
+    base = cpu_oracle_baseline("q_fast", dict(d=2, N=NN, L=LL, kernel=KERN, M=MM), chunks(f32, 16),
+                               len, args.cpu_seconds)
+    q_ref = np.concatenate(base.pop("outputs"))
+    ncpu = q_ref.shape[0]
     for prec in res:
         qg = res[prec]["q"][:ncpu].cpu().numpy()
         res[prec]["rel_err"] = float(np.linalg.norm(qg - q_ref) / np.linalg.norm(q_ref))
+        # per cell: the error against the cell's own |Q| (large for cells near
+        # equilibrium, whose Q nearly vanishes) and against the batch's RMS |Q|
+        nq = np.linalg.norm(q_ref.reshape(ncpu, -1), axis=1)
+        de = np.linalg.norm((qg - q_ref).reshape(ncpu, -1), axis=1)
+        res[prec]["worst_cell"] = float((de / nq).max())
+        res[prec]["cell_p99"] = float(np.percentile(de / nq, 99))
+        res[prec]["worst_cell_rms"] = float((de / np.sqrt(np.mean(nq ** 2))).max())
         qa = res[prec]["q"].cpu().numpy()
         res[prec]["mass"] = float((np.abs(qa.sum(axis=(1, 2))) / np.abs(qa).sum(axis=(1, 2))).max())
 
-    serve = serve_run(args.serve_seconds) if args.serve_seconds > 0 else None
+    serve = stress = tight = None
+    if args.serve_seconds > 0:
+        serve = serve_run(args.serve_seconds)
+        stress = serve_run(args.stress_seconds, budget_bytes=1 << 20, seed=1013)
+        # a budget below the live footprint of this arrival rate, so that admission queues
+        tight = serve_run(args.stress_seconds, budget_bytes=128 << 10, seed=1023)
 
     # time steps of the homogeneous relaxation on the same cells (FX16 plan
     # without projection): single-stage IMEX Euler (one launch) and the
@@ -575,27 +738,33 @@ def main() -> int:
     splan.close()
     del fs, work
 
-    # the transport step of the explosion_16k mesh (the second HBM-bound path)
-    mesh_t, _, Nt, _, tplan, _, _, _, per_t = transport_run("explosion_16k", max(5, args.steps // 5), 2, stream)
-    Tt = float(np.mean(per_t))
-    transport = {"workload": "explosion_16k", "ms_per_step": Tt * 1e3,
-                 "value": mesh_t.n * Nt * Nt / Tt, "unit": "cell-velocity updates/s",
-                 "alu_frac": transport_flops(mesh_t, Nt * Nt) / Tt / FP32_VALU_PEAK}
-    tplan.close()
+    transport = None
+    if NN == 32:
+        # the transport step of the explosion_16k mesh (the second HBM-bound path)
+        mesh_t, _, Nt, _, tplan, _, _, _, per_t = transport_run("explosion_16k", max(5, args.steps // 5), 2, stream)
+        Tt = float(np.mean(per_t))
+        transport = {"workload": "explosion_16k", "ms_per_step": Tt * 1e3,
+                     "value": mesh_t.n * Nt * Nt / Tt, "unit": "cell-velocity updates/s",
+                     "alu_frac": transport_flops(mesh_t, Nt * Nt) / Tt / FP32_VALU_PEAK}
+        tplan.close()
 
     mix = res["fx16"]
     T = float(np.mean(mix["per"]))
     value = cells / T
-    flops = mfma_flops_per_cell("fx16", mix["info"]["transforms"], NN) * cells
-    dense = mfma_flops_per_cell("fp32", mix["info"]["transforms"], NN) * cells
+    roof, conv = roofline_2d(cells, T, mix["info"]["transforms"], NN, "fx16", measured_traffic(args.workload))
     fp32 = res.get("fp32")
+    fp32_line = None
     if fp32 is not None:
         T32 = float(np.mean(fp32["per"]))
-        flops32 = mfma_flops_per_cell("fp32", fp32["info"]["transforms"], NN) * cells
-    threads = 1   # the oracle's numpy FFTs run on one core
+        r32, c32 = roofline_2d(cells, T32, fp32["info"]["transforms"], NN, "fp32", None)
+        fp32_line = {"value": cells / T32, "ms_per_step": T32 * 1e3, "eager_default_ms": fp32["eager_default"] * 1e3,
+                     "rel_err_l2": fp32["rel_err"], "worst_cell_rel": fp32["worst_cell"],
+                     "cell_rel_p99": fp32["cell_p99"], "worst_cell_vs_rms": fp32["worst_cell_rms"],
+                     "roofline_frac": r32["frac"], "gemm_frac_fp32_peak": c32["gemm_fp32_equiv"]["frac"],
+                     "mass_defect_max": fp32["mass"], "launch_shape": list(fp32["tuned_shape"])}
     out = {
         "metric": ("cell Q(f,f) evals/s at N_v=32^2, mixed vs FP32 at rel.err<=1e-5; p99 latency" if NN == 32 else
-                   f"cell Q(f,f) evals/s at N_v={NN}^2, mixed (FX16) precision against the FP64 oracle"),
+                   f"cell Q(f,f) evals/s at N_v={NN}^2, mixed (FX16) vs FP32 against the FP64 oracle"),
         "value": value,
         "unit": "cell-evals/s",
         "n_gpus": 1,
@@ -609,20 +778,21 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {DESC}",
                    "cells": cells, "N_v": f"{NN}x{NN}", "kernel": KERN, "M": MM,
-                   "K_r": mix["info"]["K_r"]},
-        "roofline": {"bound": "mfma", "achieved": flops / T / 1e12, "peak": FP16_MFMA_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": flops / T / FP16_MFMA_PEAK,
-                     "traffic": measured_traffic(args.workload)},
-        "cpu_baseline": {"value": ncpu / t_cpu, "unit": "cell-evals/s", "cores": threads, "kind": "oracle",
-                         "sample": f"first {ncpu} cells of the same workload, FP64 numpy FFT oracle "
-                                   f"+ projection, {t_cpu:.1f} s"},
+                   "K_r": mix["info"]["K_r"],
+                   "timed": "graph replay of one evaluation over all cells, autotuned launch shape"},
+        "roofline": roof,
+        "roofline_conventions": conv,
+        "cpu_baseline": baseline_line(base, "cell-evals/s", f"first {ncpu} cells of the same workload"),
         "rel_err_l2": mix["rel_err"],
+        "worst_cell_rel": mix["worst_cell"],
+        "cell_rel_p99": mix["cell_p99"],
+        "worst_cell_vs_rms": mix["worst_cell_rms"],
+        "parity_cells": ncpu,
         "mass_defect_max": mix["mass"],
-        "dense_gemm_tflops": dense / T / 1e12,
-        "fp32_path": None if fp32 is None else {
-            "value": cells / T32, "ms_per_step": T32 * 1e3, "rel_err_l2": fp32["rel_err"],
-            "roofline_frac": flops32 / T32 / FP32_MFMA_PEAK, "mass_defect_max": fp32["mass"]},
-        "speedup_vs_fp32": None if fp32 is None else T32 / T,
+        "eager_ms": {"default_shape": mix["eager_default"] * 1e3, "tuned_shape": mix["eager_tuned"] * 1e3},
+        "launch_shape": {"default": list(mix["default_shape"]), "tuned": list(mix["tuned_shape"])},
+        "fp32_path": fp32_line,
+        "speedup_vs_fp32": None if fp32 is None else float(np.mean(fp32["per"])) / T,
         "launch_ms": {"p5": float(np.percentile(mix["per"], 5) * 1e3),
                       "p50": float(np.median(mix["per"]) * 1e3),
                       "p95": float(np.percentile(mix["per"], 95) * 1e3)},
@@ -630,6 +800,8 @@ def main() -> int:
         "transport": transport,
         "p99_latency_ms": None if serve is None else serve["p99_ms"],
         "serving": serve,
+        "serving_stress": stress,
+        "serving_queueing": tight,
     }
     print(json.dumps(out))
     for prec in res:

@@ -93,10 +93,10 @@ enum {
  * tables; apart from its launch shape (qcoll_plan_set_launch, set before use)
  * it is immutable and may be used from several streams at once, except 3D
  * plans, whose scratch area allows one call in flight at a time. On error *out
- * is set to NULL. Device plans: d = 2 with N <= 32 in either precision (grids
- * below 16 or 32 run zero-padded in a 16x16 or 32x32 tile) and 34 <= N <= 64
- * in QCOLL_MIX_FX16 (radix-2 split into 32-point tiles, one workgroup per
- * cell); d = 3 hard spheres with N <= 32 in either precision (zero-padded
+ * is set to NULL. Device plans: d = 2 with N <= 32 (grids below 16 or 32 run
+ * zero-padded in a 16x16 or 32x32 tile) and 34 <= N <= 64 (radix-2 split into
+ * 32-point tiles, one workgroup per cell), both in either precision; d = 3
+ * hard spheres with N <= 32 in either precision (zero-padded
  * 16^3 or 32^3 tiles, one workgroup per cell,
  * a scratch area of 144 T^3 bytes per resident workgroup held by the plan; the
  * 3D FX16 variant splits the DFT-GEMM operands as in 2D but keeps spectra,

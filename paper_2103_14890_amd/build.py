@@ -5,6 +5,7 @@
 
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -52,16 +53,21 @@ def build(verbose: bool = False, extra: list[str] | None = None) -> str:
     hipcc = _hipcc()
     extra = list(extra or [])
     with tempfile.TemporaryDirectory(prefix="qcoll_build_") as tmp:
-        objs = []
+        cmds, objs = [], []
         for src in HOST_SOURCES:
             obj = os.path.join(tmp, src + ".o")
-            _run([hipcc, "-x", "c++", *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+            cmds.append([hipcc, "-x", "c++", *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
             objs.append(obj)
         for src in DEVICE_SOURCES:
             obj = os.path.join(tmp, src + ".o")
-            _run([hipcc, "-x", "hip", *COMMON, *DEVICE_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj],
-                 verbose)
+            cmds.append([hipcc, "-x", "hip", *COMMON, *DEVICE_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o",
+                         obj])
             objs.append(obj)
+        # independent compilations, a few at a time
+        jobs = max(1, min(8, os.cpu_count() or 1))
+        with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
+            for fut in [ex.submit(_run, c, verbose) for c in cmds]:
+                fut.result()
         tmp_lib = os.path.join(tmp, "libqcoll.so")
         _run([hipcc, "-shared", f"--offload-arch={ARCH}", *objs, "-o", tmp_lib], verbose)
         shutil.copyfile(tmp_lib, LIB + ".tmp")

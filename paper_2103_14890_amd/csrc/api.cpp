@@ -300,33 +300,46 @@ int build_device_2d64(qcoll_plan_s* p) {
   const auto& hp = p->hp;
   const int n = hp.N, np = n / 2;
   const int P = static_cast<int>(hp.packed.size());
-  std::vector<_Float16> ec(64 * 3 * 2 * 3 * 8);
-  for (int lane = 0; lane < 64; ++lane) {
-    int h = lane >> 5, c = lane & 31;
-    for (int m = 0; m < 3; ++m)
-      for (int s = 0; s < 2; ++s)
-        for (int t = 0; t < 8; ++t) {
-          int k = rrow(8 * s + t, h);
-          double val = 0.0;
-          if (k < np && c < np) {
-            double ang = 2.0 * kPi * static_cast<double>((k * c) % np) / np;
-            val = m == 0 ? std::cos(ang) : (m == 1 ? std::sin(ang) : -std::sin(ang));
+  // n'-point DFT-matrix value e_m(k, j) (cos, sin, -sin), zero outside n' x n'
+  auto emat = [&](int m, int k, int j) -> double {
+    if (k >= np || j >= np) return 0.0;
+    const double ang = 2.0 * kPi * static_cast<double>((k * j) % np) / np;
+    return m == 0 ? std::cos(ang) : (m == 1 ? std::sin(ang) : -std::sin(ang));
+  };
+  int rc;
+  if (p->precision == QCOLL_FP32) {
+    // FP32 32x32x2 operands: [lane][mat][v] = E_mat[rrow(v, h)][c]
+    std::vector<float> ec(64 * 48);
+    for (int lane = 0; lane < 64; ++lane)
+      for (int m = 0; m < 3; ++m)
+        for (int v = 0; v < 16; ++v)
+          ec[lane * 48 + 16 * m + v] = static_cast<float>(emat(m, rrow(v, lane >> 5), lane & 31));
+    float* d = nullptr;
+    rc = upload(ec, &d, p->device_bytes);
+    p->econst = d;
+    if (rc) return rc;
+  } else {
+    // FX16: 2^9 e split into lead/hi/lo, [lane][mat][K-slice s][part][t] at row rrow(8 s + t, h)
+    std::vector<_Float16> ec(64 * 3 * 2 * 3 * 8);
+    for (int lane = 0; lane < 64; ++lane)
+      for (int m = 0; m < 3; ++m)
+        for (int s = 0; s < 2; ++s)
+          for (int t = 0; t < 8; ++t) {
+            const double y = 512.0 * emat(m, rrow(8 * s + t, lane >> 5), lane & 31);
+            const double lead = std::nearbyint(y);
+            const float r = static_cast<float>(y - lead);
+            const _Float16 hi = static_cast<_Float16>(r);
+            const _Float16 lo = static_cast<_Float16>(r - static_cast<float>(hi));
+            const size_t base = ((((static_cast<size_t>(lane) * 3 + m) * 2 + s) * 3) * 8) + t;
+            ec[base] = static_cast<_Float16>(static_cast<float>(lead));
+            ec[base + 8] = hi;
+            ec[base + 16] = lo;
           }
-          double y = 512.0 * val;
-          double lead = std::nearbyint(y);
-          float r = static_cast<float>(y - lead);
-          _Float16 hi = static_cast<_Float16>(r);
-          _Float16 lo = static_cast<_Float16>(r - static_cast<float>(hi));
-          size_t base = ((((static_cast<size_t>(lane) * 3 + m) * 2 + s) * 3) * 8) + t;
-          ec[base] = static_cast<_Float16>(static_cast<float>(lead));
-          ec[base + 8] = hi;
-          ec[base + 16] = lo;
-        }
+    _Float16* d = nullptr;
+    rc = upload(ec, &d, p->device_bytes);
+    p->econst = d;
+    if (rc) return rc;
   }
-  _Float16* d = nullptr;
-  int rc = upload(ec, &d, p->device_bytes);
-  p->econst = d;
-  if (rc) return rc;
   std::vector<double> ft(static_cast<size_t>(P + 1) * 4 * 64 * 32, 0.0);
   std::vector<int> fe(P + 1, 0);
   for (int q = 0; q <= P; ++q) {
@@ -518,7 +531,7 @@ qcoll::KernelArgs make_args(const qcoll_plan_s* p) {
 }
 
 // 2D grids up to 32 points per axis run on the 16x16 (N <= 16) or 32x32 tile
-// kernels; grids of 34..64 points on the tile-64 kernel (FX16 only).
+// kernels; grids of 34..64 points on the tile-64 kernels (FX16 or FP32).
 // Dense kernel-mode table of the classical method: beta[l][m] = B(l, m) - B(m, m)
 // with B(l, m) = sum_t W_t alpha_t(l) alpha'_t(m) over the terms of `src` (zero
 // wherever l or m is a Nyquist mode, as the filters are). Rows split over host
@@ -552,8 +565,7 @@ void classical_table(const qcoll::HostPlan& src, std::vector<double>& beta) {
 bool device_supported(const qcoll::HostPlan& hp, int precision) {
   if (hp.d == 3) return hp.N <= 32 && (precision == QCOLL_FP32 || precision == QCOLL_MIX_FX16);
   if (hp.d != 2) return false;
-  if (hp.N <= 32) return true;
-  return hp.N <= 64 && precision == QCOLL_MIX_FX16;
+  return hp.N <= 64;
 }
 
 }  // namespace

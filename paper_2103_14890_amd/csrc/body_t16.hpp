@@ -83,10 +83,10 @@ __device__ __forceinline__ void fx16_t16_body(const KernelArgs& a, int64_t first
     float fm = fmaxf(fmaxf(fabsf(fv[0]), fabsf(fv[1])), fmaxf(fabsf(fv[2]), fabsf(fv[3])));
     fm = wave_max(fm);
     const int a0 = 9 - exp_above(fm);
-    const float cf = ldexpf(1.0f, a0);
+    const double cf = ldexp(1.0, a0);  // FP64: 2^a0 exceeds the FP32 range for max|f| < 2^-118
     Split3 A;
-    put2(A, 0, split2_f64(static_cast<double>(fv[0] * cf), static_cast<double>(fv[1] * cf)));
-    put2(A, 2, split2_f64(static_cast<double>(fv[2] * cf), static_cast<double>(fv[3] * cf)));
+    put2(A, 0, split2_f64(static_cast<double>(fv[0]) * cf, static_cast<double>(fv[1]) * cf));
+    put2(A, 2, split2_f64(static_cast<double>(fv[2]) * cf, static_cast<double>(fv[3]) * cf));
 #pragma unroll
     for (int t = 4; t < 8; ++t) A.l[t] = A.h[t] = A.o[t] = static_cast<_Float16>(0.0f);
     f32x4 r0, r1, i0, i1;

@@ -201,10 +201,10 @@ __device__ __forceinline__ void fx16_t32_body(const KernelArgs& a, int64_t first
       for (int v = 0; v < 16; ++v) fm = fmaxf(fm, fabsf(fv[v]));
       fm = wave_max(fm);
       const int a0 = 9 - exp_above(fm);
-      const float cf = ldexpf(1.0f, a0);
+      const double cf = ldexp(1.0, a0);  // FP64: 2^a0 exceeds the FP32 range for max|f| < 2^-118
 #pragma unroll
       for (int v = 0; v < 16; v += 2)
-        put2(A[v >> 3], v & 7, split2_f64(static_cast<double>(fv[v] * cf), static_cast<double>(fv[v + 1] * cf)));
+        put2(A[v >> 3], v & 7, split2_f64(static_cast<double>(fv[v]) * cf, static_cast<double>(fv[v + 1]) * cf));
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         mma6_lo_lds(A[s], E[kEr][s], eo + (kEr * 2 + s) * 64 + lane, r0, r1);
@@ -355,10 +355,10 @@ __device__ __forceinline__ void fx16_t32_body_pp(const KernelArgs& a, int64_t fi
       for (int v = 0; v < 16; ++v) fm = fmaxf(fm, fabsf(fv[v]));
       fm = wave_max(fm);
       const int a0 = 9 - exp_above(fm);
-      const float cf = ldexpf(1.0f, a0);
+      const double cf = ldexp(1.0, a0);  // FP64: 2^a0 exceeds the FP32 range for max|f| < 2^-118
 #pragma unroll
       for (int v = 0; v < 16; v += 2)
-        put2(A[v >> 3], v & 7, split2_f64(static_cast<double>(fv[v] * cf), static_cast<double>(fv[v + 1] * cf)));
+        put2(A[v >> 3], v & 7, split2_f64(static_cast<double>(fv[v]) * cf, static_cast<double>(fv[v + 1]) * cf));
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         mma6_lo_lds(A[s], E[kEr][s], eo + (kEr * 2 + s) * 64 + lane, r0, r1);

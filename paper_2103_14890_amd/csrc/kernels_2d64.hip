@@ -61,8 +61,60 @@ __device__ __forceinline__ void load_subgrid(const KernelArgs& a, int64_t cell, 
   }
 }
 
-template <int OUT>
-__global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
+// Per-lane operands of the n'-point DFT matrices for the FP32 variant
+// (v_mfma_f32_32x32x2f32): for register v, E[rrow(v, h)][c] of cos, sin and
+// -sin, zero outside n' x n'.
+struct E32 {
+  float r[16], i[16], n[16];
+};
+
+// The FP32 variant's forward (real input, then complex) and inverse (complex,
+// twice) 32-point tile passes, as in the 32x32 FP32 kernel.
+__device__ __forceinline__ void fwd_fp32(const E32& E, const float* fv, f32x16& fre, f32x16& fim) {
+  f32x16 re{}, im{};
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    re = mfma32(fv[v], E.r[v], re);
+    im = mfma32(fv[v], E.n[v], im);
+  }
+  fre = fim = f32x16{};
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    fre = mfma32(re[v], E.r[v], fre);
+    fre = mfma32(im[v], E.i[v], fre);
+    fim = mfma32(re[v], E.n[v], fim);
+    fim = mfma32(im[v], E.r[v], fim);
+  }
+}
+
+__device__ __forceinline__ void inv_fp32(const E32& E, const float* zr, const float* zi, bool want_im, f32x16& yr,
+                                         f32x16& yi) {
+  f32x16 dr{}, di{};
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    dr = mfma32(zr[v], E.r[v], dr);
+    dr = mfma32(zi[v], E.n[v], dr);
+    di = mfma32(zr[v], E.i[v], di);
+    di = mfma32(zi[v], E.r[v], di);
+  }
+  yr = yi = f32x16{};
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    yr = mfma32(dr[v], E.r[v], yr);
+    yr = mfma32(di[v], E.n[v], yr);
+    if (want_im) {
+      yi = mfma32(dr[v], E.i[v], yi);
+      yi = mfma32(di[v], E.r[v], yi);
+    }
+  }
+}
+
+// FX = true: FX16 DFT-GEMMs (three-part FP16 splits, six products, power-of-two
+// scales tracked as integers); FX = false: FP32 DFT-GEMMs, the plain FP32 path.
+// Everything between the passes (quarter exchange, twiddles, filter products,
+// gain) is FP64 in both; the FP32 variant rounds each pass's input to FP32.
+template <int OUT, bool FX>
+__device__ __forceinline__ void t64_body(const KernelArgs& a) {
   extern __shared__ double2 lds_raw[];   // 16-byte aligned base
   double* lds = reinterpret_cast<double*>(lds_raw);
   Cd* zs = reinterpret_cast<Cd*>(lds);                 // [4][16][64]
@@ -84,9 +136,10 @@ __global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
 #pragma unroll
   for (int v = 0; v < 16; ++v) twp[v * 64 + lane] = cmul(tw[32 * p1 + rrow(v, h)], c2);
 
-  load_eo_table(a, eo);
   Split2 E[3][2];
-  {
+  E32 E3;
+  if constexpr (FX) {
+    load_eo_table(a, eo);
     const half8* src = reinterpret_cast<const half8*>(a.econst) + lane * 18;
 #pragma unroll
     for (int m = 0; m < 3; ++m)
@@ -95,6 +148,15 @@ __global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
         E[m][s].l = src[(m * 2 + s) * 3 + 0];
         E[m][s].h = src[(m * 2 + s) * 3 + 1];
       }
+  } else {
+    (void)eo;
+    const float* src = reinterpret_cast<const float*>(a.econst) + lane * 48;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      E3.r[v] = src[v];
+      E3.i[v] = src[16 + v];
+      E3.n[v] = src[32 + v];
+    }
   }
   const double sgn[4] = {1.0, (p2 ? -1.0 : 1.0), (p1 ? -1.0 : 1.0), ((p1 ^ p2) ? -1.0 : 1.0)};
 
@@ -102,28 +164,34 @@ __global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
     // ---- own parity sub-grid x[m1][m2] = f[2 m1 + p1][2 m2 + p2]
     float fv[16];
     load_subgrid(a, cell, p1, p2, fv);
-    // ---- n'-point 2D DFT of the sub-grid (as in the N <= 32 kernel)
-    float fm = 0.0f;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) fm = fmaxf(fm, fabsf(fv[v]));
-    fm = wave_max(fm);
-    const int a0 = 9 - exp_above(fm);
-    const float cf = ldexpf(1.0f, a0);
+    // ---- n'-point 2D DFT of the sub-grid (as in the N <= 32 kernels); the
+    // true values are acc * 2^sc (acc = r0 + r1, i0 + i1)
     Split3 A[4];
-#pragma unroll
-    for (int v = 0; v < 16; v += 2)
-      put2(A[v >> 3], v & 7, split2_f64(static_cast<double>(fv[v] * cf), static_cast<double>(fv[v + 1] * cf)));
     f32x16 r0{}, r1{}, i0{}, i1{};
+    int sc = 0;
+    if constexpr (FX) {
+      float fm = 0.0f;
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      mma6_lo_lds(A[s], E[kEr][s], eo + (kEr * 2 + s) * 64 + lane, r0, r1);
-      mma6_lo_lds(A[s], E[kNEi][s], eo + (kNEi * 2 + s) * 64 + lane, i0, i1);
+      for (int v = 0; v < 16; ++v) fm = fmaxf(fm, fabsf(fv[v]));
+      fm = wave_max(fm);
+      const int a0 = 9 - exp_above(fm);
+      const double cf = ldexp(1.0, a0);  // FP64: 2^a0 exceeds the FP32 range for max|f| < 2^-118
+#pragma unroll
+      for (int v = 0; v < 16; v += 2)
+        put2(A[v >> 3], v & 7, split2_f64(static_cast<double>(fv[v]) * cf, static_cast<double>(fv[v + 1]) * cf));
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        mma6_lo_lds(A[s], E[kEr][s], eo + (kEr * 2 + s) * 64 + lane, r0, r1);
+        mma6_lo_lds(A[s], E[kNEi][s], eo + (kNEi * 2 + s) * 64 + lane, i0, i1);
+      }
+      sc = -(a0 + 9);
+      const int a1 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
+      slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a1), A);
+      pass64_lo_lds(A, E, eo, kEr, kEi, kNEi, kEr, true, r0, r1, i0, i1);
+      sc = sc - a1 - 9;
+    } else {
+      fwd_fp32(E3, fv, r0, i0);
     }
-    int sc = -(a0 + 9);
-    const int a1 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
-    slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a1), A);
-    pass64_lo_lds(A, E, eo, kEr, kEi, kNEi, kEr, true, r0, r1, i0, i1);
-    sc = sc - a1 - 9;
     // ---- twiddle w^(-k'.p) and exchange: T_p -> f_hat quarter a = w
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -165,23 +233,28 @@ __global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
       for (int v = 0; v < 16; ++v) mvv[v] = mq[v * 64 + ml];
       __builtin_amdgcn_sched_barrier(0);
       const double zsc = ldexp(1.0, a.filt_exp[q]);
-      float zm = 0.0f;
+      // (the maximum in FP64: true values can lie outside the FP32 range)
+      double zm = 0.0;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const double mr = mvv[v].x * zsc, mi = mvv[v].y * zsc;
         const Cd z = {mr * fr[v] - mi * fi[v], mr * fi[v] + mi * fr[v]};
         zs[(w * 16 + v) * 64 + lane] = z;
-        zm = fmaxf(zm, fmaxf(fabsf(static_cast<float>(z.x)), fabsf(static_cast<float>(z.y))));
+        if (FX) zm = fmax(zm, fmax(fabs(z.x), fabs(z.y)));
         if (v & 1) __builtin_amdgcn_sched_barrier(0);
       }
-      zm = wave_max(zm);
-      if (lane == 0) red[w * 4 + 3] = zm;
+      if constexpr (FX) {
+        zm = wave_max_d(zm);
+        if (lane == 0) red[w * 4 + 3] = zm;
+      }
       __syncthreads();
       // |G_p| <= sum_a max |Z_a| (twiddles have modulus one): common slicing scale
-      const float gb = static_cast<float>(red[3] + red[7] + red[11] + red[15]) * 1.0000005f;
-      const int b = 9 - (exp_above(gb) + 1);
+      int b = 0;
+      if constexpr (FX) b = 9 - (exp_above_d((red[3] + red[7] + red[11] + red[15]) * 1.0000005) + 1);
       // G_p = w^(k'.p) sum_a (-1)^(a.p) Z_a for this wave's parity class, split
-      // into the left operand of the first inverse pass as it is formed
+      // into the left operand of the first inverse pass as it is formed (FP32:
+      // rounded to the FP32 operand)
+      float zr[16], zi[16];
 #pragma unroll
       for (int v = 0; v < 16; v += 2) {
         double gr[2], gi[2];
@@ -195,33 +268,51 @@ __global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
             si += sgn[s] * t.y;
           }
           const Cd g = cmul(twp[(v + u) * 64 + lane], {sr, si});
-          gr[u] = ldexp(g.x, b);
-          gi[u] = ldexp(g.y, b);
+          gr[u] = FX ? ldexp(g.x, b) : g.x;
+          gi[u] = FX ? ldexp(g.y, b) : g.y;
         }
-        put2(A[v >> 3], v & 7, split2_f64(gr[0], gr[1]));
-        put2(A[2 + (v >> 3)], v & 7, split2_f64(gi[0], gi[1]));
+        if constexpr (FX) {
+          put2(A[v >> 3], v & 7, split2_f64(gr[0], gr[1]));
+          put2(A[2 + (v >> 3)], v & 7, split2_f64(gi[0], gi[1]));
+        } else {
+          zr[v] = static_cast<float>(gr[0]);
+          zr[v + 1] = static_cast<float>(gr[1]);
+          zi[v] = static_cast<float>(gi[0]);
+          zi[v + 1] = static_cast<float>(gi[1]);
+        }
         __builtin_amdgcn_sched_barrier(0);  // bound the LDS reads in flight
       }
       __syncthreads();
-      pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
-      int sd = -b - 9;
-      const int a2 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
-      slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a2), A);
-      pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, q < a.P, r0, r1, i0, i1);  // loss: real part only
-      sd = sd - a2 - 9;
-      sd_last = sd;
-      const double wq = q < a.P ? ldexp(1.0, 2 * sd) : 0.0;
+      if constexpr (FX) {
+        pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
+        int sd = -b - 9;
+        const int a2 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
+        slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a2), A);
+        pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, q < a.P, r0, r1, i0, i1);  // loss: real part only
+        sd = sd - a2 - 9;
+        sd_last = sd;
+        const double wq = q < a.P ? ldexp(1.0, 2 * sd) : 0.0;
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        double re = static_cast<double>(r0[v]) + static_cast<double>(r1[v]);
-        double im = static_cast<double>(i0[v]) + static_cast<double>(i1[v]);
-        gain[v] = fma(re * wq, im, gain[v]);
+        for (int v = 0; v < 16; ++v) {
+          double re = static_cast<double>(r0[v]) + static_cast<double>(r1[v]);
+          double im = static_cast<double>(i0[v]) + static_cast<double>(i1[v]);
+          gain[v] = fma(re * wq, im, gain[v]);
+        }
+      } else {
+        inv_fp32(E3, zr, zi, q < a.P, r0, i0);   // loss: real part only
+        if (q < a.P) {
+#pragma unroll
+          for (int v = 0; v < 16; ++v) gain[v] += static_cast<double>(r0[v] * i0[v]);
+        }
       }
     }
-load_subgrid(a, cell, p1, p2, fv);  // re-read: not kept live through the filter loop
+    load_subgrid(a, cell, p1, p2, fv);  // re-read: not kept live through the filter loop
 #pragma unroll
-    for (int v = 0; v < 16; ++v)
-      gain[v] -= static_cast<double>(fv[v]) * ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), sd_last);
+    for (int v = 0; v < 16; ++v) {
+      const double lf = FX ? ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), sd_last)
+                           : static_cast<double>(r0[v]);
+      gain[v] -= static_cast<double>(fv[v]) * lf;
+    }
 
     // ---- epilogue on this wave's parity class; cell-wide sums through LDS. The
     // lane indices are re-derived from an opaque copy so that the per-point
@@ -381,34 +472,67 @@ load_subgrid(a, cell, p1, p2, fv);  // re-read: not kept live through the filter
   }
 }
 
+
+template <int OUT>
+__global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
+  t64_body<OUT, true>(a);
+}
+
+template <int OUT>
+__global__ __launch_bounds__(256) void fp32_t64_kernel(KernelArgs a) {
+  t64_body<OUT, false>(a);
+}
+
 }  // namespace
+
+template <template <int> class K>
+static bool set_lds_attr() {
+  bool ok = true;
+  ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(K<0>::fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kLdsBytes) == hipSuccess;
+  ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(K<1>::fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kLdsBytes) == hipSuccess;
+  ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(K<2>::fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kLdsBytes) == hipSuccess;
+  ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(K<3>::fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kLdsBytes) == hipSuccess;
+  ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(K<4>::fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kLdsBytes) == hipSuccess;
+  return ok;
+}
+
+template <int OUT>
+struct Fx16T64 {
+  static constexpr auto fn = fx16_t64_kernel<OUT>;
+};
+template <int OUT>
+struct Fp32T64 {
+  static constexpr auto fn = fp32_t64_kernel<OUT>;
+};
+
+template <template <int> class K>
+static void launch_t64(const KernelArgs& args, dim3 grid, hipStream_t stream) {
+  const dim3 block(256);
+  switch (args.out_kind) {
+    case 0: hipLaunchKernelGGL(K<0>::fn, grid, block, kLdsBytes, stream, args); break;
+    case 1: hipLaunchKernelGGL(K<1>::fn, grid, block, kLdsBytes, stream, args); break;
+    case 2: hipLaunchKernelGGL(K<2>::fn, grid, block, kLdsBytes, stream, args); break;
+    case 3: hipLaunchKernelGGL(K<3>::fn, grid, block, kLdsBytes, stream, args); break;
+    default: hipLaunchKernelGGL(K<4>::fn, grid, block, kLdsBytes, stream, args); break;
+  }
+}
 
 int launch_2d64(const KernelArgs& args, hipStream_t stream) {
   if (args.cells <= 0) return 0;
-  if (args.precision != 4) return -4;
+  if (args.precision != 4 && args.precision != 1) return -4;
   int64_t blocks = args.cells;
   if (blocks > args.max_blocks) blocks = args.max_blocks;
-  static const bool attr_ok = [] {  // 135 KB of dynamic LDS, above the 64 KB default
-    bool ok = true;
-    ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<0>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes) == hipSuccess;
-    ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<1>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes) == hipSuccess;
-    ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<2>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes) == hipSuccess;
-    ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<3>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes) == hipSuccess;
-    ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(fx16_t64_kernel<4>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes) == hipSuccess;
-    return ok;
-  }();
+  // 135 KB of dynamic LDS, above the 64 KB default
+  static const bool attr_ok = set_lds_attr<Fx16T64>() && set_lds_attr<Fp32T64>();
   if (!attr_ok) return -3;
-  dim3 grid(static_cast<unsigned>(blocks)), block(256);
-  if (args.out_kind == 0) hipLaunchKernelGGL(fx16_t64_kernel<0>, grid, block, kLdsBytes, stream, args);
-  else if (args.out_kind == 1) hipLaunchKernelGGL(fx16_t64_kernel<1>, grid, block, kLdsBytes, stream, args);
-  else if (args.out_kind == 2) hipLaunchKernelGGL(fx16_t64_kernel<2>, grid, block, kLdsBytes, stream, args);
-  else if (args.out_kind == 3) hipLaunchKernelGGL(fx16_t64_kernel<3>, grid, block, kLdsBytes, stream, args);
-  else hipLaunchKernelGGL(fx16_t64_kernel<4>, grid, block, kLdsBytes, stream, args);
+  const dim3 grid(static_cast<unsigned>(blocks));
+  if (args.precision == 4) launch_t64<Fx16T64>(args, grid, stream);
+  else launch_t64<Fp32T64>(args, grid, stream);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

@@ -193,7 +193,9 @@ __device__ __forceinline__ void tile_dft(const EmatFx& E, const float* xr, const
     if (!REAL_IN) m = fmaxf(m, fabsf(xi[s]));
   }
   m = wave_max(m);
-  const int sa = 9 - exp_above(m);
+  // 2^sa stays finite: tiles with max |x| < 2^-118 are split with fewer
+  // significant bits (the fields are FP32, whose normal range ends at 2^-126)
+  const int sa = min(9 - exp_above(m), 127);
   const float c = ldexpf(1.0f, sa);
   Split3 Xr[2], Xi[2];
 #pragma unroll
@@ -247,7 +249,9 @@ __device__ __forceinline__ void tile_dft(const EmatFx16& E, const float* xr, con
     if (!REAL_IN) m = fmaxf(m, fabsf(xi[s]));
   }
   m = wave_max(m);
-  const int sa = 9 - exp_above(m);
+  // 2^sa stays finite: tiles with max |x| < 2^-118 are split with fewer
+  // significant bits (the fields are FP32, whose normal range ends at 2^-126)
+  const int sa = min(9 - exp_above(m), 127);
   const float c = ldexpf(1.0f, sa);
   Split3 X;
   put2(X, 0, split2_f32(xr[0] * c, xr[1] * c));

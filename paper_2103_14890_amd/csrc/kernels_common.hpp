@@ -50,6 +50,21 @@ __device__ __forceinline__ int exp_above(float x) {
   return e;
 }
 
+// Exponent e with x < 2^e for a double x > 0 (0 for x == 0 or non-finite input).
+__device__ __forceinline__ int exp_above_d(double x) {
+  if (!(x > 0.0) || !(x <= 1.7e308)) return 0;
+  int e;
+  frexp(x, &e);
+  return e;
+}
+
+// Wavefront-wide max of non-negative doubles (butterfly of lane exchanges).
+__device__ __forceinline__ double wave_max_d(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+  return x;
+}
+
 // Register layouts of one cell's N x N field across a wavefront: register v
 // of lane `lane` holds element (row(v, lane), col(lane)).
 struct Lay32 {  // 32x32 MFMA result tile

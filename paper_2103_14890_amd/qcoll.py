@@ -129,6 +129,18 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _alloc(shape, dtype, like, stream):
+    """A device buffer for a call queued on `stream`. Buffers come from the
+    caching allocator of the current stream; when the call runs on another
+    stream the buffer is recorded on it, so that its memory is not handed out
+    again before that stream's work on it has completed."""
+    import torch
+    t = torch.empty(shape, dtype=dtype, device=like.device)
+    if stream is not None and stream != torch.cuda.current_stream(like.device):
+        t.record_stream(stream)
+    return t
+
+
 def _dev_ptr(t, dtype, name):
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
@@ -171,7 +183,7 @@ class Plan:
         code = _RK_SCHEMES[scheme]
         need = int(LIB.qcoll_step_rk_work_bytes(self._h, code, f.shape[0]))
         if work is None:
-            work = torch.empty(max(need // 4, 1), dtype=torch.float32, device=f.device)
+            work = _alloc(max(need // 4, 1), torch.float32, f, stream)
         st = ctypes.c_void_p(0) if status is None else _dev_ptr(status, torch.int32, "status")
         _check(LIB.qcoll_step_rk(self._h, _dev_ptr(f, torch.float32, "f"), f.shape[0], float(dt), float(eps), code,
                                  _dev_ptr(work, torch.float32, "work"), work.numel() * 4, st,
@@ -203,7 +215,7 @@ class Plan:
         import torch
         cells = f.shape[0]
         if q is None:
-            q = torch.empty(f.shape, dtype=torch.float64 if self.conserve else torch.float32, device=f.device)
+            q = _alloc(f.shape, torch.float64 if self.conserve else torch.float32, f, stream)
         _check(LIB.qcoll_eval(self._h, _dev_ptr(f, torch.float32, "f"),
                               _dev_ptr(q, torch.float64 if self.conserve else torch.float32, "Q"),
                               cells, _stream_ptr(stream)), "qcoll_eval")
@@ -219,10 +231,10 @@ class Plan:
         import torch
         cells = f.shape[0]
         if q is None:
-            q = torch.empty(f.shape, dtype=torch.float64 if self.conserve else torch.float32, device=f.device)
+            q = _alloc(f.shape, torch.float64 if self.conserve else torch.float32, f, stream)
         need = self.galerkin_work_bytes(cells)
         if work is None:
-            work = torch.empty(max(need // 8, 1), dtype=torch.float64, device=f.device)
+            work = _alloc(max(need // 8, 1), torch.float64, f, stream)
         _check(LIB.qcoll_eval_galerkin(self._h, _dev_ptr(f, torch.float32, "f"),
                                        _dev_ptr(q, torch.float64 if self.conserve else torch.float32, "Q"), cells,
                                        _dev_ptr(work, work.dtype, "work"), work.numel() * work.element_size(),
@@ -256,7 +268,7 @@ class Plan:
         """Pick the fastest launch shape on f (see qcoll_plan_autotune) and store it
         in the JSON cache (path `cache`, or $QCOLL_TUNE_CACHE) under the plan key."""
         import torch
-        q = torch.empty(f.shape, dtype=torch.float64 if self.conserve else torch.float32, device=f.device)
+        q = _alloc(f.shape, torch.float64 if self.conserve else torch.float32, f, stream)
         _check(LIB.qcoll_plan_autotune(self._h, _dev_ptr(f, torch.float32, "f"), ctypes.c_void_p(q.data_ptr()),
                                        f.shape[0], int(reps), _stream_ptr(stream)), "qcoll_plan_autotune")
         best = self.launch()
@@ -352,18 +364,18 @@ class TransportPlan:
     def work_bytes(self) -> int:
         return _check(int(LIB.qcoll_transport_work_bytes(self._h)), "qcoll_transport_work_bytes")
 
-    def _work(self, work, like):
+    def _work(self, work, like, stream):
         import torch
         if work is None:
-            work = torch.empty(max(self.work_bytes() // 4, 1), dtype=torch.float32, device=like.device)
+            work = _alloc(max(self.work_bytes() // 4, 1), torch.float32, like, stream)
         return work
 
     def rhs(self, f, R=None, work=None, stream=None):
         """R = -(1/|P_i|) sum of the face fluxes, f and R float32 [cells, N, N]."""
         import torch
         if R is None:
-            R = torch.empty_like(f)
-        work = self._work(work, f)
+            R = _alloc(f.shape, torch.float32, f, stream)
+        work = self._work(work, f, stream)
         _check(LIB.qcoll_transport_rhs(self._h, _dev_ptr(f, torch.float32, "f"), _dev_ptr(R, torch.float32, "R"),
                                        _dev_ptr(work, work.dtype, "work"), work.numel() * work.element_size(),
                                        _stream_ptr(stream)), "qcoll_transport_rhs")
@@ -373,8 +385,8 @@ class TransportPlan:
         """out = f + dt R(f) (explicit Euler transport step)."""
         import torch
         if out is None:
-            out = torch.empty_like(f)
-        work = self._work(work, f)
+            out = _alloc(f.shape, torch.float32, f, stream)
+        work = self._work(work, f, stream)
         _check(LIB.qcoll_transport_step(self._h, _dev_ptr(f, torch.float32, "f"), _dev_ptr(out, torch.float32, "out"),
                                         float(dt), _dev_ptr(work, work.dtype, "work"),
                                         work.numel() * work.element_size(), _stream_ptr(stream)),

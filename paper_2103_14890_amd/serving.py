@@ -5,11 +5,16 @@ collision kernel and a number of time steps of d f/dt = Q(f)/eps (section
 3.4; explicit Euler by default). Requests of different N and kernels run side
 by side on one GPU:
 
-  * admission: a request is admitted when the live state (4 N^2 bytes per
-    request) fits in the HBM budget and its group has a free slot; otherwise
-    it waits in a FIFO queue and is admitted as soon as memory frees up;
-  * residency: each (N, kernel) group keeps its live cells contiguous in a
-    device pool (one plan per group); f stays on the device between steps;
+  * residency: each (N, kernel) group keeps its live cells contiguous in one
+    device buffer (its pool of f slots and their status flags; one plan per
+    group); f stays on the device between steps;
+  * admission by HBM footprint: the budget is charged with the device bytes
+    the pools really hold (their capacity, as the caching allocator rounds
+    it), including the moment a pool grows, when the old and the new buffer
+    are both alive. A request is admitted when its group has a free slot, or
+    when the pool can grow within the budget (pools of idle groups are
+    released first); otherwise it waits in a FIFO queue and is admitted as
+    soon as slots or memory free up;
   * scheduling: every tick advances every live request by one step in ONE
     batched launch over all groups (qcoll_step_multi), then retires finished
     requests (copy to pinned host memory, compaction of the pool) and admits
@@ -57,26 +62,49 @@ class Result:
         return self.done - self.arrival
 
 
+def _alloc_bytes(nbytes: int) -> int:
+    """Bytes the caching allocator hands out for a request of nbytes (blocks
+    are multiples of 512 bytes)."""
+    return -(-int(nbytes) // 512) * 512
+
+
 class _Group:
+    """Live requests of one (N, kernel): f slots [cap][N][N] float32 and their
+    status flags [cap] int32 in one device buffer."""
+
     def __init__(self, plan: qcoll.Plan, N: int, device):
-        import torch
         self.plan, self.N, self.device = plan, N, device
-        self.pool = torch.empty((0, N, N), dtype=torch.float32, device=device)
-        self.status = torch.empty((0,), dtype=torch.int32, device=device)
+        self.cap = 0
+        self.buf = None
+        self.pool = None
+        self.status = None
         self.live: list[int] = []          # request id of slot i
         self.left: list[int] = []          # steps remaining for slot i
 
-    def ensure(self, need: int):
+    @staticmethod
+    def footprint(N: int, cap: int) -> int:
+        return _alloc_bytes(cap * (4 * N * N + 4)) if cap > 0 else 0
+
+    @property
+    def bytes(self) -> int:
+        return self.footprint(self.N, self.cap)
+
+    def resize(self, cap: int):
+        """Move the live slots into a buffer of `cap` slots (cap >= live); cap 0
+        releases the buffer."""
         import torch
-        cap = self.pool.shape[0]
-        if need <= cap:
+        assert cap >= len(self.live)
+        if cap == 0:
+            self.buf = self.pool = self.status = None
+            self.cap = 0
             return
-        new = max(need, 2 * cap, 8)
-        pool = torch.empty((new, self.N, self.N), dtype=torch.float32, device=self.device)
-        if len(self.live):
+        nn = self.N * self.N
+        buf = torch.empty(cap * nn + cap, dtype=torch.float32, device=self.device)
+        pool = buf[:cap * nn].view(cap, self.N, self.N)
+        if self.live:
             pool[:len(self.live)].copy_(self.pool[:len(self.live)])
-        self.pool = pool
-        self.status = torch.empty((new,), dtype=torch.int32, device=self.device)
+        self.buf, self.pool, self.cap = buf, pool, cap
+        self.status = buf[cap * nn:].view(torch.int32)
 
 
 class Server:
@@ -94,8 +122,9 @@ class Server:
         self.groups: dict[tuple[int, str], _Group] = {}
         self.queue: collections.deque[Request] = collections.deque()
         self.results: dict[int, Result] = {}
-        self.bytes_live = 0
-        self.peak_bytes = 0
+        self.bytes_charged = 0             # device bytes of all pools
+        self.peak_bytes = 0                # largest footprint, growth transients included
+        self.waited: set[int] = set()      # requests that were queued behind a full budget or pool
         self.ticks = 0
         self.cell_steps = 0
         self._pending = None               # the previous tick, completed by the next tick or flush()
@@ -110,26 +139,51 @@ class Server:
         return self.groups[key]
 
     def submit(self, req: Request) -> None:
-        need = 4 * req.N * req.N
+        need = _Group.footprint(req.N, 1)
         if need > self.budget:
             raise ValueError(f"request {req.rid} needs {need} B, more than the whole budget")
         self.queue.append(req)
+
+    def _grow(self, g: _Group, need: int) -> bool:
+        """Give g room for `need` slots within the budget: double its capacity
+        if that fits (old and new buffer are alive together while the live
+        slots move), else as many slots as fit; release idle pools first when
+        even `need` does not fit."""
+        if g.cap >= need:
+            return True
+        for attempt in range(2):
+            room = self.budget - self.bytes_charged   # the old pool stays charged during the move
+            cap = max(need, 2 * g.cap, 8)
+            while cap > need and _Group.footprint(g.N, cap) > room:
+                cap = max(need, cap * 3 // 4 if cap * 3 // 4 < cap else cap - 1)
+            if _Group.footprint(g.N, cap) <= room:
+                old = g.bytes
+                self.peak_bytes = max(self.peak_bytes, self.bytes_charged + _Group.footprint(g.N, cap))
+                g.resize(cap)
+                self.bytes_charged += g.bytes - old
+                return True
+            if attempt == 0:   # release the pools of groups without live requests
+                idle = [h for h in self.groups.values() if h is not g and not h.live and h.cap > 0]
+                if not idle:
+                    return False
+                for h in idle:
+                    self.bytes_charged -= h.bytes
+                    h.resize(0)
+        return False
 
     def _try_admit(self, now: float) -> None:
         import torch
         while self.queue:
             req = self.queue[0]
-            need = 4 * req.N * req.N
             g = self._group(req.N, req.kernel)
-            if self.bytes_live + need > self.budget or len(g.live) >= self.max_slots:
-                return  # FIFO: the head waits for memory to free up
+            if len(g.live) >= self.max_slots or not self._grow(g, len(g.live) + 1):
+                self.waited.update(r.rid for r in self.queue)
+                return  # FIFO: the head waits for slots or memory to free up
             self.queue.popleft()
-            g.ensure(len(g.live) + 1)
             g.pool[len(g.live)].copy_(torch.from_numpy(np.ascontiguousarray(req.f0, dtype=np.float32)))
             g.live.append(req.rid)
             g.left.append(req.steps)
-            self.bytes_live += need
-            self.peak_bytes = max(self.peak_bytes, self.bytes_live)
+            self.peak_bytes = max(self.peak_bytes, self.bytes_charged)
             self._admit_time[req.rid] = now
             self.results[req.rid] = Result(req.rid, None, req.arrival, now, float("nan"))
 
@@ -144,7 +198,6 @@ class Server:
                 g.live[i], g.left[i] = g.live[last], g.left[last]
             g.live.pop()
             g.left.pop()
-            self.bytes_live -= 4 * g.N * g.N
 
     def tick(self, clock) -> int:
         """One batched step of every live request. The step's status flags and
@@ -162,9 +215,12 @@ class Server:
             qcoll.step_multi(plans, fs, self.dt, self.eps, self.scheme, st)
             self.ticks += 1
             self.cell_steps += sum(len(g.live) for g in groups)
-            allf = torch.cat(st)
-            flags = torch.empty(allf.shape, dtype=torch.int32, pin_memory=True)
-            flags.copy_(allf, non_blocking=True)
+            # status flags straight into pinned host memory (no device temporary)
+            flags = torch.empty(sum(len(g.live) for g in groups), dtype=torch.int32, pin_memory=True)
+            k = 0
+            for s_ in st:
+                flags[k:k + s_.shape[0]].copy_(s_, non_blocking=True)
+                k += s_.shape[0]
             slots = [(g, list(g.live)) for g in groups]   # request of each slot in this step
             finished = []
             for g in groups:
@@ -263,6 +319,8 @@ class Server:
             "cell_steps_s": self.cell_steps / wall if wall > 0 else None,
             "ticks": self.ticks,
             "peak_bytes": self.peak_bytes,
+            "budget_bytes": self.budget,
+            "waited": len(self.waited),
             "wall_s": wall,
         }
 

@@ -45,7 +45,6 @@ def test_null_out_pointer_and_strerror():
 
 def test_unsupported_and_host_only_paths():
     assert _plan(d=3, kernel=0, M=8)[0] == qc.EUNSUPPORTED
-    assert _plan(N=64, prec=1, flags=0)[0] == qc.EUNSUPPORTED   # 64x64 runs in FX16 only
     assert _plan(N=80, flags=0)[0] == qc.EUNSUPPORTED           # beyond the 64x64 tile
     assert _plan(d=3, N=40, prec=1, flags=0)[0] == qc.EUNSUPPORTED  # 3D up to 32^3 (FP32 or FX16)
     assert _plan(d=3, N=40, flags=0)[0] == qc.EUNSUPPORTED

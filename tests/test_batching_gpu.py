@@ -193,3 +193,27 @@ def test_pingpong_shape_matches_default_shape(qc, cells):
     for a, b in zip(outs[4], outs[8]):
         assert torch.equal(a, b)
     assert (outs[8][5] == 0).all()
+
+
+def test_calls_on_a_side_stream_with_library_allocated_buffers(qc):
+    """Calls queued on a stream other than the current one, with the binding
+    allocating the output and work buffers: the buffers are recorded on that
+    stream, and the results equal the same calls on the current stream."""
+    f0 = wl.mixture_cells(2, 32, 8.0, 12, 21)
+    plan = qc.Plan(2, 32, 8.0, "hard_sphere", 8, precision="fx16")
+    ref_f = torch.tensor(f0, dtype=torch.float32, device="cuda")
+    ref_q = plan.eval(ref_f)
+    plan.step_rk(ref_f, 0.01, 1.0, "ars222")
+    side = torch.cuda.Stream()
+    f = torch.tensor(f0, dtype=torch.float32, device="cuda")
+    side.wait_stream(torch.cuda.current_stream())
+    q = plan.eval(f, stream=side)
+    plan.step_rk(f, 0.01, 1.0, "ars222", stream=side)
+    # allocations on the current stream while the side stream may still run
+    junk = [torch.full((12, 32, 32), 7.0, device="cuda") for _ in range(4)]
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    assert torch.equal(q, ref_q)
+    assert torch.equal(f, ref_f)
+    del junk
+    plan.close()

@@ -6,8 +6,8 @@ batched launch of the 3D workload (32^3 and 16^3 cells in one launch).
 Tolerance: the plain-FP32 bound of the 2D tests (relative L2 2e-4 over the
 batch, 1e-3 per cell); the projection leaves mass, momentum and energy at FP64
 rounding (1e-12 relative). The FX16 variant (split-FP16 DFT-GEMMs on 16^3 and
-32^3 tiles; spectrum, work fields and filters still stored in FP32, which sets
-its error floor near 1e-5): 2e-5 over the batch, 1e-4 per cell.
+32^3 tiles; spectrum, work fields and filters still stored in FP32): the
+mixed-operator target 1e-5 over the batch, 1e-4 per cell.
 """
 
 import numpy as np
@@ -21,7 +21,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL, CELL_TOL = 2e-4, 1e-3
-FX_TOL, FX_CELL_TOL = 2e-5, 1e-4
+FX_TOL, FX_CELL_TOL = 1e-5, 1e-4
 
 
 @pytest.fixture(scope="module")
@@ -65,8 +65,8 @@ def test_parity_3d(qc, N, L, M, cells):
     plan.close()
 
 
-@pytest.mark.parametrize("N,M,cells", [(32, 8, 3), (24, 8, 3), (20, 8, 2), (32, 32, 2), (16, 8, 6), (16, 32, 5),
-                                       (12, 8, 5), (8, 8, 7)])
+@pytest.mark.parametrize("N,M,cells", [(32, 8, 8), (24, 8, 8), (20, 8, 8), (32, 32, 8), (16, 8, 8), (16, 32, 8),
+                                       (12, 8, 8), (8, 8, 8)])
 def test_parity_3d_fx16(qc, N, M, cells):
     f = wl.mixture_cells(3, N, 8.0, cells, 40 + N)
     plan = qc.Plan(3, N, 8.0, "hard_sphere", M, precision="fx16")
@@ -78,14 +78,59 @@ def test_parity_3d_fx16(qc, N, M, cells):
     plan.close()
 
 
+def test_parity_3d_fx16_every_even_grid(qc):
+    """Every even grid from 8^3 to 32^3 (M = 8, batches of 8 cells): the batch
+    stays within the mixed-operator target. Single cells near equilibrium,
+    where gain and loss cancel most, carry the FP32 storage floor of this
+    variant's spectrum, filters and work fields: up to about 1e-4 of their own
+    norm."""
+    for N in range(8, 33, 2):
+        f = wl.mixture_cells(3, N, 8.0, 8, 40 + N)
+        plan = qc.Plan(3, N, 8.0, "hard_sphere", 8, precision="fx16")
+        q = _eval(plan, f)
+        ref = _ref(f, N, 8.0, 8)
+        err, cerr = _rel(q, ref), _cell_rel(q, ref)
+        print(f"3D FX16 N={N}: rel L2 {err:.3e}, worst cell {cerr:.3e}")
+        assert err < FX_TOL and cerr < 2 * FX_CELL_TOL, N
+        plan.close()
+
+
+@pytest.mark.parametrize("N", [16, 32])
+@pytest.mark.parametrize("e2", [-120, -100, 90])
+def test_fx16_3d_extreme_magnitudes(qc, N, e2):
+    """Small (max |f| ~ 2^-101, ~2^-121) and large (~2^89) cells on the 3D FX16
+    path: the tile scales stay finite at every magnitude, and Q keeps the
+    accuracy it has at unit scale while the FP32 spectra and work fields stay in
+    the FP32 normal range (at 2^-121 their tails are subnormal: finite results,
+    fewer digits)."""
+    f1 = wl.mixture_cells(3, N, 8.0, 8, 78).astype(np.float32)
+    s = sp.Setup(d=3, N=N, L=8.0, kernel="hard_sphere", M=8)
+    bank = sp.filter_bank(s)
+    plan = qc.Plan(3, N, 8.0, "hard_sphere", 8, precision="fx16", conserve=True)
+    errs = []
+    for f in (f1, (f1 * np.float32(2.0 ** e2)).astype(np.float32)):
+        q = plan.eval(torch.tensor(f, device="cuda"))
+        torch.cuda.synchronize()
+        qn = q.cpu().numpy()
+        assert np.isfinite(qn).all()
+        errs.append(_rel(qn, sp.project_conservative(sp.q_fast(f.astype(np.float64), s, bank), 3, 8.0)))
+    print(f"3D FX16 N={N} scale 2^{e2}: rel L2 {errs[1]:.3e} (unit scale {errs[0]:.3e})")
+    assert errs[0] < FX_TOL
+    if e2 > -110:
+        assert errs[1] < FX_TOL and errs[1] < 1.5 * errs[0] + 1e-7
+    else:
+        assert errs[1] < 1e-3
+    plan.close()
+
+
 def test_fx16_and_fp32_slots_in_one_call(qc):
     """FX16 plans of 32^3, 24^3 and 16^3 and an FP32 16^3 plan in one batched
     call equal their single-plan calls bitwise (eval with the projection, the
     IMEX step); FX16 plans of different grids in one launch use their own DFT
     tables."""
-    fa = wl.mixture_cells(3, 32, 8.0, 3, 81)
-    fc = wl.mixture_cells(3, 24, 8.0, 4, 82)
-    fd = wl.mixture_cells(3, 16, 8.0, 6, 84)
+    fa = wl.mixture_cells(3, 32, 8.0, 8, 81)
+    fc = wl.mixture_cells(3, 24, 8.0, 8, 82)
+    fd = wl.mixture_cells(3, 16, 8.0, 8, 84)
     fb = wl.mixture_cells(3, 16, 8.0, 5, 83)
     pa = qc.Plan(3, 32, 8.0, "hard_sphere", 8, precision="fx16", conserve=True)
     pc = qc.Plan(3, 24, 8.0, "hard_sphere", 8, precision="fx16", conserve=True)
@@ -199,21 +244,25 @@ def test_two_resolutions_one_launch(qc):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fx16"])
-def test_3d_workload_sampled_cells(qc, precision):
-    """The 32^3 half of the 3D workload at 1024 cells in the launch shape of the
-    benchmark; 3 sampled cells against the oracle, and the projection's moments
-    on all cells."""
-    f = wl.config_inputs("hs3d_32", cells=1024)
-    plan = qc.Plan(3, 32, 8.0, "hard_sphere", 32, precision=precision, conserve=True)
+@pytest.mark.parametrize("name,N", [("hs3d_32", 32), ("hs3d_16", 16)])
+def test_3d_workload_sampled_cells(qc, precision, name, N):
+    """Each resolution of the 3D workload at 1024 cells in the launch shape of
+    the benchmark: 32 cells spread over the batch against the oracle (batch
+    and per-cell bounds), and the projection's moments on all cells."""
+    f = wl.config_inputs(name, cells=1024)
+    plan = qc.Plan(3, N, 8.0, "hard_sphere", 32, precision=precision, conserve=True)
     ft = torch.tensor(f, dtype=torch.float32, device="cuda")
     q = plan.eval(ft)
     torch.cuda.synchronize()
-    idx = np.array([0, 511, 1023])
+    idx = np.linspace(0, 1023, 32).astype(int)
     got = q[idx].cpu().numpy()
-    ref = sp.project_conservative(_ref(f[idx], 32, 8.0, 32), 3, 8.0)
-    err = _rel(got, ref)
-    print(f"hs3d_32 1024 cells ({precision}): sampled rel L2 {err:.3e}")
-    assert err < (FX_TOL if precision == "fx16" else TOL)
+    ref = sp.project_conservative(_ref(f[idx], N, 8.0, 32), 3, 8.0)
+    err, cerr = _rel(got, ref), _cell_rel(got, ref)
+    print(f"{name} 1024 cells ({precision}): 32 sampled cells rel L2 {err:.3e}, worst cell {cerr:.3e}")
+    if precision == "fx16":
+        assert err < FX_TOL and cerr < FX_CELL_TOL
+    else:
+        assert err < TOL and cerr < CELL_TOL
     qa = q.cpu().numpy()
     mass = np.abs(qa.sum(axis=(1, 2, 3))) / np.abs(qa).sum(axis=(1, 2, 3))
     assert mass.max() <= 1e-12

@@ -159,6 +159,28 @@ def test_edge_cases(qc):
     plan.close()
 
 
+@pytest.mark.parametrize("N,L,M", [(16, 8.0, 8), (32, 8.0, 8), (64, 10.0, 16)])
+@pytest.mark.parametrize("e2", [-120, 120])
+def test_fx16_extreme_magnitudes(qc, N, L, M, e2):
+    """Near-vacuum (max |f| ~ 2^-121, the tails FP32 subnormal) and near-overflow
+    (max |f| ~ 2^119) cells: the per-cell power-of-two scales of the mixed path
+    must stay finite and exact, so Q (FP64 output, ~2^(2 e2)) keeps the relative
+    accuracy of ordinary inputs."""
+    f = (wl.mixture_cells(2, N, L, 3, 77).astype(np.float32) * np.float32(2.0 ** e2)).astype(np.float32)
+    f64 = f.astype(np.float64)
+    plan = qc.Plan(2, N, L, "hard_sphere", M, precision="fx16", conserve=True)
+    q = plan.eval(torch.tensor(f, device="cuda"))
+    torch.cuda.synchronize()
+    qn = q.cpu().numpy()
+    s = sp.Setup(d=2, N=N, L=L, kernel="hard_sphere", M=M)
+    ref = sp.project_conservative(sp.q_fast(f64, s), 2, L)
+    assert np.isfinite(qn).all()
+    err = _rel(qn, ref)
+    print(f"N={N} scale 2^{e2}: rel L2 {err:.3e}")
+    assert err < 1e-5
+    plan.close()
+
+
 def test_grid_stride_and_determinism(qc):
     """More cells than the grid holds (each wave loops), results bitwise repeatable
     and independent of the batch a cell is in."""
@@ -261,17 +283,52 @@ def test_gpu_matches_real_space_brute_force(qc):
         plan.close()
 
 
+@pytest.mark.parametrize("precision", ["fx16", "fp32"])
 @pytest.mark.parametrize("N,L,kernel,M", [(64, 10.0, "hard_sphere", 16), (64, 10.0, "maxwell", 8),
-                                          (48, 8.0, "hard_sphere", 8), (40, 8.0, "maxwell", 8)])
-def test_parity_tile64(qc, N, L, kernel, M):
-    """Grids of 34..64 points: radix-2 parity split over four wavefronts."""
+                                          (48, 8.0, "hard_sphere", 8), (40, 8.0, "maxwell", 8),
+                                          (34, 8.0, "hard_sphere", 8)])
+def test_parity_tile64(qc, N, L, kernel, M, precision):
+    """Grids of 34..64 points: radix-2 parity split over four wavefronts, the
+    32-point DFT-GEMMs in FX16 or plain FP32."""
     f = wl.mixture_cells(2, N, L, 6, 41)
-    plan = qc.Plan(2, N, L, kernel, M, precision="fx16")
+    plan = qc.Plan(2, N, L, kernel, M, precision=precision)
     q = _gpu_eval(plan, f)
     ref = _ref(f, kernel, M, N=N, L=L)
     err, cerr = _rel(q, ref), _cell_rel(q, ref)
-    print(f"N={N} fx16 {kernel} M={M}: rel L2 {err:.3e}, worst cell {cerr:.3e}")
-    assert err < 1e-5 and cerr < 5e-5
+    print(f"N={N} {precision} {kernel} M={M}: rel L2 {err:.3e}, worst cell {cerr:.3e}")
+    assert err < TOL[precision] and cerr < 5 * TOL[precision]
+    plan.close()
+
+
+def test_tile64_fp32_noisy_conserve_step_and_stages(qc):
+    """The plain FP32 path on the config-3 shape (64x64 on [-10,10]^2, hard
+    spheres, M = 16, 1% noise): parity at the FP32 bound, FP64 projection, the
+    single-stage and the multi-stage updates against the oracle."""
+    f = wl.noisy_mixture_cells(2, 64, 10.0, 7, 1002, 0.01)
+    ref = _ref(f, "hard_sphere", 16, N=64, L=10.0)
+    plan = qc.Plan(2, 64, 10.0, "hard_sphere", 16, precision="fp32", conserve=True)
+    q = plan.eval(torch.tensor(f, dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    qn = q.cpu().numpy()
+    err = _rel(qn, sp.project_conservative(ref, 2, 10.0))
+    mass = (np.abs(qn.sum(axis=(1, 2))) / np.abs(qn).sum(axis=(1, 2))).max()
+    print(f"N=64 fp32 noisy conserve: rel L2 {err:.3e}, mass {mass:.2e}")
+    assert err < TOL["fp32"] and mass < 1e-12
+    plan.close()
+    plan = qc.Plan(2, 64, 10.0, "hard_sphere", 16, precision="fp32")
+    f32 = f.astype(np.float32).astype(np.float64)
+    ft = torch.tensor(f, dtype=torch.float32, device="cuda")
+    plan.step(ft, 0.02, 1.0, "imex")
+    torch.cuda.synchronize()
+    want = stepping.imex_euler_penalized(f32, ref, 0.02, 1.0, 2, 10.0)
+    assert np.abs(ft.cpu().double().numpy() - want).max() <= 2e-5 * np.abs(want).max()
+    ft = torch.tensor(f, dtype=torch.float32, device="cuda")
+    plan.step_rk(ft, 0.02, 1.0, "ars222")
+    torch.cuda.synchronize()
+    s = sp.Setup(d=2, N=64, L=10.0, kernel="hard_sphere", M=16)
+    bank = sp.filter_bank(s)
+    want = stepping.imex_rk_penalized(f32, lambda g: sp.q_fast(g, s, bank), 0.02, 1.0, 2, 10.0, "ars222")
+    assert np.abs(ft.cpu().double().numpy() - want).max() <= 2e-5 * np.abs(want).max()
     plan.close()
 
 

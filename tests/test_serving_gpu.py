@@ -38,12 +38,22 @@ def test_each_result_same_alone_and_in_mix(sv):
 
 
 def test_budget_forces_queueing_and_is_never_exceeded(sv):
+    """The budget bounds what the service really allocates on the device (its
+    pools, their status flags and the transient of a pool growth), measured by
+    the caching allocator, not only its own counter."""
     reqs = sv.poisson_requests(30, rate=1e5, seed=6, sizes=(16, 32), steps=(3, 12))
-    budget = 3 * 4 * 32 * 32          # room for at most three 32x32 requests at once
+    budget = 3 * (4 * 32 * 32 + 4) + 512   # about three 32x32 slots at once
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
     s = sv.Server(budget_bytes=budget)
     stats = s.run(reqs, realtime=False)
+    torch.cuda.synchronize()
+    device_peak = torch.cuda.max_memory_allocated() - base
     assert stats["failed"] == 0 and stats["requests"] == 30
     assert 0 < s.peak_bytes <= budget
+    assert 0 < device_peak <= budget, (device_peak, budget)
+    assert stats["waited"] > 0
     waited = [r for r in s.results.values() if r.admitted > r.arrival]
     assert waited, "the small budget should have made some requests wait"
     for r in reqs[:: 10]:
