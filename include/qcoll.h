@@ -70,7 +70,8 @@ enum {
   QCOLL_EINVAL = -1,      /* bad argument (dimension, N, M, L, pointer, count) */
   QCOLL_ENOMEM = -2,      /* host or device allocation failed                  */
   QCOLL_EDEVICE = -3,     /* HIP runtime error or no device                    */
-  QCOLL_EUNSUPPORTED = -4 /* valid but not implemented (size, kernel, mode)    */
+  QCOLL_EUNSUPPORTED = -4, /* valid but not implemented (size, kernel, mode)    */
+  QCOLL_ETOOLARGE = -5     /* larger than the fixed scratch of qcoll_step_rk_noalloc */
 };
 
 /* Plan flags. */
@@ -182,6 +183,23 @@ int qcoll_eval_galerkin(qcoll_plan_t plan, const float* f, void* Q, int64_t cell
 int64_t qcoll_step_rk_work_bytes(qcoll_plan_t plan, int scheme, int64_t cells);
 int qcoll_step_rk(qcoll_plan_t plan, float* f, int64_t cells, double dt, double eps, int scheme, float* work,
                   int64_t work_bytes, int32_t* status, hipStream_t stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * step as qcoll_step_rk, with the work buffer taken from a fixed array of
+ * QCOLL_NOALLOC_SCRATCH_BYTES in the library's device memory (one per GPU, held
+ * from the first call on that GPU until the process ends). The call allocates
+ * nothing. Problems whose qcoll_step_rk_work_bytes() exceed the array return
+ * QCOLL_ETOOLARGE before any device work (e.g. at most 2340 cells of 32^2 for
+ * QCOLL_IMEX_BPR343, 5461 for QCOLL_IMEX_ARS222). Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (several streams, several
+ * host threads) race and must be ordered by the caller. The array needs no
+ * clearing (each stage slot is written before it is read). Other arguments,
+ * errors and results as for qcoll_step_rk, whose results it reproduces
+ * bitwise. */
+#define QCOLL_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int qcoll_step_rk_noalloc(qcoll_plan_t plan, float* f, int64_t cells, double dt, double eps, int scheme,
+                          int32_t* status, hipStream_t stream);
 
 /* Batched launches (cell-locality of section 3.3: cells of different velocity
  * grids and kernels share one launch). Slot i uses plans[i] with f[i], Q[i]

@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "libqcoll.so")
 
 HOST_SOURCES = ["plan.cpp", "api.cpp", "transport.cpp"]
 DEVICE_SOURCES = ["kernels_2d.hip", "kernels_2d16.hip", "kernels_2d64.hip", "kernels_multi.hip", "kernels_3d.hip",
-                  "kernels_galerkin.hip", "kernels_transport.hip", "kernels_classical.hip"]
+                  "kernels_galerkin.hip", "kernels_transport.hip", "kernels_classical.hip", "noalloc.hip"]
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}", "-I/opt/rocm/include", "-D__HIP_PLATFORM_AMD__"]

@@ -570,6 +570,12 @@ bool device_supported(const qcoll::HostPlan& hp, int precision) {
 
 }  // namespace
 
+namespace qcoll {
+// Device of a device plan, -1 for a host-only plan (used by the no-allocation
+// entry point, which looks up its fixed scratch on that device).
+int plan_device(const qcoll_plan_s* p) { return p && p->on_device ? p->device : -1; }
+}  // namespace qcoll
+
 extern "C" {
 
 static int plan_create(qcoll_plan_t* out, int d, int n_per_dim, double L, int kernel, double gamma, double b,
@@ -1185,6 +1191,7 @@ const char* qcoll_strerror(int code) {
     case QCOLL_ENOMEM: return "out of memory";
     case QCOLL_EDEVICE: return "HIP device error";
     case QCOLL_EUNSUPPORTED: return "unsupported configuration";
+    case QCOLL_ETOOLARGE: return "work larger than the fixed scratch of the no-allocation entry point";
     default: return "unknown error";
   }
 }

@@ -20,7 +20,8 @@ MAXWELL, HARD_SPHERE, VHS = 0, 1, 2
 FP32, MIX_FX16 = 1, 4
 EXPLICIT_EULER, IMEX_EULER_PENALIZED, IMEX_ARS222, IMEX_BPR343 = 0, 1, 2, 3
 CONSERVE, R_LITERAL, GALERKIN, CLASSICAL, SEPARABLE_MODES, HOST_ONLY = 0x1, 0x2, 0x4, 0x8, 0x10, 0x100
-OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ETOOLARGE = 0, -1, -2, -3, -4, -5
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _KERNELS = {"maxwell": MAXWELL, "hard_sphere": HARD_SPHERE, "vhs": VHS}
 _PRECISIONS = {"fp32": FP32, "fx16": MIX_FX16}
@@ -61,6 +62,8 @@ def _load() -> ctypes.CDLL:
     lib.qcoll_step_rk_work_bytes.restype = i64
     lib.qcoll_step_rk.argtypes = [vp, vp, i64, dbl, dbl, c_int, vp, i64, vp, vp]
     lib.qcoll_step_rk.restype = c_int
+    lib.qcoll_step_rk_noalloc.argtypes = [vp, vp, i64, dbl, dbl, c_int, vp, vp]
+    lib.qcoll_step_rk_noalloc.restype = c_int
     lib.qcoll_galerkin_work_bytes.argtypes = [vp, i64]
     lib.qcoll_galerkin_work_bytes.restype = i64
     lib.qcoll_eval_galerkin.argtypes = [vp, vp, vp, i64, vp, i64, vp]
@@ -188,6 +191,16 @@ class Plan:
         _check(LIB.qcoll_step_rk(self._h, _dev_ptr(f, torch.float32, "f"), f.shape[0], float(dt), float(eps), code,
                                  _dev_ptr(work, torch.float32, "work"), work.numel() * 4, st,
                                  _stream_ptr(stream)), "qcoll_step_rk")
+        return f
+
+    def step_rk_noalloc(self, f, dt: float, eps: float = 1.0, scheme: str = "ars222", status=None, stream=None):
+        """qcoll_step_rk_noalloc: the same step with the library's fixed device
+        scratch as the work buffer (nothing allocated)."""
+        import torch
+        st = ctypes.c_void_p(0) if status is None else _dev_ptr(status, torch.int32, "status")
+        _check(LIB.qcoll_step_rk_noalloc(self._h, _dev_ptr(f, torch.float32, "f"), f.shape[0], float(dt),
+                                         float(eps), _RK_SCHEMES[scheme], st, _stream_ptr(stream)),
+               "qcoll_step_rk_noalloc")
         return f
 
     @property
