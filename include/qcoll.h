@@ -230,8 +230,23 @@ int qcoll_step_multi(const qcoll_plan_t* plans, int nplans, float* const* f, con
 int qcoll_plan_set_launch(qcoll_plan_t plan, int waves_per_block, int64_t max_blocks);
 int qcoll_plan_get_launch(qcoll_plan_t plan, int* waves_per_block, int64_t* max_blocks);
 
+/* Tile family of a 2D plan: 2D plans with N <= 16 run on the 16x16 MFMA tile
+ * kernels (v_mfma_f32_16x16x32_f16 / 16x16x4f32) by default and also hold the
+ * tables of the 32x32 tile kernels (v_mfma_f32_32x32x16_f16 / 32x32x2f32, the
+ * grid zero-padded), so either can run them (same Q_h up to rounding; the
+ * parity bounds of the plan's precision hold for both). set_tile selects 16
+ * or 32 for such plans and returns QCOLL_EINVAL for any other value (other
+ * plans have one tile family: 32 for 18..32 points, 64 for 34..64); get_tile
+ * reports the selected tile and the alternate one (0: none). Selecting a
+ * family whose kernels lack the launch shape 8 resets that shape to 4. */
+int qcoll_plan_set_tile(qcoll_plan_t plan, int tile);
+int qcoll_plan_get_tile(qcoll_plan_t plan, int* tile, int* alternate);
+
 /* Autotuner: times every launch shape on the caller's f (device, cells cells)
- * with HIP events, `reps` launches each, and keeps the fastest in the plan.
+ * with HIP events, `reps` launches each, and keeps the fastest in the plan:
+ * tile family (see qcoll_plan_set_tile) x cells per workgroup (1, 2, 4, and 8
+ * where the ping-pong variant exists) x grid cap. 2D fast plans only (3D,
+ * Galerkin and classical plans have one launch shape: QCOLL_EUNSUPPORTED).
  * Synchronises the stream; Q (device, as for qcoll_eval) is overwritten. */
 int qcoll_plan_autotune(qcoll_plan_t plan, const float* f, void* Q, int64_t cells, int reps, hipStream_t stream);
 

@@ -7,6 +7,7 @@
 #include <mutex>
 #include <new>
 #include <thread>
+#include <utility>
 #include <vector>
 
 #include "classical_args.hpp"
@@ -43,6 +44,15 @@ struct qcoll_plan_s {
   int64_t scratch_stride = 0;
   int64_t scratch_blocks = 0;
   int tile = 32;
+  // 2D plans with N <= 16 also hold the tables of the 32x32 tile kernels (zero
+  // padded), so that the autotuner can choose the tile family: alt_* is the set
+  // of the tile that is not selected, swapped with the fields above by set_tile.
+  int alt_tile = 0;
+  void* alt_econst = nullptr;
+  double* alt_filt = nullptr;
+  int* alt_filt_exp = nullptr;
+  float* alt_filt32 = nullptr;
+  float* alt_loss32 = nullptr;
   int64_t device_bytes = 0;
   int64_t max_blocks = 0;    // grid cap of single-plan launches
   int waves_per_block = 4;   // cells per workgroup
@@ -74,6 +84,16 @@ int upload(const std::vector<T>& host, T** dev, int64_t& bytes) {
 }
 
 void free_device(qcoll_plan_s* p) {
+  hipFree(p->alt_econst);
+  hipFree(p->alt_filt);
+  hipFree(p->alt_filt_exp);
+  hipFree(p->alt_filt32);
+  hipFree(p->alt_loss32);
+  p->alt_econst = nullptr;
+  p->alt_filt = nullptr;
+  p->alt_filt_exp = nullptr;
+  p->alt_filt32 = p->alt_loss32 = nullptr;
+  p->alt_tile = 0;
   hipFree(p->econst);
   hipFree(p->filt);
   hipFree(p->filt_exp);
@@ -286,6 +306,16 @@ int build_device_2d16(qcoll_plan_s* p) {
     if ((rc = upload(lt, &p->loss32, p->device_bytes))) return rc;
   }
   return QCOLL_OK;
+}
+
+// Exchange the selected tile's tables with the alternate set (2D, N <= 16).
+void swap_tile_tables(qcoll_plan_s* p) {
+  std::swap(p->tile, p->alt_tile);
+  std::swap(p->econst, p->alt_econst);
+  std::swap(p->filt, p->alt_filt);
+  std::swap(p->filt_exp, p->alt_filt_exp);
+  std::swap(p->filt32, p->alt_filt32);
+  std::swap(p->loss32, p->alt_loss32);
 }
 
 int launch(const qcoll::KernelArgs& a, hipStream_t stream) {
@@ -659,6 +689,12 @@ static int plan_create(qcoll_plan_t* out, int d, int n_per_dim, double L, int ke
       rc = build_device_3d(p);
     } else {
       rc = p->tile == 64 ? build_device_2d64(p) : (p->tile == 32 ? build_device_2d32(p) : build_device_2d16(p));
+      if (!rc && p->tile == 16) {   // the 32x32 tile family as the alternate set
+        swap_tile_tables(p);
+        p->tile = 32;
+        rc = build_device_2d32(p);
+        swap_tile_tables(p);
+      }
     }
     if (!rc && p->galerkin) {
       std::vector<double> gi, gr;
@@ -1094,48 +1130,82 @@ int qcoll_plan_get_launch(qcoll_plan_t p, int* waves_per_block, int64_t* max_blo
   return QCOLL_OK;
 }
 
-// Time every launch shape (cells per workgroup x grid cap) on the caller's
-// data with HIP events and keep the fastest in the plan. Synchronises the
-// stream. Q receives the result of the last timed launch.
+int qcoll_plan_set_tile(qcoll_plan_t p, int tile) {
+  if (!p) return QCOLL_EINVAL;
+  if (tile == p->tile) return QCOLL_OK;
+  if (!p->on_device || tile != p->alt_tile || p->alt_tile == 0) return QCOLL_EINVAL;
+  swap_tile_tables(p);
+  if (p->waves_per_block == 8 && !pingpong_ok(p)) p->waves_per_block = 4;
+  return QCOLL_OK;
+}
+
+int qcoll_plan_get_tile(qcoll_plan_t p, int* tile, int* alternate) {
+  if (!p) return QCOLL_EINVAL;
+  if (tile) *tile = p->tile;
+  if (alternate) *alternate = p->alt_tile;
+  return QCOLL_OK;
+}
+
+// Time every launch shape on the caller's data with HIP events and keep the
+// fastest in the plan: tile family (2D plans with N <= 16: 16x16 or zero-padded
+// 32x32 MFMA tiles) x cells per workgroup (1, 2, 4; 8 = the ping-pong variant
+// of the FX16 32x32 kernel) x grid cap (1, 2, 8 workgroups per CU, or one per
+// cell group). Synchronises the stream. Q receives the result of the last
+// timed launch.
 int qcoll_plan_autotune(qcoll_plan_t p, const float* f, void* Q, int64_t cells, int reps, hipStream_t stream) {
   if (!p || !f || !Q || cells < 1 || reps < 1) return QCOLL_EINVAL;
   if (!p->on_device || p->hp.d == 3 || p->galerkin || p->classical) return QCOLL_EUNSUPPORTED;  // one fixed launch shape
   hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return QCOLL_EDEVICE;
+  if (hipEventCreate(&e0) != hipSuccess) return QCOLL_EDEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return QCOLL_EDEVICE;
+  }
+  const int tiles[2] = {p->tile, p->alt_tile};
   const int wpbs[4] = {1, 2, 4, 8};
   const int64_t caps[4] = {1, 2, 8, 1 << 30};  // multiples of the CU count; last = one wave per cell
   float best = 1e30f;
-  int best_w = p->waves_per_block;
+  int best_t = p->tile, best_w = p->waves_per_block;
   int64_t best_b = p->max_blocks;
   int rc = QCOLL_OK;
-  for (int w : wpbs)
-    for (int64_t c : caps) {
+  for (int ti = 0; ti < 2 && rc == QCOLL_OK; ++ti) {
+    if (tiles[ti] == 0) continue;
+    if (p->tile != tiles[ti]) swap_tile_tables(p);
+    for (int w : wpbs) {
       if (w == 8 && !pingpong_ok(p)) continue;
-      qcoll::KernelArgs a = make_args(p);
-      a.f = f;
-      a.q = Q;
-      a.cells = cells;
-      a.out_kind = (p->flags & QCOLL_CONSERVE) ? 1 : 0;
-      a.waves_per_block = w;
-      a.max_blocks = c >= (1 << 30) ? (int64_t{1} << 40) : c * p->cus * (w >= 4 ? 1 : 4 / w);
-      if (launch(a, stream)) { rc = QCOLL_EDEVICE; break; }  // warm-up
-      hipEventRecord(e0, stream);
-      for (int r = 0; r < reps; ++r) launch(a, stream);
-      hipEventRecord(e1, stream);
-      if (hipEventSynchronize(e1) != hipSuccess) { rc = QCOLL_EDEVICE; break; }
-      float ms = 0.0f;
-      hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best) {
-        best = ms;
-        best_w = w;
-        best_b = a.max_blocks;
+      for (int64_t c : caps) {
+        qcoll::KernelArgs a = make_args(p);
+        a.f = f;
+        a.q = Q;
+        a.cells = cells;
+        a.out_kind = (p->flags & QCOLL_CONSERVE) ? 1 : 0;
+        a.waves_per_block = w;
+        a.max_blocks = c >= (1 << 30) ? (int64_t{1} << 40) : c * p->cus * (w >= 4 ? 1 : 4 / w);
+        if (launch(a, stream)) { rc = QCOLL_EDEVICE; break; }  // warm-up
+        hipEventRecord(e0, stream);
+        for (int r = 0; r < reps; ++r) launch(a, stream);
+        hipEventRecord(e1, stream);
+        if (hipEventSynchronize(e1) != hipSuccess) { rc = QCOLL_EDEVICE; break; }
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+          best = ms;
+          best_t = p->tile;
+          best_w = w;
+          best_b = a.max_blocks;
+        }
       }
+      if (rc != QCOLL_OK) break;
     }
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  if (p->tile != best_t) swap_tile_tables(p);
   if (rc == QCOLL_OK) {
     p->waves_per_block = best_w;
     p->max_blocks = best_b;
+  } else if (p->waves_per_block == 8 && !pingpong_ok(p)) {
+    p->waves_per_block = 4;
   }
   return rc;
 }

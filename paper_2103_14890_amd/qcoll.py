@@ -15,6 +15,8 @@ import re
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libqcoll.so")
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "qcoll.h")
+# launch shapes chosen by the autotuner on the batch workloads (see tune.py)
+DEFAULT_TUNING = os.path.join(_PKG, "tuning_gfx950.json")
 
 MAXWELL, HARD_SPHERE, VHS = 0, 1, 2
 FP32, MIX_FX16 = 1, 4
@@ -83,6 +85,10 @@ def _load() -> ctypes.CDLL:
     lib.qcoll_plan_set_launch.restype = c_int
     lib.qcoll_plan_get_launch.argtypes = [vp, ctypes.POINTER(c_int), ctypes.POINTER(i64)]
     lib.qcoll_plan_get_launch.restype = c_int
+    lib.qcoll_plan_set_tile.argtypes = [vp, c_int]
+    lib.qcoll_plan_set_tile.restype = c_int
+    lib.qcoll_plan_get_tile.argtypes = [vp, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
+    lib.qcoll_plan_get_tile.restype = c_int
     lib.qcoll_plan_autotune.argtypes = [vp, vp, vp, i64, c_int, vp]
     lib.qcoll_plan_autotune.restype = c_int
     lib.qcoll_plan_destroy.argtypes = [vp]
@@ -277,19 +283,38 @@ class Plan:
     def set_launch(self, waves_per_block: int, max_blocks: int) -> None:
         _check(LIB.qcoll_plan_set_launch(self._h, int(waves_per_block), int(max_blocks)), "qcoll_plan_set_launch")
 
-    def autotune(self, f, reps: int = 3, cache: str | None = None, stream=None) -> tuple[int, int]:
+    def tile(self) -> tuple[int, int]:
+        """(selected tile family, alternate one or 0)."""
+        t, a = ctypes.c_int(), ctypes.c_int()
+        _check(LIB.qcoll_plan_get_tile(self._h, ctypes.byref(t), ctypes.byref(a)), "qcoll_plan_get_tile")
+        return t.value, a.value
+
+    def set_tile(self, tile: int) -> None:
+        _check(LIB.qcoll_plan_set_tile(self._h, int(tile)), "qcoll_plan_set_tile")
+
+    def shape(self) -> dict:
+        """The launch shape the autotuner chooses among."""
+        w, b = self.launch()
+        return {"tile": self.tile()[0], "waves_per_block": w, "max_blocks": b}
+
+    def apply_shape(self, shape: dict) -> None:
+        if "tile" in shape:
+            self.set_tile(shape["tile"])
+        self.set_launch(shape["waves_per_block"], shape["max_blocks"])
+
+    def autotune(self, f, reps: int = 3, cache: str | None = None, stream=None) -> dict:
         """Pick the fastest launch shape on f (see qcoll_plan_autotune) and store it
         in the JSON cache (path `cache`, or $QCOLL_TUNE_CACHE) under the plan key."""
         import torch
         q = _alloc(f.shape, torch.float64 if self.conserve else torch.float32, f, stream)
         _check(LIB.qcoll_plan_autotune(self._h, _dev_ptr(f, torch.float32, "f"), ctypes.c_void_p(q.data_ptr()),
                                        f.shape[0], int(reps), _stream_ptr(stream)), "qcoll_plan_autotune")
-        best = self.launch()
+        best = self.shape()
         path = cache or os.environ.get("QCOLL_TUNE_CACHE")
         if path:
             import json
             data = json.load(open(path)) if os.path.exists(path) else {}
-            data[self.key] = {"waves_per_block": best[0], "max_blocks": best[1]}
+            data[self.key] = best
             tmp = path + ".tmp"
             with open(tmp, "w") as fh:
                 json.dump(data, fh, indent=1, sort_keys=True)
@@ -297,15 +322,16 @@ class Plan:
         return best
 
     def load_tuning(self, cache: str | None = None) -> bool:
-        """Apply a cached launch shape for this plan's key, if any."""
+        """Apply a cached launch shape for this plan's key, if any (cache path,
+        else $QCOLL_TUNE_CACHE, else the shapes shipped with the package)."""
         import json
-        path = cache or os.environ.get("QCOLL_TUNE_CACHE")
+        path = cache or os.environ.get("QCOLL_TUNE_CACHE") or DEFAULT_TUNING
         if not path or not os.path.exists(path):
             return False
         ent = json.load(open(path)).get(self.key)
         if not ent:
             return False
-        self.set_launch(ent["waves_per_block"], ent["max_blocks"])
+        self.apply_shape(ent)
         return True
 
     def close(self):

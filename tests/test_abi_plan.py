@@ -117,6 +117,10 @@ def test_multi_and_tuning_argument_checks():
     assert qc.LIB.qcoll_plan_set_launch(p._h, 2, 0) == qc.EINVAL
     p.set_launch(2, 512)
     assert p.launch() == (2, 512)
+    # a host-only plan has no alternate tile tables to select
+    assert qc.LIB.qcoll_plan_set_tile(p._h, 16) == qc.EINVAL
+    assert qc.LIB.qcoll_plan_set_tile(None, 16) == qc.EINVAL
+    assert p.tile()[1] == 0
     assert qc.LIB.qcoll_plan_autotune(p._h, None, None, 4, 1, None) == qc.EINVAL
     p.close()
 

@@ -130,18 +130,61 @@ def test_autotune_keeps_results_and_caches(qc, tmp_path):
     f = torch.tensor(wl.mixture_cells(2, 32, 8.0, 1024, 9), dtype=torch.float32, device="cuda")
     before = plan.eval(f)
     cache = str(tmp_path / "tune.json")
-    w, b = plan.autotune(f, reps=2, cache=cache)
-    assert w in (1, 2, 4, 8) and b >= 1
+    best = plan.autotune(f, reps=2, cache=cache)
+    assert best["tile"] == 32 and best["waves_per_block"] in (1, 2, 4, 8) and best["max_blocks"] >= 1
     after = plan.eval(f)
     torch.cuda.synchronize()
     assert torch.equal(before, after)
     data = json.load(open(cache))
-    assert data[plan.key] == {"waves_per_block": w, "max_blocks": b}
+    assert data[plan.key] == best
     other = qc.Plan(2, 32, 8.0, "hard_sphere", 8, precision="fx16")
-    assert other.load_tuning(cache) and other.launch() == (w, b)
+    assert other.load_tuning(cache) and other.shape() == best
     for ws in (1, 2, 4, 8):
         other.set_launch(ws, 64)
         assert torch.equal(other.eval(f), before)
+    with pytest.raises(qc.QcollError):
+        other.set_tile(16)                  # 18..32-point grids have one tile family
+    plan.close()
+    other.close()
+
+
+@pytest.mark.parametrize("precision", ["fx16", "fp32"])
+def test_autotune_tile_family(qc, tmp_path, precision):
+    """A 16x16 plan runs on either tile family (the 16x16 kernels, or the 32x32
+    kernels on the zero-padded grid): both stay within the precision's bound of
+    the oracle, the autotuner picks among tiles x cells per workgroup x grid
+    caps, the cached choice reproduces its results bitwise, and the batched
+    call follows the plan's selected tile."""
+    from oracle import spectral as sp
+    tol = {"fx16": 1e-5, "fp32": 2e-4}[precision]
+    f64 = wl.mixture_cells(2, 16, 8.0, 600, 19)
+    f = torch.tensor(f64, dtype=torch.float32, device="cuda")
+    ref = sp.q_fast(f64.astype(np.float32).astype(np.float64), sp.Setup(d=2, N=16, L=8.0, kernel="maxwell", M=16))
+    plan = qc.Plan(2, 16, 8.0, "maxwell", 16, precision=precision)
+    assert plan.tile() == (16, 32)
+    outs = {}
+    for t in (16, 32):
+        plan.set_tile(t)
+        assert plan.tile() == (t, 48 - t)
+        q = plan.eval(f)
+        torch.cuda.synchronize()
+        outs[t] = q
+        err = np.linalg.norm(q.cpu().double().numpy() - ref) / np.linalg.norm(ref)
+        print(f"16x16 {precision} on the {t}x{t} tile kernels: rel L2 {err:.3e}")
+        assert err < tol
+    cache = str(tmp_path / "tune.json")
+    best = plan.autotune(f, reps=2, cache=cache)
+    assert best["tile"] in (16, 32) and plan.tile()[0] == best["tile"]
+    tuned = plan.eval(f)
+    other = qc.Plan(2, 16, 8.0, "maxwell", 16, precision=precision)
+    assert other.load_tuning(cache) and other.shape() == best
+    again = other.eval(f)
+    out_m = torch.empty_like(again)
+    qc.eval_multi([other], [f], [out_m])
+    torch.cuda.synchronize()
+    assert torch.equal(tuned, outs[best["tile"]]) and torch.equal(again, tuned) and torch.equal(out_m, tuned)
+    with pytest.raises(qc.QcollError):
+        other.set_tile(64)
     plan.close()
     other.close()
 
