@@ -75,27 +75,31 @@ __device__ __forceinline__ void pass64(const Split3 A[4], const Split3 E[3][2], 
 
 enum { kEr = 0, kEi = 1, kNEi = 2 };
 
-// DFT-matrix operands with the lo parts in LDS: lead and hi stay in registers
-// (48 VGPRs), the lo part (used by one of the six products) is read from a
-// block-shared LDS table [mat][K-slice][lane] right before its product.
-struct Split2 {
-  half8 l, h;
+// DFT-matrix operands with the hi and lo parts in LDS: the leads stay in
+// registers (24 VGPRs), the hi and lo parts are read from a block-shared LDS
+// table right before their products: lo at [mat][K-slice][lane], hi
+// kEoHiOffset entries further.
+struct Lead {
+  half8 l;
 };
 
-__device__ __forceinline__ void mma6_lo_lds(const Split3& a, const Split2& b, const half8* bo, f32x16& acc0,
+constexpr int kEoHiOffset = 6 * 64;
+
+__device__ __forceinline__ void mma6_lo_lds(const Split3& a, const Lead& b, const half8* bo, f32x16& acc0,
                                             f32x16& acc1) {
-  const half8 b_o = *bo;
+  const half8 b_o = bo[0];
+  const half8 b_h = bo[kEoHiOffset];
   acc0 = mfma16(a.l, b.l, acc0);
-  acc1 = mfma16(a.l, b.h, acc1);
   acc1 = mfma16(a.h, b.l, acc1);
-  acc1 = mfma16(a.h, b.h, acc1);
   acc1 = mfma16(a.o, b.l, acc1);
+  acc1 = mfma16(a.l, b_h, acc1);
+  acc1 = mfma16(a.h, b_h, acc1);
   acc1 = mfma16(a.l, b_o, acc1);
 }
 
-// pass64 with Split2 operands; eo is the LDS table of lo parts. An opaque lane
+// pass64 with Lead operands; eo is the LDS table of hi and lo parts. An opaque lane
 // index keeps the table reads inside the caller's loops.
-__device__ __forceinline__ void pass64_lo_lds(const Split3 A[4], const Split2 E[3][2], const half8* eo, int re_a,
+__device__ __forceinline__ void pass64_lo_lds(const Split3 A[4], const Lead E[3][2], const half8* eo, int re_a,
                                               int re_b, int im_a, int im_b, bool want_im, f32x16& r0, f32x16& r1,
                                               f32x16& i0, f32x16& i1) {
   int lane = threadIdx.x & 63;
@@ -116,9 +120,11 @@ __device__ __forceinline__ void pass64_lo_lds(const Split3 A[4], const Split2 E[
 // workgroup take part; ends with a workgroup barrier).
 __device__ __forceinline__ void load_eo_table(const KernelArgs& a, half8* eo) {
   const half8* src = reinterpret_cast<const half8*>(a.econst);
-  for (int i = threadIdx.x; i < 6 * 64; i += blockDim.x) {
-    const int ms = i >> 6, ln = i & 63;
-    eo[i] = src[ln * 18 + ms * 3 + 2];
+  for (int i = threadIdx.x; i < 2 * kEoHiOffset; i += blockDim.x) {
+    const int part = i < kEoHiOffset ? 2 : 1;   // lo, then hi
+    const int j = i < kEoHiOffset ? i : i - kEoHiOffset;
+    const int ms = j >> 6, ln = j & 63;
+    eo[i] = src[ln * 18 + ms * 3 + part];
   }
   __syncthreads();
 }
@@ -158,9 +164,9 @@ __device__ __forceinline__ void filtered_split(const double2* mv, const double2*
 
 // LDS of the FX16 body: per wavefront the cell's spectrum as FP64 complex
 // values in [register][lane] order, per workgroup the table of DFT-matrix lo
-// parts [mat][K-slice][lane].
+// and hi parts.
 constexpr int kFhatLdsBytes = 16 * 64 * 16;
-constexpr int kEoLdsBytes = 6 * 64 * 16;
+constexpr int kEoLdsBytes = 2 * kEoHiOffset * 16;
 
 // FX16 body. Register budget: at most 256 VGPRs per lane, so that two
 // wavefronts share each SIMD and the matrix-core work of one overlaps the
@@ -175,7 +181,7 @@ __device__ __forceinline__ void fx16_t32_body(const KernelArgs& a, int64_t first
 
   // DFT-matrix operands (Er, Ei, -Ei; two K-slices; lead and hi per lane; the
   // lo parts in the LDS table eo).
-  Split2 E[3][2];
+  Lead E[3][2];
   {
     const half8* src = reinterpret_cast<const half8*>(a.econst) + lane * 18;
 #pragma unroll
@@ -183,7 +189,6 @@ __device__ __forceinline__ void fx16_t32_body(const KernelArgs& a, int64_t first
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         E[m][s].l = src[(m * 2 + s) * 3 + 0];
-        E[m][s].h = src[(m * 2 + s) * 3 + 1];
       }
   }
 
@@ -326,7 +331,7 @@ template <int OUT>
 __device__ __forceinline__ void fx16_t32_body_pp(const KernelArgs& a, int64_t first, int64_t stride, int64_t kmax,
                                                  bool late, double2* fh, const half8* eo) {
   const int lane = threadIdx.x & 63;
-  Split2 E[3][2];
+  Lead E[3][2];
   {
     const half8* src = reinterpret_cast<const half8*>(a.econst) + lane * 18;
 #pragma unroll
@@ -334,7 +339,6 @@ __device__ __forceinline__ void fx16_t32_body_pp(const KernelArgs& a, int64_t fi
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         E[m][s].l = src[(m * 2 + s) * 3 + 0];
-        E[m][s].h = src[(m * 2 + s) * 3 + 1];
       }
   }
   if (late) pp_phase_end();

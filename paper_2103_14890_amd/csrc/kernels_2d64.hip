@@ -136,7 +136,7 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
 #pragma unroll
   for (int v = 0; v < 16; ++v) twp[v * 64 + lane] = cmul(tw[32 * p1 + rrow(v, h)], c2);
 
-  Split2 E[3][2];
+  Lead E[3][2];
   E32 E3;
   if constexpr (FX) {
     load_eo_table(a, eo);
@@ -146,7 +146,6 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         E[m][s].l = src[(m * 2 + s) * 3 + 0];
-        E[m][s].h = src[(m * 2 + s) * 3 + 1];
       }
   } else {
     (void)eo;
@@ -314,7 +313,9 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
       gain[v] -= static_cast<double>(fv[v]) * lf;
     }
 
-    // ---- epilogue on this wave's parity class; cell-wide sums through LDS. The
+    // ---- epilogue on this wave's parity class; cell-wide sums through LDS.
+    // Results and stage slots stream through L2 with non-temporal accesses, so
+    // that they do not evict the filter table all cells of a CU share. The
     // lane indices are re-derived from an opaque copy so that the per-point
     // velocities and addresses are not hoisted out of the cell loop.
     int elane = lane;
@@ -326,14 +327,14 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int r = rrow(v, h);
-        if (r < np && c < np) Qc[(2 * r + p1) * n + 2 * c + p2] = gain[v];
+        if (r < np && c < np) __builtin_nontemporal_store(gain[v], &Qc[(2 * r + p1) * n + 2 * c + p2]);
       }
     } else if (OUT == 0) {
       float* Qc = reinterpret_cast<float*>(a.q) + cell * static_cast<int64_t>(n) * n;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int r = rrow(v, h);
-        if (r < np && c < np) Qc[(2 * r + p1) * n + 2 * c + p2] = static_cast<float>(gain[v]);
+        if (r < np && c < np) __builtin_nontemporal_store(static_cast<float>(gain[v]), &Qc[(2 * r + p1) * n + 2 * c + p2]);
       }
     } else if (OUT == 1) {
       double m[4] = {0, 0, 0, 0};
@@ -364,29 +365,34 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
         const int r = rrow(v, h);
         const double v1 = -a.L + a.dv * (2 * r + p1);
         const double corr = lam[0] + lam[1] * v1 + lam[2] * v2c + lam[3] * (v1 * v1 + v2c * v2c);
-        if (r < np && c < np) Qc[(2 * r + p1) * n + 2 * c + p2] = gain[v] - corr;
+        if (r < np && c < np) __builtin_nontemporal_store(gain[v] - corr, &Qc[(2 * r + p1) * n + 2 * c + p2]);
       }
     } else if (OUT == 3) {
       // stage l of the penalised IMEX RK step (as finish_cell<3> of the 32x32
       // kernels); fv holds the input F_{l-1}, gain its Q (FP64)
-      const int sch = a.rk_scheme - 1;
+      // The scheme and stage indices are made opaque here, so that the tableau
+      // coefficients are loaded in the epilogue of each cell: hoisted out of
+      // the cell loop they would occupy scalar registers through the filter
+      // loop, whose spills to vector lanes cost it its overlapped LDS reads.
+      int sch = a.rk_scheme - 1, l = a.rk_stage;
+      asm volatile("" : "+s"(sch), "+s"(l));
       const int S = sch == 0 ? 3 : 5;
-      const int l = a.rk_stage;
       const double* At = kRkAt[sch][l - 1];
       const double* Ai = kRkA[sch][l - 1];
       const int64_t base = cell * static_cast<int64_t>(n) * n;
       float* fnp = a.rk_fn + base;
-      double fn[16];
+      // f^n is read twice (moments, then the update) instead of being held in
+      // registers through the stage sums
       double sm[4] = {0, 0, 0, 0};
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int r = rrow(v, h);
         const double v1 = -a.L + a.dv * (2 * r + p1);
-        fn[v] = (r < np && c < np) ? static_cast<double>(fnp[(2 * r + p1) * n + 2 * c + p2]) : 0.0;
-        sm[0] += fn[v];
-        sm[1] += v1 * fn[v];
-        sm[2] += v2c * fn[v];
-        sm[3] += (v1 * v1 + v2c * v2c) * fn[v];
+        const double fnv = (r < np && c < np) ? static_cast<double>(fnp[(2 * r + p1) * n + 2 * c + p2]) : 0.0;
+        sm[0] += fnv;
+        sm[1] += v1 * fnv;
+        sm[2] += v2c * fnv;
+        sm[3] += (v1 * v1 + v2c * v2c) * fnv;
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) sm[i] = wave_sum(sm[i]);
@@ -408,17 +414,18 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
         if (!(r < np && c < np)) continue;
         const int o = (2 * r + p1) * n + 2 * c + p2;
         const double v1 = -a.L + a.dv * (2 * r + p1);
+        const double fnv = static_cast<double>(fnp[o]);
         const double M = cM * exp(-((v1 - u1) * (v1 - u1) + (v2c - u2) * (v2c - u2)) / (2.0 * Tm));
-        double rhs = fn[v] + Ai[l - 1] * k * nu * M;
+        double rhs = fnv + Ai[l - 1] * k * nu * M;
         for (int m = 1; m < l; ++m) {
-          const double Fm = m == 1 ? fn[v]
+          const double Fm = m == 1 ? fnv
                             : (m == l - 1 ? static_cast<double>(fv[v])
-                                          : static_cast<double>(a.rk_work[(m - 2) * a.rk_stride + base + o]));
+                                          : static_cast<double>(__builtin_nontemporal_load(&a.rk_work[(m - 2) * a.rk_stride + base + o])));
           const double Sm = nu * (M - Fm);
           double acc = Ai[m - 1] * Sm;
           if (At[m - 1] != 0.0) {
             const double Qm =
-                m == l - 1 ? gain[v] : static_cast<double>(a.rk_work[(S - 3 + m) * a.rk_stride + base + o]);
+                m == l - 1 ? gain[v] : static_cast<double>(__builtin_nontemporal_load(&a.rk_work[(S - 3 + m) * a.rk_stride + base + o]));
             acc += At[m - 1] * (Qm - Sm);
           }
           rhs += k * acc;
@@ -426,10 +433,10 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
         const float Fl = static_cast<float>(rhs / den);
         if (l == S) {
           bad |= !(fabsf(Fl) <= 3.0e38f);
-          fnp[o] = Fl;
+          __builtin_nontemporal_store(Fl, &fnp[o]);
         } else {
-          a.rk_work[(l - 2) * a.rk_stride + base + o] = Fl;
-          a.rk_work[(S - 3 + (l - 1)) * a.rk_stride + base + o] = static_cast<float>(gain[v]);
+          __builtin_nontemporal_store(Fl, &a.rk_work[(l - 2) * a.rk_stride + base + o]);
+          __builtin_nontemporal_store(static_cast<float>(gain[v]), &a.rk_work[(S - 3 + (l - 1)) * a.rk_stride + base + o]);
         }
       }
       if (l == S && a.status) {
@@ -457,7 +464,7 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
         const float nv = static_cast<float>(static_cast<double>(fv[v]) + k * gain[v]);
         if (r < np && c < np) {
           bad |= !(fabsf(nv) <= 3.0e38f);
-          fcell[(2 * r + p1) * n + 2 * c + p2] = nv;
+          __builtin_nontemporal_store(nv, &fcell[(2 * r + p1) * n + 2 * c + p2]);
         }
       }
       if (a.status) {

@@ -687,9 +687,11 @@ __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red
     // stage l of the penalised IMEX RK step (as finish_cell<3> of the 2D
     // kernels): M from the discrete moments of f^n, nu = rho(f^n); gain holds
     // Q(F_{l-1}) in FP64 and fc the input F_{l-1}
-    const int sch = a.rk_scheme - 1;
+    // opaque stage indices: the tableau coefficients are loaded here, per cell,
+    // not hoisted into scalar registers held through the transform loops
+    int sch = a.rk_scheme - 1, l = a.rk_stage;
+    asm volatile("" : "+s"(sch), "+s"(l));
     const int S = sch == 0 ? 3 : 5;
-    const int l = a.rk_stage;
     const double* At = kRkAt[sch][l - 1];
     const double* Ai = kRkA[sch][l - 1];
     float* fnp = a.rk_fn + base;

@@ -171,24 +171,27 @@ __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, 
     // nu = rho(f^n), S_m = nu (M - F_m), G_m = Q(F_m) - S_m,
     //   F_l = [f^n + k sum_{m<l} (At_lm G_m + A_lm S_m) + A_ll k nu M] / (1 + A_ll k nu).
     // q holds Q(F_{l-1}) of this launch (FP64), fv the input F_{l-1}.
-    const int sch = a.rk_scheme - 1;
+    // opaque stage indices: the tableau coefficients are loaded here, per cell,
+    // not hoisted into scalar registers held through the transform loops
+    int sch = a.rk_scheme - 1, l = a.rk_stage;
+    asm volatile("" : "+s"(sch), "+s"(l));
     const int S = sch == 0 ? 3 : 5;
-    const int l = a.rk_stage;
     const double* At = kRkAt[sch][l - 1];
     const double* Ai = kRkA[sch][l - 1];
     float* fnp = a.rk_fn + base;
-    double fn[kV];
+    // f^n is read twice (moments, then the update; the second read hits the
+    // cache) instead of being held in registers through the stage sums
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
     const double v2c = -a.L + a.dv * c;
 #pragma unroll
     for (int v = 0; v < kV; ++v) {
       const int r = LY::row(v, lane);
-      fn[v] = (r < n && c < n) ? static_cast<double>(fnp[r * n + c]) : 0.0;
+      const double fnv = (r < n && c < n) ? static_cast<double>(fnp[r * n + c]) : 0.0;
       const double v1 = -a.L + a.dv * r;
-      s0 += fn[v];
-      s1 += v1 * fn[v];
-      s2 += v2c * fn[v];
-      s3 += (v1 * v1 + v2c * v2c) * fn[v];
+      s0 += fnv;
+      s1 += v1 * fnv;
+      s2 += v2c * fnv;
+      s3 += (v1 * v1 + v2c * v2c) * fnv;
     }
     s0 = wave_sum(s0);
     s1 = wave_sum(s1);
@@ -205,11 +208,12 @@ __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, 
       const int r = LY::row(v, lane);
       if (!(r < n && c < n)) continue;
       const int o = r * n + c;
+      const double fnv = static_cast<double>(fnp[o]);
       const double v1 = -a.L + a.dv * r;
       const double M = cM * exp(-((v1 - u1) * (v1 - u1) + (v2c - u2) * (v2c - u2)) / (2.0 * T));
-      double rhs = fn[v] + Ai[l - 1] * k * nu * M;
+      double rhs = fnv + Ai[l - 1] * k * nu * M;
       for (int m = 1; m < l; ++m) {
-        const double Fm = m == 1 ? fn[v]
+        const double Fm = m == 1 ? fnv
                           : (m == l - 1 ? static_cast<double>(fv[v])
                                         : static_cast<double>(a.rk_work[(m - 2) * a.rk_stride + base + o]));
         const double Sm = nu * (M - Fm);
