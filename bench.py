@@ -593,6 +593,35 @@ def bench_variant(args) -> int:
     return 0
 
 
+def bkw_run(qcoll) -> dict:
+    """The BKW run (16x16 on [-8,8]^2, Maxwell molecules, M = 16, 100 explicit
+    Euler steps of dt = 0.01 from the closed form at t = 0): the error norms of
+    the paper's convergence table at t = 1 against the closed form, for both
+    GPU paths and for the FP64 oracle's own trajectory (accuracy leg)."""
+    import torch
+    from oracle import spectral as sp
+    from oracle.bkw import bkw_grid, error_norms
+    N, L, steps, dt = 16, 8.0, 100, 0.01
+    f0 = bkw_grid(N, L, 0.0)[None]
+    exact = bkw_grid(N, L, 1.0)[None]
+    out = {"setup": "N=16 on [-8,8]^2, Maxwell b=1/(2 pi), M=16, 100 explicit Euler steps dt=0.01, t=1"}
+    for prec in ("fx16", "fp32"):
+        plan = qcoll.Plan(2, N, L, "maxwell", 16, precision=prec)
+        f = torch.tensor(f0, dtype=torch.float32, device="cuda:0")
+        for _ in range(steps):
+            plan.step(f, dt, 1.0, "explicit")
+        torch.cuda.synchronize()
+        out[prec] = dict(zip(("L1", "L2", "Linf"), error_norms(f.cpu().double().numpy(), exact)))
+        plan.close()
+    s = sp.Setup(d=2, N=N, L=L, kernel="maxwell", M=16)
+    bank = sp.filter_bank(s)
+    g = f0.astype(np.float64)
+    for _ in range(steps):
+        g = g + dt * sp.q_fast(g, s, bank)
+    out["oracle_fp64"] = dict(zip(("L1", "L2", "Linf"), error_norms(g, exact)))
+    return out
+
+
 def graph_of(fn):
     """Capture fn (queued on the current stream) into a graph after one eager
     call on a side stream; returns the graph, whose replay repeats fn."""
@@ -742,6 +771,8 @@ def main() -> int:
     splan.close()
     del fs, work
 
+    bkw = bkw_run(qcoll) if NN == 32 else None
+
     transport = None
     if NN == 32:
         # the transport step of the explosion_16k mesh (the second HBM-bound path)
@@ -801,6 +832,7 @@ def main() -> int:
                       "p50": float(np.median(mix["per"]) * 1e3),
                       "p95": float(np.percentile(mix["per"], 95) * 1e3)},
         "step_ms": step_ms,
+        "bkw": bkw,
         "transport": transport,
         "p99_latency_ms": None if serve is None else serve["p99_ms"],
         "serving": serve,

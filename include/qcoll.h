@@ -208,12 +208,13 @@ int qcoll_step_rk_noalloc(qcoll_plan_t plan, float* f, int64_t cells, double dt,
  * on one device; slots with cells[i] == 0 are skipped. status may be NULL.
  * 2D plans with N <= 32 share one launch per 8 such slots; 2D plans with
  * N > 32 (a workgroup per cell) get one launch each; 3D plans (all slots 3D)
- * share one launch per 8 slots. When a 2D call has several launches they run
- * concurrently, the first on `stream` and the others on up to three side
+ * share one launch per 8 slots. When a 2D call has several launches and few
+ * cells (at most four per compute unit in total, as in a serving tick) they
+ * run concurrently, the first on `stream` and the others on up to three side
  * streams of the library (default priority) that wait for `stream` before
  * they start and that `stream` waits for afterwards, so the call as a whole is
- * ordered on `stream`; while `stream` is being captured into a graph they are
- * queued on `stream` one after another. 2D and 3D plans cannot be mixed in
+ * ordered on `stream`; larger calls, and calls while `stream` is being
+ * captured into a graph, queue the launches on `stream` one after another. 2D and 3D plans cannot be mixed in
  * one call (QCOLL_EUNSUPPORTED). 3D plans hold a scratch area: calls that use
  * the same 3D plan must not run concurrently on different streams. */
 int qcoll_eval_multi(const qcoll_plan_t* plans, int nplans, const float* const* f, void* const* Q,
