@@ -93,7 +93,9 @@ enum {
  * flags a combination of QCOLL_* flags. The plan owns its host and device
  * tables; apart from its launch shape (qcoll_plan_set_launch, set before use)
  * it is immutable and may be used from several streams at once, except 3D
- * plans, whose scratch area allows one call in flight at a time. On error *out
+ * plans, whose scratch area allows one call in flight at a time (the
+ * qcoll_eval_ws / qcoll_step_ws calls take a workspace of the caller's and
+ * lift that limit). On error *out
  * is set to NULL. Device plans: d = 2 with N <= 32 (grids below 16 or 32 run
  * zero-padded in a 16x16 or 32x32 tile) and 34 <= N <= 64 (radix-2 split into
  * 32-point tiles, one workgroup per cell), both in either precision; d = 3
@@ -136,6 +138,23 @@ int qcoll_plan_vhs(qcoll_plan_t* out, int n_per_dim, double L, double gamma, dou
  * buffers. Returns QCOLL_EINVAL for a NULL pointer or negative count,
  * QCOLL_EUNSUPPORTED for a host-only plan. */
 int qcoll_eval(qcoll_plan_t plan, const float* f, void* Q, int64_t cells, hipStream_t stream);
+
+/* The same evaluation and single-stage step with a workspace owned by the
+ * caller in place of the plan's own scratch: 3D plans run one workgroup per
+ * qcoll_scratch_bytes() of `work` (at least one; more allow more workgroups in
+ * flight, up to one per cell), so that calls on the same 3D plan with distinct
+ * workspaces may run concurrently on different streams (the plan's own scratch
+ * allows one call in flight). 2D plans use no scratch: work may be NULL and
+ * is ignored. QCOLL_EINVAL for a 3D plan with work NULL, not 256-byte aligned,
+ * or work_bytes below one workgroup's scratch; otherwise arguments, results and errors as for
+ * qcoll_eval and qcoll_step. qcoll_scratch_bytes: bytes of one workgroup's
+ * scratch of a 3D device plan (144 T^3 for its T^3 tile), 0 for other plans,
+ * -1 for NULL. */
+int64_t qcoll_scratch_bytes(qcoll_plan_t plan);
+int qcoll_eval_ws(qcoll_plan_t plan, const float* f, void* Q, int64_t cells, void* work, int64_t work_bytes,
+                  hipStream_t stream);
+int qcoll_step_ws(qcoll_plan_t plan, float* f, int64_t cells, double dt, double eps, int scheme, int32_t* status,
+                  void* work, int64_t work_bytes, hipStream_t stream);
 
 /* One space-homogeneous step of d f/dt = Q(f)/eps in place (section 3.4):
  *   QCOLL_EXPLICIT_EULER:        f <- f + (dt/eps) Q(f)

@@ -517,9 +517,10 @@ qcoll::Slot3 make_slot3(const qcoll_plan_s* p) {
 }
 
 // One 3D launch over the given slots, using the scratch of the plan with the
-// largest tile.
+// largest tile, or the caller's scratch area `ws` of ws_bytes (one workgroup
+// per scratch_3d_bytes of it).
 int launch3(const qcoll_plan_s* const* plans, const qcoll::Slot3* slots, int nslots, const int64_t* cells,
-            hipStream_t stream) {
+            hipStream_t stream, char* ws = nullptr, int64_t ws_bytes = 0) {
   qcoll::Args3 A;
   const qcoll_plan_s* big = nullptr;
   int64_t total = 0;
@@ -535,6 +536,11 @@ int launch3(const qcoll_plan_s* const* plans, const qcoll::Slot3* slots, int nsl
   A.scratch = big->scratch;
   A.scratch_stride = big->scratch_stride;
   A.blocks = big->scratch_blocks;
+  if (ws) {
+    A.scratch = ws;
+    A.blocks = ws_bytes / big->scratch_stride;
+    if (A.blocks < 1) return -1;
+  }
   return qcoll::launch_3d(A, stream);
 }
 
@@ -736,7 +742,8 @@ int qcoll_plan_vhs(qcoll_plan_t* out, int n_per_dim, double L, double gamma, dou
   return plan_create_nothrow(out, 2, n_per_dim, L, QCOLL_VHS, gamma, b, M, K_r, precision, flags);
 }
 
-int qcoll_eval(qcoll_plan_t p, const float* f, void* Q, int64_t cells, hipStream_t stream) {
+static int eval_impl(qcoll_plan_t p, const float* f, void* Q, int64_t cells, char* ws, int64_t ws_bytes,
+                     hipStream_t stream) {
   if (!p || cells < 0) return QCOLL_EINVAL;
   if (!p->on_device || p->galerkin) return QCOLL_EUNSUPPORTED;
   if (cells == 0) return QCOLL_OK;
@@ -763,7 +770,7 @@ int qcoll_eval(qcoll_plan_t p, const float* f, void* Q, int64_t cells, hipStream
     s3.q = Q;
     s3.out_kind = (p->flags & QCOLL_CONSERVE) ? 1 : 0;
     const qcoll_plan_s* pl = p;
-    return launch3(&pl, &s3, 1, &cells, stream) ? QCOLL_EDEVICE : QCOLL_OK;
+    return launch3(&pl, &s3, 1, &cells, stream, ws, ws_bytes) ? QCOLL_EDEVICE : QCOLL_OK;
   }
   qcoll::KernelArgs a = make_args(p);
   a.f = f;
@@ -773,8 +780,12 @@ int qcoll_eval(qcoll_plan_t p, const float* f, void* Q, int64_t cells, hipStream
   return launch(a, stream) ? QCOLL_EDEVICE : QCOLL_OK;
 }
 
-int qcoll_step(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps, int scheme,
-               int32_t* status, hipStream_t stream) {
+int qcoll_eval(qcoll_plan_t p, const float* f, void* Q, int64_t cells, hipStream_t stream) {
+  return eval_impl(p, f, Q, cells, nullptr, 0, stream);
+}
+
+static int step_impl(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps, int scheme,
+                     int32_t* status, char* ws, int64_t ws_bytes, hipStream_t stream) {
   if (!p || cells < 0) return QCOLL_EINVAL;
   if (!(dt > 0.0) || !(eps > 0.0) || !std::isfinite(dt) || !std::isfinite(eps)) return QCOLL_EINVAL;
   if (scheme != QCOLL_EXPLICIT_EULER && scheme != QCOLL_IMEX_EULER_PENALIZED) return QCOLL_EINVAL;
@@ -789,7 +800,7 @@ int qcoll_step(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps, i
     s3.status = status;
     s3.out_kind = 2;
     const qcoll_plan_s* pl = p;
-    return launch3(&pl, &s3, 1, &cells, stream) ? QCOLL_EDEVICE : QCOLL_OK;
+    return launch3(&pl, &s3, 1, &cells, stream, ws, ws_bytes) ? QCOLL_EDEVICE : QCOLL_OK;
   }
   qcoll::KernelArgs a = make_args(p);
   a.f = f;
@@ -799,6 +810,42 @@ int qcoll_step(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps, i
   a.status = status;
   a.out_kind = 2;
   return launch(a, stream) ? QCOLL_EDEVICE : QCOLL_OK;
+}
+
+int qcoll_step(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps, int scheme,
+               int32_t* status, hipStream_t stream) {
+  return step_impl(p, f, cells, dt, eps, scheme, status, nullptr, 0, stream);
+}
+
+int64_t qcoll_scratch_bytes(qcoll_plan_t p) {
+  if (!p) return -1;
+  return (p->on_device && p->hp.d == 3) ? p->scratch_stride : 0;
+}
+
+// A workspace for 3D plans must hold at least one workgroup's scratch and be
+// 256-byte aligned (the kernels use 16-byte vector accesses at offsets that are
+// multiples of T^3 * 8 from it); 2D plans use none (work may be NULL).
+static int check_ws(qcoll_plan_t p, const void* work, int64_t work_bytes) {
+  if (!p) return QCOLL_EINVAL;
+  if (p->on_device && p->hp.d == 3 &&
+      (!work || work_bytes < p->scratch_stride || (reinterpret_cast<uintptr_t>(work) & 255) != 0))
+    return QCOLL_EINVAL;
+  return QCOLL_OK;
+}
+
+int qcoll_eval_ws(qcoll_plan_t p, const float* f, void* Q, int64_t cells, void* work, int64_t work_bytes,
+                  hipStream_t stream) {
+  if (int rc = check_ws(p, work, work_bytes)) return rc;
+  const bool d3 = p->on_device && p->hp.d == 3;
+  return eval_impl(p, f, Q, cells, d3 ? static_cast<char*>(work) : nullptr, work_bytes, stream);
+}
+
+int qcoll_step_ws(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps, int scheme, int32_t* status,
+                  void* work, int64_t work_bytes, hipStream_t stream) {
+  if (int rc = check_ws(p, work, work_bytes)) return rc;
+  const bool d3 = p->on_device && p->hp.d == 3;
+  return step_impl(p, f, cells, dt, eps, scheme, status, d3 ? static_cast<char*>(work) : nullptr, work_bytes,
+                   stream);
 }
 
 namespace {

@@ -60,6 +60,12 @@ def _load() -> ctypes.CDLL:
     lib.qcoll_eval.restype = c_int
     lib.qcoll_step.argtypes = [vp, vp, i64, dbl, dbl, c_int, vp, vp]
     lib.qcoll_step.restype = c_int
+    lib.qcoll_scratch_bytes.argtypes = [vp]
+    lib.qcoll_scratch_bytes.restype = i64
+    lib.qcoll_eval_ws.argtypes = [vp, vp, vp, i64, vp, i64, vp]
+    lib.qcoll_eval_ws.restype = c_int
+    lib.qcoll_step_ws.argtypes = [vp, vp, i64, dbl, dbl, c_int, vp, vp, i64, vp]
+    lib.qcoll_step_ws.restype = c_int
     lib.qcoll_step_rk_work_bytes.argtypes = [vp, c_int, i64]
     lib.qcoll_step_rk_work_bytes.restype = i64
     lib.qcoll_step_rk.argtypes = [vp, vp, i64, dbl, dbl, c_int, vp, i64, vp, vp]
@@ -239,6 +245,31 @@ class Plan:
                               _dev_ptr(q, torch.float64 if self.conserve else torch.float32, "Q"),
                               cells, _stream_ptr(stream)), "qcoll_eval")
         return q
+
+    def scratch_bytes(self) -> int:
+        """Bytes of one workgroup's scratch of a 3D plan (0 for 2D plans)."""
+        return _check(int(LIB.qcoll_scratch_bytes(self._h)), "qcoll_scratch_bytes")
+
+    def eval_ws(self, f, work, q=None, stream=None):
+        """Q_h(f) with the caller's workspace (qcoll_eval_ws): calls on one 3D plan
+        with distinct workspaces may run concurrently."""
+        import torch
+        if q is None:
+            q = _alloc(f.shape, torch.float64 if self.conserve else torch.float32, f, stream)
+        _check(LIB.qcoll_eval_ws(self._h, _dev_ptr(f, torch.float32, "f"),
+                                 _dev_ptr(q, torch.float64 if self.conserve else torch.float32, "Q"), f.shape[0],
+                                 _dev_ptr(work, work.dtype, "work"), work.numel() * work.element_size(),
+                                 _stream_ptr(stream)), "qcoll_eval_ws")
+        return q
+
+    def step_ws(self, f, dt: float, work, eps: float = 1.0, scheme: str = "explicit", status=None, stream=None):
+        """One homogeneous step of f in place with the caller's workspace (qcoll_step_ws)."""
+        import torch
+        st = ctypes.c_void_p(0) if status is None else _dev_ptr(status, torch.int32, "status")
+        _check(LIB.qcoll_step_ws(self._h, _dev_ptr(f, torch.float32, "f"), f.shape[0], float(dt), float(eps),
+                                 _SCHEMES[scheme], st, _dev_ptr(work, work.dtype, "work"),
+                                 work.numel() * work.element_size(), _stream_ptr(stream)), "qcoll_step_ws")
+        return f
 
     def galerkin_work_bytes(self, cells: int) -> int:
         return _check(int(LIB.qcoll_galerkin_work_bytes(self._h, int(cells))), "qcoll_galerkin_work_bytes")

@@ -60,6 +60,22 @@ def test_unsupported_and_host_only_paths():
     p.close()
 
 
+def test_workspace_calls_on_host_only_plans():
+    """qcoll_scratch_bytes / qcoll_eval_ws / qcoll_step_ws argument checks that
+    need no GPU: host-only plans report no scratch and refuse device work as
+    qcoll_eval does; NULL plans are refused."""
+    assert qc.LIB.qcoll_scratch_bytes(None) == -1
+    assert qc.LIB.qcoll_eval_ws(None, None, None, 4, None, 0, None) == qc.EINVAL
+    assert qc.LIB.qcoll_step_ws(None, None, 4, 0.01, 1.0, 0, None, None, 0, None) == qc.EINVAL
+    for d, N in ((2, 32), (3, 16)):
+        p = qc.Plan(d, N, 8.0, "hard_sphere", 8, host_only=True)
+        assert p.scratch_bytes() == 0
+        assert qc.LIB.qcoll_eval_ws(p._h, None, None, 4, None, 0, None) == qc.EUNSUPPORTED
+        assert qc.LIB.qcoll_eval_ws(p._h, None, None, -1, None, 0, None) == qc.EINVAL
+        assert qc.LIB.qcoll_step_ws(p._h, None, 4, 0.01, 1.0, 7, None, None, 0, None) == qc.EINVAL
+        p.close()
+
+
 @pytest.mark.parametrize("d,N,L,kernel,M", [(2, 32, 8.0, "hard_sphere", 8), (2, 32, 8.0, "maxwell", 8),
                                             (2, 16, 8.0, "maxwell", 16), (2, 64, 10.0, "hard_sphere", 16),
                                             (3, 8, 6.0, "hard_sphere", 8), (3, 16, 8.0, "hard_sphere", 32)])

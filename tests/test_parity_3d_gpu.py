@@ -321,3 +321,47 @@ def test_step_rk_3d(qc, scheme, N, precision):
     assert err <= 3e-5
     assert (status.cpu().numpy() == 0).all()
     plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fx16"])
+def test_workspace_calls_run_concurrently_on_one_plan(qc, precision):
+    """One 3D plan, two streams, two caller workspaces (qcoll_eval_ws /
+    qcoll_step_ws): concurrent calls equal the plan-scratch calls bitwise; a
+    workspace smaller than one workgroup's scratch is refused; 2D plans take
+    none."""
+    N = 16
+    plan = qc.Plan(3, N, 8.0, "hard_sphere", 8, precision=precision, conserve=True)
+    sb = plan.scratch_bytes()
+    assert sb == 144 * 16 ** 3
+    fa = torch.tensor(wl.mixture_cells(3, N, 8.0, 40, 91), dtype=torch.float32, device="cuda")
+    fb = torch.tensor(wl.mixture_cells(3, N, 8.0, 24, 92), dtype=torch.float32, device="cuda")
+    ra, rb = plan.eval(fa), plan.eval(fb)
+    torch.cuda.synchronize()
+    wa = torch.empty(3 * sb, dtype=torch.uint8, device="cuda")     # three workgroups in flight
+    wb = torch.empty(sb, dtype=torch.uint8, device="cuda")         # one
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    s2.wait_stream(torch.cuda.current_stream())
+    qa = plan.eval_ws(fa, wa, stream=s1)
+    qb = plan.eval_ws(fb, wb, stream=s2)
+    torch.cuda.current_stream().wait_stream(s1)
+    torch.cuda.current_stream().wait_stream(s2)
+    torch.cuda.synchronize()
+    assert torch.equal(qa, ra) and torch.equal(qb, rb)
+    step_plan = qc.Plan(3, N, 8.0, "hard_sphere", 8, precision=precision)
+    x, y = fa.clone(), fa.clone()
+    step_plan.step(x, 0.01, 1.0, "imex")
+    step_plan.step_ws(y, 0.01, wa, 1.0, "imex")
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
+    small = torch.empty(sb - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(qc.QcollError):
+        plan.eval_ws(fa, small)
+    with pytest.raises(qc.QcollError):          # misaligned
+        plan.eval_ws(fa, wa[16:16 + 2 * sb])
+    p2 = qc.Plan(2, 32, 8.0, "hard_sphere", 8, precision=precision)
+    assert p2.scratch_bytes() == 0
+    f2 = torch.tensor(wl.mixture_cells(2, 32, 8.0, 5, 93), dtype=torch.float32, device="cuda")
+    assert torch.equal(p2.eval_ws(f2, small), p2.eval(f2))
+    for p in (plan, step_plan, p2):
+        p.close()

@@ -142,6 +142,29 @@ def test_full_workload_sampled_cells(qc):
     plan.close()
 
 
+@pytest.mark.parametrize("precision", ["fx16", "fp32"])
+def test_config3_full_batch_sampled_cells(qc, precision):
+    """The 20000-cell 64x64 noisy workload (config 3) in one launch with the
+    stored autotuner shape the benchmark times, FP64 projection: 32 cells spread
+    over the batch against the oracle (batch and per-cell bounds of the
+    precision), and the discrete mass of every cell."""
+    f = wl.config_inputs("hs2d_64_noisy")
+    plan = qc.Plan(2, 64, 10.0, "hard_sphere", 16, precision=precision, conserve=True)
+    plan.load_tuning()
+    q = plan.eval(torch.tensor(f, dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    idx = np.linspace(0, len(f) - 1, 32).astype(int)
+    got = q[idx].cpu().numpy()
+    ref = sp.project_conservative(_ref(f[idx], "hard_sphere", 16, N=64, L=10.0), 2, 10.0)
+    err, cerr = _rel(got, ref), _cell_rel(got, ref)
+    print(f"config 3, 20000 cells, {precision}: 32 sampled cells rel L2 {err:.3e}, worst cell {cerr:.3e}")
+    assert err < TOL[precision] and cerr < 5 * TOL[precision]
+    qa = q.cpu().numpy()
+    mass = np.abs(qa.sum(axis=(1, 2))) / np.abs(qa).sum(axis=(1, 2))
+    assert mass.max() <= 1e-12
+    plan.close()
+
+
 def test_edge_cases(qc):
     plan = qc.Plan(2, 32, 8.0, "hard_sphere", 8, precision="fx16")
     empty = torch.empty((0, 32, 32), dtype=torch.float32, device="cuda")
