@@ -272,21 +272,31 @@ def measured_traffic(workload: str):
 
 
 def time_launches(fn, steps: int, warmup: int, stream):
+    """Time `steps` calls of fn after `warmup` untimed ones. Returns (step, per):
+    step = seconds per call of `steps` back-to-back calls between two events,
+    with a synchronisation on both sides (the whole-job rate); per = each call
+    of a second run of `steps` calls timed between its own pair of events (the
+    spread of a single launch's latency)."""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        fn()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    step = t0.elapsed_time(t1) / 1e3 / steps
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    t0 = time.perf_counter()
     for i in range(steps):
         starts[i].record(stream)
         fn()
         ends[i].record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     per = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)]) / 1e3
-    return wall, per
+    return step, per
 
 
 def copy_calibration(mib: int, dev) -> None:
@@ -342,9 +352,8 @@ def bench_3d(args) -> int:
     qa = torch.empty(fa.shape, dtype=torch.float64, device=dev)
     qb = torch.empty(fb.shape, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
-    wall, per = time_launches(lambda: qcoll.eval_multi([pa, pb], [fa, fb], [qa, qb]), args.steps, args.warmup,
-                              stream)
-    T_ = float(np.mean(per))
+    T_, per = time_launches(lambda: qcoll.eval_multi([pa, pb], [fa, fb], [qa, qb]), args.steps, args.warmup,
+                            stream)
     cells = fa.shape[0] + fb.shape[0]
 
     # one IMEX Euler stage (Q plus the update) over both resolutions, captured in
@@ -359,7 +368,7 @@ def bench_3d(args) -> int:
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         qcoll.step_multi([pa, pb], [ga, gb], 0.01, 1.0, "imex")
-    _, per_stage = time_launches(graph.replay, max(2, args.steps // 2), 1, stream)
+    T_stage, per_stage = time_launches(graph.replay, max(2, args.steps // 2), 1, stream)
     del ga, gb
     copy_calibration(args.calibrate_copy, dev)
     tr = pa.info()["transforms"]
@@ -425,7 +434,7 @@ def bench_3d(args) -> int:
         "mass_defect_max": mass,
         "launch_ms": {"p5": float(np.percentile(per, 5) * 1e3), "p50": float(np.median(per) * 1e3),
                       "p95": float(np.percentile(per, 95) * 1e3)},
-        "imex_stage_graph_ms": float(np.median(per_stage) * 1e3),
+        "imex_stage_graph_ms": T_stage * 1e3,
         "p99_latency_ms": None,
     }
     print(json.dumps(out))
@@ -459,16 +468,15 @@ def transport_run(name: str, steps: int, warmup: int, stream):
     out = torch.empty_like(f)
     work = torch.empty(plan.work_bytes() // 4, dtype=torch.float32, device="cuda:0")
     dt = 0.4 / 128 / (math.sqrt(2.0) * L)
-    _, per = time_launches(lambda: plan.step(f, dt, out=out, work=work), steps, warmup, stream)
-    return mesh, f64, N, L, plan, f, out, dt, per
+    T_, per = time_launches(lambda: plan.step(f, dt, out=out, work=work), steps, warmup, stream)
+    return mesh, f64, N, L, plan, f, out, dt, T_, per
 
 
 def bench_transport(args) -> int:
     import torch
     stream = torch.cuda.current_stream()
-    mesh, f64, N, L, plan, f, out, dt, per = transport_run(args.workload, args.steps, args.warmup, stream)
+    mesh, f64, N, L, plan, f, out, dt, T_, per = transport_run(args.workload, args.steps, args.warmup, stream)
     copy_calibration(args.calibrate_copy, torch.device("cuda:0"))
-    T_ = float(np.mean(per))
     V = N * N
     units = mesh.n * V
     alg_bytes = 8.0 * units            # f read once, the updated f written once
@@ -552,9 +560,8 @@ def bench_variant(args) -> int:
     else:
         plan = qcoll.Plan(2, N, L, kern, M, precision="fx16", conserve=True, gamma=0.5)
         call = lambda: plan.eval(f, q)                        # noqa: E731
-    wall, per = time_launches(call, args.steps, args.warmup, stream)
+    T_, per = time_launches(call, args.steps, args.warmup, stream)
     copy_calibration(args.calibrate_copy, dev)
-    T_ = float(np.mean(per))
     info = plan.info()
 
     # the oracle on the host cores, a bounded prefix of the same cells (tables
@@ -731,8 +738,8 @@ def main() -> int:
             continue
         q = torch.empty((cells, NN, NN), dtype=torch.float64, device=dev)
         # eager calls with the default launch shape
-        _, per = time_launches(lambda: plan.eval(f, q), args.steps, args.warmup, stream)
-        res[prec] = dict(plan=plan, q=q, per=per, info=plan.info(), eager_default=float(np.mean(per)),
+        t_def, per = time_launches(lambda: plan.eval(f, q), args.steps, args.warmup, stream)
+        res[prec] = dict(plan=plan, q=q, per=per, info=plan.info(), eager_default=t_def,
                          default_shape=plan.shape())
         # the spec form: launch shape from the autotuner (its stored choice
         # for this plan, else a tuning run now), the call captured in a graph
@@ -740,10 +747,10 @@ def main() -> int:
             res[prec]["tuned_shape"], res[prec]["tuned_from"] = plan.shape(), "stored autotuner choice"
         else:
             res[prec]["tuned_shape"], res[prec]["tuned_from"] = plan.autotune(f, reps=3), "autotuned in this run"
-        _, per_e = time_launches(lambda: plan.eval(f, q), args.steps, args.warmup, stream)
+        t_e, _ = time_launches(lambda: plan.eval(f, q), args.steps, args.warmup, stream)
         g = graph_of(lambda: plan.eval(f, q))
-        _, per_g = time_launches(g.replay, args.steps, args.warmup, stream)
-        res[prec].update(per=per_g, graph=g, eager_tuned=float(np.mean(per_e)))
+        t_g, per_g = time_launches(g.replay, args.steps, args.warmup, stream)
+        res[prec].update(per=per_g, step=t_g, graph=g, eager_tuned=t_e)
 
     copy_calibration(args.calibrate_copy, dev)
 
@@ -784,8 +791,8 @@ def main() -> int:
     for name, fn in (("imex_euler", lambda: splan.step(fs, 0.01, 1.0, "imex")),
                      ("ars222", lambda: splan.step_rk(fs, 0.01, 1.0, "ars222", work=work)),
                      ("bpr343", lambda: splan.step_rk(fs, 0.01, 1.0, "bpr343", work=work))):
-        _, per_s = time_launches(fn, max(3, args.steps // 5), 1, stream)
-        step_ms[name] = float(np.median(per_s) * 1e3)
+        t_s, _ = time_launches(fn, max(3, args.steps // 5), 1, stream)
+        step_ms[name] = t_s * 1e3
     splan.close()
     del fs, work
 
@@ -794,21 +801,21 @@ def main() -> int:
     transport = None
     if NN == 32:
         # the transport step of the explosion_16k mesh (the second HBM-bound path)
-        mesh_t, _, Nt, _, tplan, _, _, _, per_t = transport_run("explosion_16k", max(5, args.steps // 5), 2, stream)
-        Tt = float(np.mean(per_t))
+        mesh_t, _, Nt, _, tplan, _, _, _, Tt, _ = transport_run("explosion_16k", max(5, args.steps // 5), 2,
+                                                                stream)
         transport = {"workload": "explosion_16k", "ms_per_step": Tt * 1e3,
                      "value": mesh_t.n * Nt * Nt / Tt, "unit": "cell-velocity updates/s",
                      "alu_frac": transport_flops(mesh_t, Nt * Nt) / Tt / FP32_VALU_PEAK}
         tplan.close()
 
     mix = res["fx16"]
-    T = float(np.mean(mix["per"]))
+    T = mix["step"]
     value = cells / T
     roof, conv = roofline_2d(cells, T, mix["info"]["transforms"], NN, "fx16", measured_traffic(args.workload))
     fp32 = res.get("fp32")
     fp32_line = None
     if fp32 is not None:
-        T32 = float(np.mean(fp32["per"]))
+        T32 = fp32["step"]
         r32, c32 = roofline_2d(cells, T32, fp32["info"]["transforms"], NN, "fp32", None)
         fp32_line = {"value": cells / T32, "ms_per_step": T32 * 1e3, "eager_default_ms": fp32["eager_default"] * 1e3,
                      "rel_err_l2": fp32["rel_err"], "worst_cell_rel": fp32["worst_cell"],
@@ -832,7 +839,8 @@ def main() -> int:
         "config": {"workload": f"{args.workload}: {DESC}",
                    "cells": cells, "N_v": f"{NN}x{NN}", "kernel": KERN, "M": MM,
                    "K_r": mix["info"]["K_r"],
-                   "timed": "graph replay of one evaluation over all cells, autotuned launch shape"},
+                   "timed": "K back-to-back graph replays of one evaluation over all cells between two events, "
+                            "autotuned launch shape"},
         "roofline": roof,
         "roofline_conventions": conv,
         "cpu_baseline": baseline_line(base, "cell-evals/s", f"first {ncpu} cells of the same workload"),
@@ -845,7 +853,7 @@ def main() -> int:
         "eager_ms": {"default_shape": mix["eager_default"] * 1e3, "tuned_shape": mix["eager_tuned"] * 1e3},
         "launch_shape": {"default": mix["default_shape"], "tuned": mix["tuned_shape"], "from": mix["tuned_from"]},
         "fp32_path": fp32_line,
-        "speedup_vs_fp32": None if fp32 is None else float(np.mean(fp32["per"])) / T,
+        "speedup_vs_fp32": None if fp32 is None else fp32["step"] / T,
         "launch_ms": {"p5": float(np.percentile(mix["per"], 5) * 1e3),
                       "p50": float(np.median(mix["per"]) * 1e3),
                       "p95": float(np.percentile(mix["per"], 95) * 1e3)},

@@ -260,41 +260,41 @@ __device__ __forceinline__ void fx16_t32_body(const KernelArgs& a, int64_t first
       for (int v = 0; v < 16; ++v) mv[v] = load_filter_value(a.filt, 0, v, l16);
       filtered_split(mv, fh, lane, A);
     }
-    int sd_loss = 0;
-    for (int q = 0; q <= a.P; ++q) {
+    for (int q = 0; q < a.P; ++q) {
       // inverse pass A (contraction over the first axis)
       pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
       const int a2 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
       slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a2), A);
-      // inverse pass B (second axis); the loss field needs only the real part
-      const bool gain_q = q < a.P;
-      pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, gain_q, r0, r1, i0, i1);
+      // inverse pass B (second axis)
+      pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
       const int sd = a.filt_exp[q] + s_fh - 9 - a2 - 9;  // true field = accumulator * 2^sd
-      if (gain_q) {
-        // first half of the next filter in flight during the gain update, the
-        // second half once the accumulators are consumed
-        __builtin_amdgcn_sched_barrier(0);
-        double2 mv[16];
-        const unsigned l16 = opaque_lane16(lane);
+      // first half of the next filter in flight during the gain update, the
+      // second half once the accumulators are consumed
+      __builtin_amdgcn_sched_barrier(0);
+      double2 mv[16];
+      const unsigned l16 = opaque_lane16(lane);
 #pragma unroll
-        for (int v = 0; v < 8; ++v) mv[v] = load_filter_value(a.filt, q + 1, v, l16);
-        __builtin_amdgcn_sched_barrier(0);
-        const double w = ldexp(1.0, 2 * sd);
+      for (int v = 0; v < 8; ++v) mv[v] = load_filter_value(a.filt, q + 1, v, l16);
+      __builtin_amdgcn_sched_barrier(0);
+      const double w = ldexp(1.0, 2 * sd);
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const double re = static_cast<double>(r0[v]) + static_cast<double>(r1[v]);
-          const double im = static_cast<double>(i0[v]) + static_cast<double>(i1[v]);
-          gain[v] = fma(re * w, im, gain[v]);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int v = 8; v < 16; ++v) mv[v] = load_filter_value(a.filt, q + 1, v, l16);
-        __builtin_amdgcn_sched_barrier(0);
-        filtered_split(mv, fh, lane, A);
-      } else {
-        sd_loss = sd;
+      for (int v = 0; v < 16; ++v) {
+        const double re = static_cast<double>(r0[v]) + static_cast<double>(r1[v]);
+        const double im = static_cast<double>(i0[v]) + static_cast<double>(i1[v]);
+        gain[v] = fma(re * w, im, gain[v]);
       }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int v = 8; v < 16; ++v) mv[v] = load_filter_value(a.filt, q + 1, v, l16);
+      __builtin_amdgcn_sched_barrier(0);
+      filtered_split(mv, fh, lane, A);
     }
+    // the loss transform (entry P): only the real part of pass B is needed
+    pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
+    const int a2l = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
+    slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a2l), A);
+    pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, false, r0, r1, i0, i1);
+    const int sd_loss = a.filt_exp[a.P] + s_fh - 9 - a2l - 9;
     // the last transform is the loss field: Q = gain - f * loss
     float fv[16];
     load_cell<Lay32>(a, cell, lane, fv);
@@ -405,8 +405,7 @@ __device__ __forceinline__ void fx16_t32_body_pp(const KernelArgs& a, int64_t fi
       filtered_split(mv, fh, lane, A);
     }
     pp_phase_end();
-    int sd_loss = 0;
-    for (int q = 0; q <= a.P; ++q) {
+    for (int q = 0; q < a.P; ++q) {
       // [matrix] inverse pass A
       pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
       pp_phase_end();
@@ -414,39 +413,43 @@ __device__ __forceinline__ void fx16_t32_body_pp(const KernelArgs& a, int64_t fi
       const int a2 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
       slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a2), A);
       pp_phase_end();
-      // [matrix] inverse pass B (the loss field needs only the real part)
-      const bool gain_q = q < a.P;
-      pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, gain_q, r0, r1, i0, i1);
+      // [matrix] inverse pass B
+      pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
       const int sd = a.filt_exp[q] + s_fh - 9 - a2 - 9;
       pp_phase_end();
-      // [vector] gain update and the next filtered split (after the last, loss,
-      // transform the epilogue below is the vector phase)
-      if (gain_q) {
-        // first half of the next filter in flight during the gain update, the
-        // second half once the accumulators are consumed
-        __builtin_amdgcn_sched_barrier(0);
-        double2 mv[16];
-        const unsigned l16 = opaque_lane16(lane);
+      // [vector] gain update and the next filtered split; first half of the
+      // next filter in flight during the gain update, the second half once the
+      // accumulators are consumed
+      __builtin_amdgcn_sched_barrier(0);
+      double2 mv[16];
+      const unsigned l16 = opaque_lane16(lane);
 #pragma unroll
-        for (int v = 0; v < 8; ++v) mv[v] = load_filter_value(a.filt, q + 1, v, l16);
-        __builtin_amdgcn_sched_barrier(0);
-        const double w = ldexp(1.0, 2 * sd);
+      for (int v = 0; v < 8; ++v) mv[v] = load_filter_value(a.filt, q + 1, v, l16);
+      __builtin_amdgcn_sched_barrier(0);
+      const double w = ldexp(1.0, 2 * sd);
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const double re = static_cast<double>(r0[v]) + static_cast<double>(r1[v]);
-          const double im = static_cast<double>(i0[v]) + static_cast<double>(i1[v]);
-          gain[v] = fma(re * w, im, gain[v]);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int v = 8; v < 16; ++v) mv[v] = load_filter_value(a.filt, q + 1, v, l16);
-        __builtin_amdgcn_sched_barrier(0);
-        filtered_split(mv, fh, lane, A);
-        pp_phase_end();
-      } else {
-        sd_loss = sd;
+      for (int v = 0; v < 16; ++v) {
+        const double re = static_cast<double>(r0[v]) + static_cast<double>(r1[v]);
+        const double im = static_cast<double>(i0[v]) + static_cast<double>(i1[v]);
+        gain[v] = fma(re * w, im, gain[v]);
       }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int v = 8; v < 16; ++v) mv[v] = load_filter_value(a.filt, q + 1, v, l16);
+      __builtin_amdgcn_sched_barrier(0);
+      filtered_split(mv, fh, lane, A);
+      pp_phase_end();
     }
+    // the loss transform (entry P): [matrix] pass A, [vector] slice, [matrix]
+    // the real part of pass B; the epilogue below is its vector phase
+    pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
+    pp_phase_end();
+    const int a2l = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
+    slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a2l), A);
+    pp_phase_end();
+    pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, false, r0, r1, i0, i1);
+    const int sd_loss = a.filt_exp[a.P] + s_fh - 9 - a2l - 9;
+    pp_phase_end();
     // [vector] epilogue: Q = gain - f * loss
     {
       float fv[16];

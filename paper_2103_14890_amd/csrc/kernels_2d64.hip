@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "body_t32.hpp"
 
@@ -220,7 +221,11 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
 #pragma unroll
     for (int v = 0; v < 16; ++v) gain[v] = 0.0;
     int sd_last = 0;
-    for (int q = 0; q <= a.P; ++q) {
+    // one transform: q < P a gain transform (Re * Im of its inverse DFT), q = P
+    // the loss multiplier (real part only); the loss transform is issued after
+    // the loop so that the loop body has no branch on the kind of transform
+    auto transform = [&](int q, auto gain_kind) {
+      constexpr bool G = decltype(gain_kind)::value;
       // filtered quarter Z_a (true values) to LDS, with its max |component|
       // filter values of this quarter: [q][quarter][register v][lane] complex
       // (all 16 loads issued together: one exposed L2 latency per filter)
@@ -287,24 +292,29 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
         int sd = -b - 9;
         const int a2 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
         slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a2), A);
-        pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, q < a.P, r0, r1, i0, i1);  // loss: real part only
+        pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, G, r0, r1, i0, i1);  // loss: real part only
         sd = sd - a2 - 9;
-        sd_last = sd;
-        const double wq = q < a.P ? ldexp(1.0, 2 * sd) : 0.0;
+        if constexpr (G) {
+          const double wq = ldexp(1.0, 2 * sd);
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          double re = static_cast<double>(r0[v]) + static_cast<double>(r1[v]);
-          double im = static_cast<double>(i0[v]) + static_cast<double>(i1[v]);
-          gain[v] = fma(re * wq, im, gain[v]);
+          for (int v = 0; v < 16; ++v) {
+            double re = static_cast<double>(r0[v]) + static_cast<double>(r1[v]);
+            double im = static_cast<double>(i0[v]) + static_cast<double>(i1[v]);
+            gain[v] = fma(re * wq, im, gain[v]);
+          }
+        } else {
+          sd_last = sd;
         }
       } else {
-        inv_fp32(E3, zr, zi, q < a.P, r0, i0);   // loss: real part only
-        if (q < a.P) {
+        inv_fp32(E3, zr, zi, G, r0, i0);   // loss: real part only
+        if constexpr (G) {
 #pragma unroll
           for (int v = 0; v < 16; ++v) gain[v] += static_cast<double>(r0[v] * i0[v]);
         }
       }
-    }
+    };
+    for (int q = 0; q < a.P; ++q) transform(q, std::true_type{});
+    transform(a.P, std::false_type{});
     load_subgrid(a, cell, p1, p2, fv);  // re-read: not kept live through the filter loop
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
