@@ -3,6 +3,8 @@
 // multi-plan kernels.
 #pragma once
 
+#include <type_traits>
+
 #include "kernels_common.hpp"
 
 namespace qcoll {
@@ -506,10 +508,13 @@ __device__ __forceinline__ void fp32_t32_body(const KernelArgs& a, int64_t first
     double gain[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) gain[v] = 0.0;
-    for (int q = 0; q <= a.P; ++q) {
-      const bool loss = (q == a.P);
+    // gain transforms q < P, then the loss multiplier (entry P, real part
+    // only), issued after the loop so that the loop body has no branch on the
+    // kind of transform
+    auto transform = [&](int q, auto gain_kind) {
+      constexpr bool loss = !decltype(gain_kind)::value;
       float zr[16], zi[16];
-      if (!loss) {
+      if constexpr (!loss) {
         const float* mq = a.filt32 + (static_cast<int64_t>(q) * 64 + lane) * 32;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
@@ -538,12 +543,12 @@ __device__ __forceinline__ void fp32_t32_body(const KernelArgs& a, int64_t first
       for (int v = 0; v < 16; ++v) {
         yr = mfma32(dr[v], Er[v], yr);
         yr = mfma32(di[v], Ne[v], yr);
-        if (!loss) {
+        if constexpr (!loss) {
           yi = mfma32(dr[v], Ei[v], yi);
           yi = mfma32(di[v], Er[v], yi);
         }
       }
-      if (!loss) {
+      if constexpr (!loss) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) gain[v] += static_cast<double>(yr[v] * yi[v]);
       } else {
@@ -551,7 +556,9 @@ __device__ __forceinline__ void fp32_t32_body(const KernelArgs& a, int64_t first
         for (int v = 0; v < 16; ++v)
           gain[v] = gain[v] - static_cast<double>(fv[v]) * static_cast<double>(yr[v]);
       }
-    }
+    };
+    for (int q = 0; q < a.P; ++q) transform(q, std::true_type{});
+    transform(a.P, std::false_type{});
     finish_cell<OUT, Lay32>(a, cell, fv, gain, lane);
   }
 }
