@@ -690,6 +690,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--rounds", type=int, default=5,
+                    help="timed runs of --steps steps per form (eager default shape, eager tuned shape, graph "
+                         "replay), alternating; the medians are reported")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="host time for the three timed passes of the oracle baseline together")
     ap.add_argument("--workload", default="hs2d_32",
@@ -737,20 +740,32 @@ def main() -> int:
                 raise
             continue
         q = torch.empty((cells, NN, NN), dtype=torch.float64, device=dev)
-        # eager calls with the default launch shape
-        t_def, per = time_launches(lambda: plan.eval(f, q), args.steps, args.warmup, stream)
-        res[prec] = dict(plan=plan, q=q, per=per, info=plan.info(), eager_default=t_def,
-                         default_shape=plan.shape())
+        default = plan.shape()
+        res[prec] = dict(plan=plan, q=q, info=plan.info(), default_shape=default)
         # the spec form: launch shape from the autotuner (its stored choice
         # for this plan, else a tuning run now), the call captured in a graph
         if plan.load_tuning():
             res[prec]["tuned_shape"], res[prec]["tuned_from"] = plan.shape(), "stored autotuner choice"
         else:
             res[prec]["tuned_shape"], res[prec]["tuned_from"] = plan.autotune(f, reps=3), "autotuned in this run"
-        t_e, _ = time_launches(lambda: plan.eval(f, q), args.steps, args.warmup, stream)
+        tuned = plan.shape()
         g = graph_of(lambda: plan.eval(f, q))
-        t_g, per_g = time_launches(g.replay, args.steps, args.warmup, stream)
-        res[prec].update(per=per_g, step=t_g, graph=g, eager_tuned=t_e)
+        # rounds of K steps each in the three forms (eager with the default shape,
+        # eager with the tuned shape, graph replay), alternating, so that a
+        # transient of the GPU's clock affects all three alike; medians reported
+        td, te, tg = [], [], []
+        for r in range(args.rounds):
+            wu = args.warmup if r == 0 else 2
+            plan.apply_shape(default)
+            td.append(time_launches(lambda: plan.eval(f, q), args.steps, wu, stream)[0])
+            plan.apply_shape(tuned)
+            te.append(time_launches(lambda: plan.eval(f, q), args.steps, wu, stream)[0])
+            t_g, per_g = time_launches(g.replay, args.steps, wu, stream)
+            tg.append(t_g)
+        res[prec].update(per=per_g, step=float(np.median(tg)), graph=g, eager_tuned=float(np.median(te)),
+                         eager_default=float(np.median(td)),
+                         rounds_ms={"graph": [t * 1e3 for t in tg], "eager_tuned": [t * 1e3 for t in te],
+                                    "eager_default": [t * 1e3 for t in td]})
 
     copy_calibration(args.calibrate_copy, dev)
 
@@ -840,7 +855,7 @@ def main() -> int:
                    "cells": cells, "N_v": f"{NN}x{NN}", "kernel": KERN, "M": MM,
                    "K_r": mix["info"]["K_r"],
                    "timed": "K back-to-back graph replays of one evaluation over all cells between two events, "
-                            "autotuned launch shape"},
+                            "autotuned launch shape; median of --rounds such runs"},
         "roofline": roof,
         "roofline_conventions": conv,
         "cpu_baseline": baseline_line(base, "cell-evals/s", f"first {ncpu} cells of the same workload"),
@@ -851,6 +866,7 @@ def main() -> int:
         "parity_cells": ncpu,
         "mass_defect_max": mix["mass"],
         "eager_ms": {"default_shape": mix["eager_default"] * 1e3, "tuned_shape": mix["eager_tuned"] * 1e3},
+        "rounds_ms": mix["rounds_ms"],
         "launch_shape": {"default": mix["default_shape"], "tuned": mix["tuned_shape"], "from": mix["tuned_from"]},
         "fp32_path": fp32_line,
         "speedup_vs_fp32": None if fp32 is None else fp32["step"] / T,
