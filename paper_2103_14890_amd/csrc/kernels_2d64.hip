@@ -29,13 +29,14 @@
 namespace qcoll {
 namespace {
 
-// LDS: four complex FP64 32x32 slots in [slot][register][lane] order (a lane's
-// 16-byte value for register v of slot s sits at (s * 16 + v) * 64 + lane), the
-// row-twiddle table [p1][k1'], a small reduction area, and per wavefront the
-// combined twiddle w^(k'.p) of each of its lane's modes (same [register][lane]
-// order), which is the same for every cell and filter.
+// LDS (79 KB, so that two cells' workgroups share a CU): four complex FP64
+// 32x32 slots in [slot][register][lane] order (a lane's 16-byte value for
+// register v of slot s sits at (s * 16 + v) * 64 + lane), the row-twiddle table
+// [p1][k1'], a small reduction area and the DFT-matrix table. A mode's twiddle
+// w^(k'.p) is formed where it is used, as the row twiddle (broadcast from the
+// table) times the lane's column twiddle.
 constexpr int kZSlot = 16 * 64;                      // complex values per slot
-constexpr int kLdsBytes = (4 * kZSlot + 2 * 32 + 8 * 4 + 4 * kZSlot) * 16 + kEoLdsBytes;
+constexpr int kLdsBytes = (4 * kZSlot + 2 * 32 + 8 * 4) * 16 + kEoLdsBytes;
 
 // 16-byte aligned, so that a lane's complex value is one ds_read_b128 /
 // ds_write_b128 (two 8-byte halves with a 16-byte lane stride conflict in
@@ -121,11 +122,10 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
   Cd* zs = reinterpret_cast<Cd*>(lds);                 // [4][16][64]
   Cd* tw = zs + 4 * kZSlot;                            // [2][32]
   double* red = reinterpret_cast<double*>(tw + 64);    // [4 waves][4]
-  Cd* twp = reinterpret_cast<Cd*>(red + 32) + (threadIdx.x >> 6) * kZSlot;  // this wave's [16][64]
-  half8* eo = reinterpret_cast<half8*>(reinterpret_cast<Cd*>(red + 32) + 4 * kZSlot);  // DFT lo parts
+  half8* eo = reinterpret_cast<half8*>(reinterpret_cast<Cd*>(red + 32));  // DFT lo parts
 
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (scalar registers)
   const int p1 = w >> 1, p2 = w & 1;                   // parity class = mode quarter
   const int h = lane >> 5, c = lane & 31;
   const int n = a.n, np = n >> 1;
@@ -134,8 +134,7 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
   for (int i = threadIdx.x; i < 64; i += blockDim.x) tw[i] = {a.tw[2 * i], a.tw[2 * i + 1]};
   const Cd c2 = {a.tw[2 * (32 * p2 + c)], a.tw[2 * (32 * p2 + c) + 1]};
   __syncthreads();
-#pragma unroll
-  for (int v = 0; v < 16; ++v) twp[v * 64 + lane] = cmul(tw[32 * p1 + rrow(v, h)], c2);
+  auto twv = [&](int v) { return cmul(tw[32 * p1 + rrow(v, h)], c2); };
 
   Lead E[3][2];
   E32 E3;
@@ -195,27 +194,32 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
     // ---- twiddle w^(-k'.p) and exchange: T_p -> f_hat quarter a = w
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const Cd t = twp[v * 64 + lane];
+      const Cd t = twv(v);
       const Cd F = {ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), sc),
                     ldexp(static_cast<double>(i0[v]) + static_cast<double>(i1[v]), sc)};
       zs[(w * 16 + v) * 64 + lane] = cmul({t.x, -t.y}, F);
     }
     __syncthreads();
-    double fr[16], fi[16];
+    {
+      Cd fq[16];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      double sr = 0.0, si = 0.0;
+      for (int v = 0; v < 16; ++v) {
+        double sr = 0.0, si = 0.0;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const Cd t = zs[(s * 16 + v) * 64 + lane];
-        sr += sgn[s] * t.x;
-        si += sgn[s] * t.y;
+        for (int s = 0; s < 4; ++s) {
+          const Cd t = zs[(s * 16 + v) * 64 + lane];
+          sr += sgn[s] * t.x;
+          si += sgn[s] * t.y;
+        }
+        fq[v] = {sr, si};
+        __builtin_amdgcn_sched_barrier(0);
       }
-      fr[v] = sr;
-      fi[v] = si;
-      __builtin_amdgcn_sched_barrier(0);
+      __syncthreads();
+      // The quarter f_hat_a lives in this wave's slot between transforms (the
+      // slot is free while the inverse passes run), not in registers.
+#pragma unroll
+      for (int v = 0; v < 16; ++v) zs[(w * 16 + v) * 64 + lane] = fq[v];
     }
-    __syncthreads();
 
     double gain[16];
 #pragma unroll
@@ -227,22 +231,31 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
     auto transform = [&](int q, auto gain_kind) {
       constexpr bool G = decltype(gain_kind)::value;
       // filtered quarter Z_a (true values) to LDS, with its max |component|
-      // filter values of this quarter: [q][quarter][register v][lane] complex
-      // (all 16 loads issued together: one exposed L2 latency per filter)
+      // filter values of this quarter: [q][quarter][register v][lane] complex,
+      // loaded in two batches of eight (the register budget of two workgroups
+      // per CU; the other workgroup covers the latency)
       const double2* mq = reinterpret_cast<const double2*>(a.filt) + (static_cast<int64_t>(q) * 4 + w) * kZSlot;
       int ml = lane;
       asm volatile("" : "+v"(ml));
+      constexpr int kMv = 8;
       double2 mvv[16];
 #pragma unroll
-      for (int v = 0; v < 16; ++v) mvv[v] = mq[v * 64 + ml];
+      for (int v = 0; v < kMv; ++v) mvv[v] = mq[v * 64 + ml];
       __builtin_amdgcn_sched_barrier(0);
       const double zsc = ldexp(1.0, a.filt_exp[q]);
       // (the maximum in FP64: true values can lie outside the FP32 range)
       double zm = 0.0;
+      Cd fq[16];   // f_hat_a, from this wave's slot, which then takes Z_a
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
+        if (v == kMv) {
+#pragma unroll
+          for (int u = kMv; u < 16; ++u) mvv[u] = mq[u * 64 + ml];
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        fq[v] = zs[(w * 16 + v) * 64 + lane];
         const double mr = mvv[v].x * zsc, mi = mvv[v].y * zsc;
-        const Cd z = {mr * fr[v] - mi * fi[v], mr * fi[v] + mi * fr[v]};
+        const Cd z = {mr * fq[v].x - mi * fq[v].y, mr * fq[v].y + mi * fq[v].x};
         zs[(w * 16 + v) * 64 + lane] = z;
         if (FX) zm = fmax(zm, fmax(fabs(z.x), fabs(z.y)));
         if (v & 1) __builtin_amdgcn_sched_barrier(0);
@@ -271,7 +284,7 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
             sr += sgn[s] * t.x;
             si += sgn[s] * t.y;
           }
-          const Cd g = cmul(twp[(v + u) * 64 + lane], {sr, si});
+          const Cd g = cmul(twv(v + u), {sr, si});
           gr[u] = FX ? ldexp(g.x, b) : g.x;
           gi[u] = FX ? ldexp(g.y, b) : g.y;
         }
@@ -287,6 +300,9 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
         __builtin_amdgcn_sched_barrier(0);  // bound the LDS reads in flight
       }
       __syncthreads();
+      // every wave has read the Z slots: f_hat_a back into this wave's slot
+#pragma unroll
+      for (int v = 0; v < 16; ++v) zs[(w * 16 + v) * 64 + lane] = fq[v];
       if constexpr (FX) {
         pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
         int sd = -b - 9;
@@ -417,6 +433,7 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
       const double nu = rho, k = a.dt_eps;
       const double cM = rho / (2.0 * 3.14159265358979323846 * Tm);
       const double den = 1.0 + Ai[l - 1] * k * nu;
+      const double* ec = exp_consts();
       int bad = 0;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
@@ -425,7 +442,7 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
         const int o = (2 * r + p1) * n + 2 * c + p2;
         const double v1 = -a.L + a.dv * (2 * r + p1);
         const double fnv = static_cast<double>(fnp[o]);
-        const double M = cM * exp(-((v1 - u1) * (v1 - u1) + (v2c - u2) * (v2c - u2)) / (2.0 * Tm));
+        const double M = cM * exp_nonpos(-((v1 - u1) * (v1 - u1) + (v2c - u2) * (v2c - u2)) / (2.0 * Tm), ec);
         double rhs = fnv + Ai[l - 1] * k * nu * M;
         for (int m = 1; m < l; ++m) {
           const double Fm = m == 1 ? fnv
@@ -490,13 +507,17 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
 }
 
 
+// Two workgroups (cells) per CU: at most 256 registers per lane, which with
+// the 79 KB of LDS lets the matrix work of one cell overlap the vector and LDS
+// work of the other.
+#define T64_BOUNDS __launch_bounds__(256, 2)
 template <int OUT>
-__global__ __launch_bounds__(256) void fx16_t64_kernel(KernelArgs a) {
+__global__ T64_BOUNDS void fx16_t64_kernel(KernelArgs a) {
   t64_body<OUT, true>(a);
 }
 
 template <int OUT>
-__global__ __launch_bounds__(256) void fp32_t64_kernel(KernelArgs a) {
+__global__ T64_BOUNDS void fp32_t64_kernel(KernelArgs a) {
   t64_body<OUT, false>(a);
 }
 
@@ -544,7 +565,7 @@ int launch_2d64(const KernelArgs& args, hipStream_t stream) {
   if (args.precision != 4 && args.precision != 1) return -4;
   int64_t blocks = args.cells;
   if (blocks > args.max_blocks) blocks = args.max_blocks;
-  // 135 KB of dynamic LDS, above the 64 KB default
+  // 79 KB of dynamic LDS, above the 64 KB default
   static const bool attr_ok = set_lds_attr<Fx16T64>() && set_lds_attr<Fp32T64>();
   if (!attr_ok) return -3;
   const dim3 grid(static_cast<unsigned>(blocks));

@@ -718,6 +718,7 @@ __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red
     const double tp = 2.0 * 3.14159265358979323846 * Tm;
     const double cM = rho / (tp * sqrt(tp));
     const double den = 1.0 + Ai[l - 1] * k * nu;
+    const double* ec = exp_consts();
     int bad = 0;
     for (int t = w; t < T; t += 4)
 #pragma unroll
@@ -727,7 +728,7 @@ __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red
         const int o = (t * n + r) * n + x;
         const double v0 = -a.L + a.dv * t, v1 = -a.L + a.dv * r, v2 = -a.L + a.dv * x;
         const double c2 = (v0 - u0) * (v0 - u0) + (v1 - u1) * (v1 - u1) + (v2 - u2) * (v2 - u2);
-        const double M = cM * exp(-c2 / (2.0 * Tm));
+        const double M = cM * exp_nonpos(-c2 / (2.0 * Tm), ec);
         const double fn = static_cast<double>(fnp[o]);
         double rhs = fn + Ai[l - 1] * k * nu * M;
         for (int m = 1; m < l; ++m) {

@@ -95,6 +95,38 @@ __constant__ double kRkA[2][5][5] = {
     {{0, 0, 0, 0, 0}, {0.5, 0.5, 0, 0, 0}, {5.0 / 18, -1.0 / 9, 0.5, 0, 0}, {0.5, 0, 0, 0.5, 0},
      {0.25, 0, 0.75, -0.5, 0.5}}};
 
+// exp(x) for x <= 0 in FP64 (the Maxwellian of the stage updates): x = k ln 2
+// + r with k = rint(x / ln 2) and |r| <= ln(2) / 2 (ln 2 in two parts, so that r
+// is exact to a few units of 2^-60), exp(r) from its Taylor series to degree 13
+// (truncation error below 2^-60 on that interval) in Horner form, times 2^k.
+// NaN stays NaN; results below the subnormal range are 0. The constants come
+// from the table c (kExpConst): read in the epilogue of each cell, they do not
+// occupy registers through the transform loops, as immediate constants
+// hoisted out of the cell loop would.
+#define QCOLL_EXP_CONSTANTS                                                                                    \
+  {1.4426950408889634074, 6.93147180369123816490e-01, 1.90821492927058770002e-10, 1.0, 1.0, 0.5, 1.0 / 6.0, \
+   1.0 / 24.0, 1.0 / 120.0, 1.0 / 720.0, 1.0 / 5040.0, 1.0 / 40320.0, 1.0 / 362880.0, 1.0 / 3628800.0,      \
+   1.0 / 39916800.0, 1.0 / 479001600.0, 1.0 / 6227020800.0}
+__constant__ double kExpConst[17] = QCOLL_EXP_CONSTANTS;
+
+__host__ __device__ __forceinline__ double exp_nonpos(double x, const double* c) {
+  if (!(x > -745.2)) return x != x ? x : 0.0;
+  const double k = __builtin_rint(x * c[0]);
+  double r = __builtin_fma(-k, c[1], x);   // ln 2, high part
+  r = __builtin_fma(-k, c[2], r);          // ln 2, low part
+  double p = c[16];                         // 1/13!
+#pragma unroll
+  for (int i = 15; i >= 3; --i) p = __builtin_fma(p, r, c[i]);
+  return __builtin_ldexp(p, static_cast<int>(k));
+}
+
+// The table of exp_nonpos behind an opaque pointer, taken once per cell.
+__device__ __forceinline__ const double* exp_consts() {
+  const double* c = kExpConst;
+  asm volatile("" : "+s"(c));
+  return c;
+}
+
 // Store Q, or apply the conservation projection (FP64 moments, wave
 // reductions) and store Q as double, or apply the stage update to f.
 template <int OUT, class LY>
@@ -202,6 +234,7 @@ __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, 
     const double nu = rho, k = a.dt_eps;
     const double cM = rho / (2.0 * 3.14159265358979323846 * T);
     const double den = 1.0 + Ai[l - 1] * k * nu;
+    const double* ec = exp_consts();
     int bad = 0;
 #pragma unroll
     for (int v = 0; v < kV; ++v) {
@@ -210,7 +243,7 @@ __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, 
       const int o = r * n + c;
       const double fnv = static_cast<double>(fnp[o]);
       const double v1 = -a.L + a.dv * r;
-      const double M = cM * exp(-((v1 - u1) * (v1 - u1) + (v2c - u2) * (v2c - u2)) / (2.0 * T));
+      const double M = cM * exp_nonpos(-((v1 - u1) * (v1 - u1) + (v2c - u2) * (v2c - u2)) / (2.0 * T), ec);
       double rhs = fnv + Ai[l - 1] * k * nu * M;
       for (int m = 1; m < l; ++m) {
         const double Fm = m == 1 ? fnv
