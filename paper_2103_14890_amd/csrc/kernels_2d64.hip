@@ -200,25 +200,30 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
       zs[(w * 16 + v) * 64 + lane] = cmul({t.x, -t.y}, F);
     }
     __syncthreads();
-    {
-      Cd fq[16];
+    // This wave's spectrum quarter f_hat_a: in registers through the filter
+    // loop (16 of them spill, two values per lane reloaded once per transform),
+    // or, in the stage kernel, whose epilogue needs more registers, in the
+    // wave's exchange slot between transforms (the slot is free while the
+    // inverse passes run). Each form measured the faster for its kernel.
+    constexpr bool kStash = OUT == 3;
+    double fr[16], fi[16];
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        double sr = 0.0, si = 0.0;
+    for (int v = 0; v < 16; ++v) {
+      double sr = 0.0, si = 0.0;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const Cd t = zs[(s * 16 + v) * 64 + lane];
-          sr += sgn[s] * t.x;
-          si += sgn[s] * t.y;
-        }
-        fq[v] = {sr, si};
-        __builtin_amdgcn_sched_barrier(0);
+      for (int s = 0; s < 4; ++s) {
+        const Cd t = zs[(s * 16 + v) * 64 + lane];
+        sr += sgn[s] * t.x;
+        si += sgn[s] * t.y;
       }
-      __syncthreads();
-      // The quarter f_hat_a lives in this wave's slot between transforms (the
-      // slot is free while the inverse passes run), not in registers.
+      fr[v] = sr;
+      fi[v] = si;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+    if constexpr (kStash) {
 #pragma unroll
-      for (int v = 0; v < 16; ++v) zs[(w * 16 + v) * 64 + lane] = fq[v];
+      for (int v = 0; v < 16; ++v) zs[(w * 16 + v) * 64 + lane] = {fr[v], fi[v]};
     }
 
     double gain[16];
@@ -245,7 +250,7 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
       const double zsc = ldexp(1.0, a.filt_exp[q]);
       // (the maximum in FP64: true values can lie outside the FP32 range)
       double zm = 0.0;
-      Cd fq[16];   // f_hat_a, from this wave's slot, which then takes Z_a
+      Cd fq[16];   // f_hat_a (stage kernel: from this wave's slot, which then takes Z_a)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         if (v == kMv) {
@@ -253,7 +258,7 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
           for (int u = kMv; u < 16; ++u) mvv[u] = mq[u * 64 + ml];
           __builtin_amdgcn_sched_barrier(0);
         }
-        fq[v] = zs[(w * 16 + v) * 64 + lane];
+        fq[v] = kStash ? zs[(w * 16 + v) * 64 + lane] : Cd{fr[v], fi[v]};
         const double mr = mvv[v].x * zsc, mi = mvv[v].y * zsc;
         const Cd z = {mr * fq[v].x - mi * fq[v].y, mr * fq[v].y + mi * fq[v].x};
         zs[(w * 16 + v) * 64 + lane] = z;
@@ -300,9 +305,11 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
         __builtin_amdgcn_sched_barrier(0);  // bound the LDS reads in flight
       }
       __syncthreads();
-      // every wave has read the Z slots: f_hat_a back into this wave's slot
+      if constexpr (kStash) {
+        // every wave has read the Z slots: f_hat_a back into this wave's slot
 #pragma unroll
-      for (int v = 0; v < 16; ++v) zs[(w * 16 + v) * 64 + lane] = fq[v];
+        for (int v = 0; v < 16; ++v) zs[(w * 16 + v) * 64 + lane] = fq[v];
+      }
       if constexpr (FX) {
         pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
         int sd = -b - 9;
