@@ -200,12 +200,11 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
       zs[(w * 16 + v) * 64 + lane] = cmul({t.x, -t.y}, F);
     }
     __syncthreads();
-    // This wave's spectrum quarter f_hat_a: in registers through the filter
-    // loop (16 of them spill, two values per lane reloaded once per transform),
-    // or, in the stage kernel, whose epilogue needs more registers, in the
-    // wave's exchange slot between transforms (the slot is free while the
-    // inverse passes run). Each form measured the faster for its kernel.
-    constexpr bool kStash = OUT == 3;
+    // This wave's spectrum quarter f_hat_a lives in the wave's exchange slot
+    // between transforms (the slot is free while the inverse passes run), not
+    // in registers: held in registers it spilled 16 VGPRs per lane, whose
+    // scratch traffic went to HBM (2.8x the algorithmic bytes per launch, for a
+    // launch 3% shorter).
     double fr[16], fi[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -221,10 +220,8 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
       __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
-    if constexpr (kStash) {
 #pragma unroll
-      for (int v = 0; v < 16; ++v) zs[(w * 16 + v) * 64 + lane] = {fr[v], fi[v]};
-    }
+    for (int v = 0; v < 16; ++v) zs[(w * 16 + v) * 64 + lane] = {fr[v], fi[v]};
 
     double gain[16];
 #pragma unroll
@@ -250,7 +247,7 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
       const double zsc = ldexp(1.0, a.filt_exp[q]);
       // (the maximum in FP64: true values can lie outside the FP32 range)
       double zm = 0.0;
-      Cd fq[16];   // f_hat_a (stage kernel: from this wave's slot, which then takes Z_a)
+      Cd fq[16];   // f_hat_a, from this wave's slot, which then takes Z_a
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         if (v == kMv) {
@@ -258,7 +255,7 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
           for (int u = kMv; u < 16; ++u) mvv[u] = mq[u * 64 + ml];
           __builtin_amdgcn_sched_barrier(0);
         }
-        fq[v] = kStash ? zs[(w * 16 + v) * 64 + lane] : Cd{fr[v], fi[v]};
+        fq[v] = zs[(w * 16 + v) * 64 + lane];
         const double mr = mvv[v].x * zsc, mi = mvv[v].y * zsc;
         const Cd z = {mr * fq[v].x - mi * fq[v].y, mr * fq[v].y + mi * fq[v].x};
         zs[(w * 16 + v) * 64 + lane] = z;
@@ -305,11 +302,9 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a) {
         __builtin_amdgcn_sched_barrier(0);  // bound the LDS reads in flight
       }
       __syncthreads();
-      if constexpr (kStash) {
-        // every wave has read the Z slots: f_hat_a back into this wave's slot
+      // every wave has read the Z slots: f_hat_a back into this wave's slot
 #pragma unroll
-        for (int v = 0; v < 16; ++v) zs[(w * 16 + v) * 64 + lane] = fq[v];
-      }
+      for (int v = 0; v < 16; ++v) zs[(w * 16 + v) * 64 + lane] = fq[v];
       if constexpr (FX) {
         pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
         int sd = -b - 9;
