@@ -225,17 +225,18 @@ int qcoll_step_rk_noalloc(qcoll_plan_t plan, float* f, int64_t cells, double dt,
  * (or status[i]) and cells[i] exactly as the single-plan call; each cell's
  * result is bitwise equal to the single-plan launch. nplans <= 64, all plans
  * on one device; slots with cells[i] == 0 are skipped. status may be NULL.
- * 2D plans with N <= 32 share one launch per 8 such slots; 2D plans with
- * N > 32 (a workgroup per cell) get one launch each; 3D plans (all slots 3D)
- * share one launch per 8 slots. When a 2D call has several launches and few
- * cells (at most four per compute unit in total, as in a serving tick) they
- * run concurrently, the first on `stream` and the others on up to three side
+ * 2D plans share one launch per 8 slots (N <= 32: a wavefront per cell; N > 32:
+ * a workgroup per cell); 3D plans (all slots 3D) share one launch per 8 slots.
+ * When a 2D call has several launches (more than 8 slots) and few cells (at
+ * most four per compute unit in total, as in a serving tick) they run
+ * concurrently, the first on `stream` and the others on up to three side
  * streams of the library (default priority) that wait for `stream` before
  * they start and that `stream` waits for afterwards, so the call as a whole is
  * ordered on `stream`; larger calls, and calls while `stream` is being
- * captured into a graph, queue the launches on `stream` one after another. 2D and 3D plans cannot be mixed in
- * one call (QCOLL_EUNSUPPORTED). 3D plans hold a scratch area: calls that use
- * the same 3D plan must not run concurrently on different streams. */
+ * captured into a graph, queue the launches on `stream` one after another. 2D
+ * and 3D plans cannot be mixed in one call (QCOLL_EUNSUPPORTED). 3D plans hold
+ * a scratch area: calls that use the same 3D plan must not run concurrently on
+ * different streams (qcoll_eval_ws takes a workspace of the caller's). */
 int qcoll_eval_multi(const qcoll_plan_t* plans, int nplans, const float* const* f, void* const* Q,
                      const int64_t* cells, hipStream_t stream);
 int qcoll_step_multi(const qcoll_plan_t* plans, int nplans, float* const* f, const int64_t* cells, double dt,

@@ -978,27 +978,23 @@ static ForkJoin* fork_join(int dev) {
   return &pool[dev];
 }
 
-// One launch of a batched 2D call: a tile-64 plan (a workgroup per cell) or a
-// slot table of plans with N <= 32.
+// One launch of a batched 2D call: a slot table of up to kMaxSlots plans (N <= 32
+// tiles, a wavefront per cell; tile-64 plans, a workgroup per cell).
 struct MultiJob {
-  bool tile64 = false;
-  qcoll::KernelArgs a;
   qcoll::MultiArgs m;
 };
 
-// Run the launches of a batched call. They write disjoint outputs, so when
-// there are several and the batch is small (`concurrent`: too few cells to
-// fill the GPU with one launch at a time, as in a serving tick) they run
-// concurrently: the first on the caller's stream, the others on side streams
-// that wait for the caller's stream and are waited for by it (so the call is
-// still ordered on the caller's stream as a whole). Large batches run one
-// launch after another (measured: 3 x 2048 cells of 16^2..32^2 plus 2048 of
-// 64^2 take 1.31 ms concurrently and 1.15 ms in sequence; with 8 cells per
-// plan 0.13 ms concurrently against 0.19 ms), and so does a call while the
-// stream is being captured into a graph.
+// Run the launches of a batched call (more than one only when the call holds
+// more plans than a slot table). They write disjoint outputs, so when there are
+// several and the batch is small (`concurrent`: too few cells to fill the GPU
+// with one launch at a time, as in a serving tick) they run concurrently: the
+// first on the caller's stream, the others on side streams that wait for the
+// caller's stream and are waited for by it (so the call is still ordered on the
+// caller's stream as a whole). Large batches run one launch after another, and
+// so does a call while the stream is being captured into a graph.
 static int run_jobs(const std::vector<MultiJob>& jobs, int wpb, int dev, bool concurrent, hipStream_t stream) {
   auto run = [&](const MultiJob& j, hipStream_t s) {
-    return j.tile64 ? qcoll::launch_2d64(j.a, s) : qcoll::launch_multi(j.m, wpb, s);
+    return qcoll::launch_multi(j.m, wpb, s);
   };
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   const bool fork = concurrent && jobs.size() > 1 && hipStreamIsCapturing(stream, &cs) == hipSuccess &&
@@ -1112,12 +1108,6 @@ static int multi_launch(const qcoll_plan_t* plans, int nplans, const float* cons
       a.q = Q[i];
       a.out_kind = (p->flags & QCOLL_CONSERVE) ? 1 : 0;
     }
-    if (p->tile == 64) {  // one workgroup per cell: a launch of its own
-      jobs.emplace_back();
-      jobs.back().tile64 = true;
-      jobs.back().a = a;
-      continue;
-    }
     if (m.nslots == qcoll::kMaxSlots) {  // slot table full: queue it and start the next
       m.block_start[m.nslots] = blocks;
       jobs.emplace_back();
@@ -1127,7 +1117,7 @@ static int multi_launch(const qcoll_plan_t* plans, int nplans, const float* cons
     }
     m.slot[m.nslots] = a;
     m.block_start[m.nslots] = blocks;
-    blocks += (cells[i] + wpb - 1) / wpb;
+    blocks += p->tile == 64 ? cells[i] : (cells[i] + wpb - 1) / wpb;   // tile 64: one workgroup per cell
     ++m.nslots;
   }
   m.block_start[m.nslots] = blocks;

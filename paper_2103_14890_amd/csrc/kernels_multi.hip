@@ -3,7 +3,9 @@
 // so every cell runs exactly the code of its single-plan launch and the
 // results are bitwise equal to separate launches. Workgroups are assigned to
 // slots by contiguous ranges; a workgroup finds its slot with a short scan of
-// the slot table (at most kMaxSlots entries) and then walks its slot's cells.
+// the slot table (at most kMaxSlots entries) and then walks its slot's cells:
+// one cell per wavefront on 16x16 and 32x32 tiles, one cell per workgroup of
+// four wavefronts on the 64-point grids (the tile-64 body).
 
 #include <hip/hip_runtime.h>
 
@@ -11,6 +13,7 @@
 
 #include "body_t16.hpp"
 #include "body_t32.hpp"
+#include "body_t64.hpp"
 
 namespace qcoll {
 namespace {
@@ -22,6 +25,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
 #pragma unroll 1
   while (s + 1 < m.nslots && b >= m.block_start[s + 1]) ++s;
   const KernelArgs& a = m.slot[s];
+  if (a.tile == 64) {  // one cell per workgroup (launched with four wavefronts per workgroup)
+    const int64_t first = b - m.block_start[s], stride = m.block_start[s + 1] - m.block_start[s];
+    if (a.precision == 4) t64_body<-1, true>(a, first, stride, lds);
+    else t64_body<-1, false>(a, first, stride, lds);
+    return;
+  }
   const int wpb = blockDim.x >> 6;
   const int64_t first = (b - m.block_start[s]) * wpb + (threadIdx.x >> 6);
   const int64_t stride = (m.block_start[s + 1] - m.block_start[s]) * wpb;
@@ -43,13 +52,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
 int launch_multi(const MultiArgs& args, int waves_per_block, hipStream_t stream) {
   const int64_t blocks = args.block_start[args.nslots];
   if (blocks <= 0) return 0;
-  static const bool attr_ok = [] {  // dynamic LDS above the 64 KB default (4 waves: 70 KB)
+  bool t64 = false;
+  for (int i = 0; i < args.nslots; ++i) t64 |= args.slot[i].tile == 64;
+  if (t64 && waves_per_block != 4) return -4;   // the tile-64 body needs four wavefronts per workgroup
+  // dynamic LDS above the 64 KB default: 76 KB for four wavefronts of N <= 32
+  // cells, 79 KB for a tile-64 cell
+  constexpr int kMaxLds = kT64LdsBytes > kEoLdsBytes + 4 * kFhatLdsBytes ? kT64LdsBytes
+                                                                          : kEoLdsBytes + 4 * kFhatLdsBytes;
+  static const bool attr_ok = [] {
     return hipFuncSetAttribute(reinterpret_cast<const void*>(multi_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               kEoLdsBytes + 4 * kFhatLdsBytes) == hipSuccess;
+                               kMaxLds) == hipSuccess;
   }();
   if (!attr_ok) return -3;
-  hipLaunchKernelGGL(multi_kernel, dim3(static_cast<unsigned>(blocks)), dim3(64 * waves_per_block),
-                     kEoLdsBytes + kFhatLdsBytes * waves_per_block, stream, args);
+  const int lds = t64 ? kMaxLds : kEoLdsBytes + kFhatLdsBytes * waves_per_block;
+  hipLaunchKernelGGL(multi_kernel, dim3(static_cast<unsigned>(blocks)), dim3(64 * waves_per_block), lds, stream,
+                     args);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

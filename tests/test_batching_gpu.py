@@ -49,11 +49,14 @@ def test_eval_multi_bitwise_equals_single_launches(qc):
 
 
 def test_concurrent_launches_stay_ordered_on_the_callers_stream(qc):
-    """Six launches in one call (five tile-64 plans and one slot table) run on
-    the caller's stream and side streams; work queued on the caller's stream
-    after the call (no host synchronisation in between) sees every result."""
+    """Two launches in one call (ten slots: a full slot table of eight, tile-64
+    and N <= 32 plans mixed, and a second table) run on the caller's stream and
+    a side stream; work queued on the caller's stream after the call (no host
+    synchronisation in between) sees every result."""
     cfg = [(64, 8.0, "hard_sphere", 8, 3), (48, 8.0, "maxwell", 8, 2), (64, 10.0, "maxwell", 16, 2),
-           (40, 8.0, "hard_sphere", 8, 1), (48, 6.0, "hard_sphere", 8, 3), (32, 8.0, "hard_sphere", 8, 70)]
+           (40, 8.0, "hard_sphere", 8, 1), (48, 6.0, "hard_sphere", 8, 3), (32, 8.0, "hard_sphere", 8, 70),
+           (16, 8.0, "maxwell", 16, 5), (24, 8.0, "hard_sphere", 8, 4), (64, 8.0, "hard_sphere", 8, 2),
+           (20, 8.0, "maxwell", 8, 6)]
     plans, fs = [], []
     for i, (N, L, kern, M, cells) in enumerate(cfg):
         plans.append(qc.Plan(2, N, L, kern, M, precision="fx16"))
