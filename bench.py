@@ -314,15 +314,16 @@ def copy_calibration(mib: int, dev) -> None:
 
 
 def serve_run(seconds: float, rate: float = 200.0, warm: float = 2.0, budget_bytes: int = 256 << 20,
-              seed: int = 1003) -> dict:
+              seed: int = 1003, split: bool = True) -> dict:
     """Open-loop serving of homogeneous relaxation requests (continuous batching):
     Poisson arrivals, N in {16, 24, 32, 48, 64}, Maxwell or hard spheres, 50-400
     explicit Euler steps of dt = 0.01, admission within an HBM budget; latencies
-    of requests arriving in the first `warm` seconds are discarded."""
+    of requests arriving in the first `warm` seconds are discarded; `split`
+    lets groups with few live cells run in the transform split form."""
     from paper_2103_14890_amd import serving as sv
     reqs = sv.poisson_requests(int(seconds * rate), rate=rate, seed=seed, L=8.0)
     server = sv.Server(L=8.0, M=8, precision="fx16", dt=0.01, eps=1.0, scheme="explicit",
-                       budget_bytes=budget_bytes)
+                       budget_bytes=budget_bytes, split=split)
     stats = server.run(reqs, realtime=True)
     kept = [r for r in server.results.values() if not r.failed and r.arrival >= warm]
     lat = np.array([r.latency for r in kept])
@@ -334,7 +335,8 @@ def serve_run(seconds: float, rate: float = 200.0, warm: float = 2.0, budget_byt
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "throughput_req_s": stats["throughput_req_s"], "cell_steps_s": stats["cell_steps_s"],
             "ticks": stats["ticks"], "wall_s": stats["wall_s"], "discarded_first_s": warm,
-            "mix": "N in {16,24,32,48,64}, Maxwell/hard spheres, 50-400 steps, M=8, FX16"}
+            "mix": "N in {16,24,32,48,64}, Maxwell/hard spheres, 50-400 steps, M=8, FX16",
+            "transform_split": split}
 
 
 def bench_3d(args) -> int:
@@ -701,6 +703,8 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="length of the open-loop serving run (Poisson arrivals at 200 requests/s, 256 MB "
                          "budget) behind p99_latency_ms; 0 skips it and the stress run")
+    ap.add_argument("--serve-split", choices=["on", "off"], default="on",
+                    help="transform split form for serving groups with few live cells")
     ap.add_argument("--stress-seconds", type=float, default=10.0,
                     help="length of each serving run under a small budget (1 MB, then 128 KB)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -790,10 +794,11 @@ def main() -> int:
 
     serve = stress = tight = None
     if args.serve_seconds > 0 and NN == 32:   # the serving runs belong to the headline line
-        serve = serve_run(args.serve_seconds)
-        stress = serve_run(args.stress_seconds, budget_bytes=1 << 20, seed=1013)
+        sp_ = args.serve_split == "on"
+        serve = serve_run(args.serve_seconds, split=sp_)
+        stress = serve_run(args.stress_seconds, budget_bytes=1 << 20, seed=1013, split=sp_)
         # a budget below the live footprint of this arrival rate, so that admission queues
-        tight = serve_run(args.stress_seconds, budget_bytes=128 << 10, seed=1023)
+        tight = serve_run(args.stress_seconds, budget_bytes=128 << 10, seed=1023, split=sp_)
 
     # time steps of the homogeneous relaxation on the same cells (FX16 plan
     # without projection): single-stage IMEX Euler (one launch) and the

@@ -263,6 +263,28 @@ int qcoll_plan_get_launch(qcoll_plan_t plan, int* waves_per_block, int64_t* max_
 int qcoll_plan_set_tile(qcoll_plan_t plan, int tile);
 int qcoll_plan_get_tile(qcoll_plan_t plan, int* tile, int* alternate);
 
+/* Transform split (latency form for small batches; the operator of section 3.3
+ * is a sum over the plan's transforms, so a cell's transforms can be shared out):
+ *   1  default: one wavefront (N <= 32) or one workgroup (N > 32) per cell;
+ *   4  FX16 plans on the 32x32 tile: a workgroup of four wavefronts per cell,
+ *      each wavefront taking every fourth transform, the partial sums added in
+ *      LDS in a fixed order;
+ *   2, 4, 8, 16  tile-64 plans (FX16 or FP32): that many workgroups per cell, the
+ *      partial sums added in a fixed order by the workgroup that finishes last
+ *      (through device buffers the plan allocates on first use, sized for the
+ *      largest batch seen: split x 32 KiB per cell, plus a counter per cell).
+ * Other values, and split factors a plan's kernels lack, return QCOLL_EINVAL;
+ * selecting a tile family without the current factor resets it to 1. The
+ * split form applies to qcoll_eval, qcoll_step and the batched calls (the
+ * qcoll_step_rk family ignores it). Results differ from the unsplit ones by
+ * the order of the gain sum only (within the precision's parity bounds) and
+ * are deterministic. A first call on more cells than the buffers hold grows
+ * them, which synchronises the stream and returns QCOLL_EINVAL under graph
+ * capture; calls that use the same split tile-64 plan must not run concurrently
+ * on different streams. */
+int qcoll_plan_set_split(qcoll_plan_t plan, int split);
+int qcoll_plan_get_split(qcoll_plan_t plan, int* split);
+
 /* Autotuner: times every launch shape on the caller's f (device, cells cells)
  * with HIP events, `reps` launches each, and keeps the fastest in the plan:
  * tile family (see qcoll_plan_set_tile) x cells per workgroup (1, 2, 4, and 8

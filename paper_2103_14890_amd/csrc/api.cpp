@@ -2,6 +2,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -57,6 +58,13 @@ struct qcoll_plan_s {
   int64_t max_blocks = 0;    // grid cap of single-plan launches
   int waves_per_block = 4;   // cells per workgroup
   int cus = 256;
+  // transform split (qcoll_plan_set_split) and, for tile-64 plans, the parts'
+  // results and arrival counters (grown on demand, split_cap cells)
+  int split = 1;
+  double* split_ws = nullptr;
+  int* split_cnt = nullptr;
+  int64_t split_cap = 0;   // cells the buffers hold ...
+  int split_alloc = 0;     // ... at this split factor
 };
 
 namespace {
@@ -106,6 +114,12 @@ void free_device(qcoll_plan_s* p) {
   hipFree(p->gal_interp);
   hipFree(p->gal_restrict);
   p->gal_interp = p->gal_restrict = nullptr;
+  hipFree(p->split_ws);
+  hipFree(p->split_cnt);
+  p->split_ws = nullptr;
+  p->split_cnt = nullptr;
+  p->split_cap = 0;
+  p->split_alloc = 0;
   hipFree(p->cl_betaT);
   hipFree(p->cl_tw);
   p->cl_betaT = p->cl_tw = nullptr;
@@ -563,6 +577,9 @@ qcoll::KernelArgs make_args(const qcoll_plan_s* p) {
   a.tile = p->tile;
   a.tw = p->tw;
   a.precision = p->precision;
+  a.split = p->split;
+  a.split_ws = p->split_ws;
+  a.split_cnt = p->split_cnt;
   return a;
 }
 
@@ -742,6 +759,10 @@ int qcoll_plan_vhs(qcoll_plan_t* out, int n_per_dim, double L, double gamma, dou
   return plan_create_nothrow(out, 2, n_per_dim, L, QCOLL_VHS, gamma, b, M, K_r, precision, flags);
 }
 
+static int multi_launch(const qcoll_plan_t* plans, int nplans, const float* const* f, void* const* Q,
+                        const int64_t* cells, bool step, double dt, double eps, int scheme,
+                        int32_t* const* status, hipStream_t stream);
+
 static int eval_impl(qcoll_plan_t p, const float* f, void* Q, int64_t cells, char* ws, int64_t ws_bytes,
                      hipStream_t stream) {
   if (!p || cells < 0) return QCOLL_EINVAL;
@@ -772,6 +793,10 @@ static int eval_impl(qcoll_plan_t p, const float* f, void* Q, int64_t cells, cha
     const qcoll_plan_s* pl = p;
     return launch3(&pl, &s3, 1, &cells, stream, ws, ws_bytes) ? QCOLL_EDEVICE : QCOLL_OK;
   }
+  if (p->split > 1) {   // the split form runs in the batched kernel
+    qcoll_plan_t pl = p;
+    return multi_launch(&pl, 1, &f, &Q, &cells, false, 0.0, 0.0, 0, nullptr, stream);
+  }
   qcoll::KernelArgs a = make_args(p);
   a.f = f;
   a.q = Q;
@@ -801,6 +826,11 @@ static int step_impl(qcoll_plan_t p, float* f, int64_t cells, double dt, double 
     s3.out_kind = 2;
     const qcoll_plan_s* pl = p;
     return launch3(&pl, &s3, 1, &cells, stream, ws, ws_bytes) ? QCOLL_EDEVICE : QCOLL_OK;
+  }
+  if (p->split > 1) {   // the split form runs in the batched kernel
+    qcoll_plan_t pl = p;
+    const float* fc = f;
+    return multi_launch(&pl, 1, &fc, nullptr, &cells, true, dt, eps, scheme, &status, stream);
   }
   qcoll::KernelArgs a = make_args(p);
   a.f = f;
@@ -1042,6 +1072,45 @@ static int run_jobs(const std::vector<MultiJob>& jobs, int wpb, int dev, bool co
   return rc;
 }
 
+// Room in a tile-64 plan's split buffers for `cells` cells (grown on demand: the
+// parts' results and the arrival counters, zeroed here; the kernels leave them
+// zero). Growing waits for the stream (the old buffers may be in use) and is
+// refused while the stream is being captured into a graph.
+static int ensure_split_ws(qcoll_plan_s* p, int64_t cells, hipStream_t stream) {
+  if (p->split <= 1 || p->tile != 64 || (cells <= p->split_cap && p->split <= p->split_alloc)) return QCOLL_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return QCOLL_EDEVICE;
+  if (cs != hipStreamCaptureStatusNone) return QCOLL_EINVAL;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return QCOLL_EDEVICE;
+  if (cur != p->device && hipSetDevice(p->device) != hipSuccess) return QCOLL_EDEVICE;
+  int rc = QCOLL_OK;
+  if (hipStreamSynchronize(stream) != hipSuccess) rc = QCOLL_EDEVICE;
+  if (rc == QCOLL_OK) {
+    hipFree(p->split_ws);
+    hipFree(p->split_cnt);
+    p->split_ws = nullptr;
+    p->split_cnt = nullptr;
+    p->split_cap = 0;
+    const int64_t cap = std::max<int64_t>(cells, 64);
+    const size_t ws_bytes = static_cast<size_t>(cap) * p->split * 4 * 1024 * sizeof(double);
+    if (hipMalloc(reinterpret_cast<void**>(&p->split_ws), ws_bytes) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&p->split_cnt), cap * sizeof(int)) != hipSuccess) {
+      hipFree(p->split_ws);
+      p->split_ws = nullptr;
+      p->split_cnt = nullptr;
+      rc = QCOLL_ENOMEM;
+    } else if (hipMemsetAsync(p->split_cnt, 0, cap * sizeof(int), stream) != hipSuccess) {   // not captured (above)
+      rc = QCOLL_EDEVICE;
+    } else {
+      p->split_cap = cap;
+      p->split_alloc = p->split;
+    }
+  }
+  if (cur != p->device) hipSetDevice(cur);
+  return rc;
+}
+
 // Shared by qcoll_eval_multi and qcoll_step_multi: validate the slot list and
 // build the batched launch (one workgroup per waves_per_block cells of a slot).
 static int multi_launch(const qcoll_plan_t* plans, int nplans, const float* const* f, void* const* Q,
@@ -1092,11 +1161,31 @@ static int multi_launch(const qcoll_plan_t* plans, int nplans, const float* cons
     if (ns == 0) return QCOLL_OK;
     return launch3(pl, sl, ns, cs, stream) ? QCOLL_EDEVICE : QCOLL_OK;
   }
+  // tile-64 plans in the split form: every slot of a plan takes its own range of
+  // the plan's split buffers (a plan may fill several slots of one launch)
+  std::vector<std::pair<qcoll_plan_s*, int64_t>> split_use;
+  for (int i = 0; i < nplans; ++i) {
+    qcoll_plan_s* p = plans[i];
+    if (p->split <= 1 || p->tile != 64 || cells[i] == 0) continue;
+    auto it = std::find_if(split_use.begin(), split_use.end(), [p](const auto& u) { return u.first == p; });
+    if (it == split_use.end()) split_use.emplace_back(p, cells[i]);
+    else it->second += cells[i];
+  }
+  for (auto& u : split_use) {
+    if (int rc = ensure_split_ws(u.first, u.second, stream)) return rc;
+    u.second = 0;   // from here on: the next free cell of the plan's buffers
+  }
   std::vector<MultiJob> jobs;
   for (int i = 0; i < nplans; ++i) {
     if (cells[i] == 0) continue;
-    const qcoll_plan_s* p = plans[i];
+    qcoll_plan_s* p = plans[i];
     qcoll::KernelArgs a = make_args(p);
+    if (p->split > 1 && p->tile == 64) {
+      auto it = std::find_if(split_use.begin(), split_use.end(), [p](const auto& u) { return u.first == p; });
+      a.split_ws = p->split_ws + it->second * p->split * 4 * 1024;
+      a.split_cnt = p->split_cnt + it->second;
+      it->second += cells[i];
+    }
     a.f = f[i];
     a.cells = cells[i];
     if (step) {
@@ -1117,7 +1206,9 @@ static int multi_launch(const qcoll_plan_t* plans, int nplans, const float* cons
     }
     m.slot[m.nslots] = a;
     m.block_start[m.nslots] = blocks;
-    blocks += p->tile == 64 ? cells[i] : (cells[i] + wpb - 1) / wpb;   // tile 64: one workgroup per cell
+    // tile 64: one workgroup per cell, or per part of a cell in the split form;
+    // N <= 32: one wavefront per cell, or one workgroup per cell in the split form
+    blocks += p->tile == 64 ? cells[i] * p->split : (p->split > 1 ? cells[i] : (cells[i] + wpb - 1) / wpb);
     ++m.nslots;
   }
   m.block_start[m.nslots] = blocks;
@@ -1151,6 +1242,8 @@ int qcoll_step_multi(const qcoll_plan_t* plans, int nplans, float* const* f, con
   }
 }
 
+static bool split_ok(const qcoll_plan_s* p, int split);
+
 // Eight wavefronts per workgroup select the ping-pong variant of the FX16
 // 32x32 kernel (two wavefronts per SIMD in alternating matrix/vector phases).
 static bool pingpong_ok(const qcoll_plan_s* p) {
@@ -1181,6 +1274,29 @@ int qcoll_plan_set_tile(qcoll_plan_t p, int tile) {
   if (!p->on_device || tile != p->alt_tile || p->alt_tile == 0) return QCOLL_EINVAL;
   swap_tile_tables(p);
   if (p->waves_per_block == 8 && !pingpong_ok(p)) p->waves_per_block = 4;
+  if (!split_ok(p, p->split)) p->split = 1;
+  return QCOLL_OK;
+}
+
+// Split factors a plan's kernels support: 4 (a workgroup of four wavefronts per
+// cell) for FX16 32x32 tiles; 2, 4, 8 or 16 workgroups per cell for tile-64 plans.
+static bool split_ok(const qcoll_plan_s* p, int split) {
+  if (split == 1) return true;
+  if (!p->on_device || p->hp.d != 2 || p->classical || p->galerkin) return false;
+  if (p->tile == 32) return split == 4 && p->precision == QCOLL_MIX_FX16;
+  if (p->tile == 64) return split == 2 || split == 4 || split == 8 || split == 16;
+  return false;
+}
+
+int qcoll_plan_set_split(qcoll_plan_t p, int split) {
+  if (!p || !split_ok(p, split)) return QCOLL_EINVAL;
+  p->split = split;
+  return QCOLL_OK;
+}
+
+int qcoll_plan_get_split(qcoll_plan_t p, int* split) {
+  if (!p || !split) return QCOLL_EINVAL;
+  *split = p->split;
   return QCOLL_OK;
 }
 
@@ -1260,7 +1376,8 @@ int qcoll_plan_info(qcoll_plan_t p, int* transforms, int* K_r, double* R, int64_
   if (transforms) *transforms = static_cast<int>(p->hp.packed.size()) + 1;
   if (K_r) *K_r = p->hp.K_r;
   if (R) *R = p->hp.R;
-  if (device_bytes) *device_bytes = p->device_bytes;
+  if (device_bytes)   // tables, plus the split buffers when allocated
+    *device_bytes = p->device_bytes + p->split_cap * (static_cast<int64_t>(p->split_alloc) * 4 * 1024 * 8 + 4);
   return QCOLL_OK;
 }
 

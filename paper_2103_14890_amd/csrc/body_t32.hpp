@@ -176,10 +176,21 @@ constexpr int kEoLdsBytes = 2 * kEoHiOffset * 16;
 // lives in LDS (`fh`, this wavefront's kFhatLdsBytes), the filters stream from
 // L2 in mode pairs, and per transform the phases run in order: split of the
 // filtered spectrum, inverse pass A, slicing, inverse pass B, gain.
-template <int OUT>  // OUT: 0 eval float, 1 eval double (projection), 2 step, -1 from a.out_kind
+//
+// SPLIT (latency form, one cell per workgroup of four wavefronts): the four
+// wavefronts compute the spectrum each, then share the cell's transforms
+// (wavefront w takes the gain transforms q = w, w + 4, ...; the one with
+// w = P mod 4 also the loss), and wavefront 0 sums the four partial results in
+// a fixed order from LDS and runs the epilogue. first and stride then count
+// cells per workgroup; fh is this wavefront's region of four consecutive ones.
+template <int OUT, bool SPLIT = false>  // OUT: 0 eval float, 1 eval double (projection), 2 step, -1 from a.out_kind
 __device__ __forceinline__ void fx16_t32_body(const KernelArgs& a, int64_t first, int64_t stride, double2* fh,
                                               const half8* eo) {
   const int lane = threadIdx.x & 63;
+  const int wv = SPLIT ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;   // wavefront of the cell
+  const int q0 = SPLIT ? (wv < a.P ? wv : a.P) : 0;   // first transform (clamped: a valid table entry)
+  constexpr int qs = SPLIT ? 4 : 1;                   // transform step
+  const bool own_loss = !SPLIT || wv == a.P % 4;
 
   // DFT-matrix operands (Er, Ei, -Ei; two K-slices; lead and hi per lane; the
   // lo parts in the LDS table eo).
@@ -259,10 +270,11 @@ __device__ __forceinline__ void fx16_t32_body(const KernelArgs& a, int64_t first
       double2 mv[16];
       const unsigned l16 = opaque_lane16(lane);
 #pragma unroll
-      for (int v = 0; v < 16; ++v) mv[v] = load_filter_value(a.filt, 0, v, l16);
+      for (int v = 0; v < 16; ++v) mv[v] = load_filter_value(a.filt, q0, v, l16);
       filtered_split(mv, fh, lane, A);
     }
-    for (int q = 0; q < a.P; ++q) {
+    for (int q = (SPLIT ? wv : 0); q < a.P; q += qs) {
+      const int qn = q + qs < a.P ? q + qs : a.P;   // next transform of this wavefront (or the loss entry)
       // inverse pass A (contraction over the first axis)
       pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
       const int a2 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
@@ -276,7 +288,7 @@ __device__ __forceinline__ void fx16_t32_body(const KernelArgs& a, int64_t first
       double2 mv[16];
       const unsigned l16 = opaque_lane16(lane);
 #pragma unroll
-      for (int v = 0; v < 8; ++v) mv[v] = load_filter_value(a.filt, q + 1, v, l16);
+      for (int v = 0; v < 8; ++v) mv[v] = load_filter_value(a.filt, qn, v, l16);
       __builtin_amdgcn_sched_barrier(0);
       const double w = ldexp(1.0, 2 * sd);
 #pragma unroll
@@ -287,25 +299,47 @@ __device__ __forceinline__ void fx16_t32_body(const KernelArgs& a, int64_t first
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int v = 8; v < 16; ++v) mv[v] = load_filter_value(a.filt, q + 1, v, l16);
+      for (int v = 8; v < 16; ++v) mv[v] = load_filter_value(a.filt, qn, v, l16);
       __builtin_amdgcn_sched_barrier(0);
       filtered_split(mv, fh, lane, A);
     }
-    // the loss transform (entry P): only the real part of pass B is needed
-    pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
-    const int a2l = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
-    slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a2l), A);
-    pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, false, r0, r1, i0, i1);
-    const int sd_loss = a.filt_exp[a.P] + s_fh - 9 - a2l - 9;
-    // the last transform is the loss field: Q = gain - f * loss
     float fv[16];
-    load_cell<Lay32>(a, cell, lane, fv);
+    if (own_loss) {   // wavefront-uniform
+      // the loss transform (entry P): only the real part of pass B is needed
+      pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
+      const int a2l = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
+      slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a2l), A);
+      pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, false, r0, r1, i0, i1);
+      const int sd_loss = a.filt_exp[a.P] + s_fh - 9 - a2l - 9;
+      // the last transform is the loss field: Q = gain - f * loss
+      load_cell<Lay32>(a, cell, lane, fv);
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const double lf = ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), sd_loss);
-      gain[v] = gain[v] - static_cast<double>(fv[v]) * lf;
+      for (int v = 0; v < 16; ++v) {
+        const double lf = ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), sd_loss);
+        gain[v] = gain[v] - static_cast<double>(fv[v]) * lf;
+      }
     }
-    finish_cell<OUT, Lay32>(a, cell, fv, gain, lane);
+    if constexpr (SPLIT) {
+      // partial results through LDS (each wavefront's spectrum region, free
+      // now); wavefront 0 adds them in the order 0, 1, 2, 3
+      double* part = reinterpret_cast<double*>(fh);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) part[v * 64 + lane] = gain[v];
+      __syncthreads();
+      if (wv == 0) {
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+          const double* other = reinterpret_cast<const double*>(fh + k * (kFhatLdsBytes / 16));
+#pragma unroll
+          for (int v = 0; v < 16; ++v) gain[v] += other[v * 64 + lane];
+        }
+        load_cell<Lay32>(a, cell, lane, fv);
+        finish_cell<OUT, Lay32>(a, cell, fv, gain, lane);
+      }
+      __syncthreads();   // the regions are rewritten by the next cell's spectrum
+    } else {
+      finish_cell<OUT, Lay32>(a, cell, fv, gain, lane);
+    }
   }
 }
 

@@ -122,7 +122,14 @@ __device__ __forceinline__ void inv_fp32(const E32& E, const float* zr, const fl
 // double without projection; -1 chosen at run time from a.out_kind among 0..2
 // (the batched launches). Cells first, first + stride, ...; lds_raw is the
 // workgroup's kT64LdsBytes of dynamic LDS (16-byte aligned).
-template <int OUT, bool FX>
+//
+// SPLIT (the latency form of batched launches): a.split workgroups share each
+// cell: work item i is part i % a.split of cell i / a.split; every part computes
+// the spectrum, part j the gain transforms q = j, j + a.split, ... and the part
+// P mod a.split the loss; the parts leave their results in a.split_ws and count
+// their arrivals in a.split_cnt; the last to arrive adds the parts in the order
+// 0, 1, ... and runs the epilogue (first and stride then count work items).
+template <int OUT, bool FX, bool SPLIT = false>
 __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int64_t stride, double2* lds_raw) {
   const int kind = OUT < 0 ? a.out_kind : OUT;
   auto can = [](int k) { return OUT == k || (OUT < 0 && k <= 2); };
@@ -167,7 +174,10 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int
   }
   const double sgn[4] = {1.0, (p2 ? -1.0 : 1.0), (p1 ? -1.0 : 1.0), ((p1 ^ p2) ? -1.0 : 1.0)};
 
-  for (int64_t cell = first; cell < a.cells; cell += stride) {
+  const int S = SPLIT ? a.split : 1;
+  for (int64_t item = first; item < a.cells * S; item += stride) {
+    const int64_t cell = SPLIT ? item / S : item;
+    const int part = SPLIT ? static_cast<int>(item - cell * S) : 0;
     // ---- own parity sub-grid x[m1][m2] = f[2 m1 + p1][2 m2 + p2]
     float fv[16];
     load_subgrid(a, cell, p1, p2, fv);
@@ -339,14 +349,38 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int
         }
       }
     };
-    for (int q = 0; q < a.P; ++q) transform(q, std::true_type{});
-    transform(a.P, std::false_type{});
+    for (int q = part; q < a.P; q += S) transform(q, std::true_type{});
+    const bool own_loss = !SPLIT || part == a.P % S;   // workgroup-uniform
+    if (own_loss) transform(a.P, std::false_type{});
     load_subgrid(a, cell, p1, p2, fv);  // re-read: not kept live through the filter loop
+    if (own_loss) {
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const double lf = FX ? ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), sd_last)
-                           : static_cast<double>(r0[v]);
-      gain[v] -= static_cast<double>(fv[v]) * lf;
+      for (int v = 0; v < 16; ++v) {
+        const double lf = FX ? ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), sd_last)
+                             : static_cast<double>(r0[v]);
+        gain[v] -= static_cast<double>(fv[v]) * lf;
+      }
+    }
+    if constexpr (SPLIT) {
+      double* mine = a.split_ws + ((cell * S + part) * 4 + w) * 1024;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) mine[v * 64 + lane] = gain[v];
+      __threadfence();   // the part is visible device-wide before it is counted
+      __syncthreads();
+      if (threadIdx.x == 0) red[20] = atomicAdd(&a.split_cnt[cell], 1) == S - 1 ? 1.0 : 0.0;
+      __syncthreads();
+      const bool last = red[20] != 0.0;
+      __syncthreads();   // red is reused by the epilogue
+      if (!last) continue;
+      __threadfence();   // the other parts' results are read after their counts
+#pragma unroll
+      for (int v = 0; v < 16; ++v) gain[v] = 0.0;
+      for (int j = 0; j < S; ++j) {
+        const double* pj = a.split_ws + ((cell * S + j) * 4 + w) * 1024;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) gain[v] += pj[v * 64 + lane];
+      }
+      if (threadIdx.x == 0) a.split_cnt[cell] = 0;   // zero for the next launch
     }
 
     // ---- epilogue on this wave's parity class; cell-wide sums through LDS.

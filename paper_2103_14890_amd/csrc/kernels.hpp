@@ -38,8 +38,17 @@ struct KernelArgs {
   int64_t rk_stride = 0;
   int rk_scheme = 0;
   int rk_stage = 0;
-  int tile = 32;                // MFMA tile of the kernel: 16 or 32
+  int tile = 32;                // MFMA tile of the kernel: 16, 32 or 64
   int precision = 4;            // 1 FP32, 4 FX16
+  // Transform split (the latency form of batched launches): 1, or the number of
+  // workers that share a cell's transforms (32x32 FX16 tiles: 4 wavefronts of
+  // one workgroup; tile 64: 2 or 4 workgroups, which leave their partial
+  // results in split_ws, [cell][part][wavefront][16][64] doubles, and count
+  // their arrivals in split_cnt[cell], zero between launches: the last to
+  // arrive adds the parts in a fixed order and runs the epilogue).
+  int split = 1;
+  double* split_ws = nullptr;
+  int* split_cnt = nullptr;
   int waves_per_block = 4;      // launch shape (1, 2 or 4 wavefronts, one cell each)
   int64_t max_blocks = 1 << 20; // grid cap; waves loop over cells beyond it
 };

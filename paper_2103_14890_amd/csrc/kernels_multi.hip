@@ -25,10 +25,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
 #pragma unroll 1
   while (s + 1 < m.nslots && b >= m.block_start[s + 1]) ++s;
   const KernelArgs& a = m.slot[s];
-  if (a.tile == 64) {  // one cell per workgroup (launched with four wavefronts per workgroup)
+  if (a.tile == 64) {  // one cell (or one part of one, in the split form) per workgroup of four wavefronts
     const int64_t first = b - m.block_start[s], stride = m.block_start[s + 1] - m.block_start[s];
-    if (a.precision == 4) t64_body<-1, true>(a, first, stride, lds);
-    else t64_body<-1, false>(a, first, stride, lds);
+    if (a.split > 1) {
+      if (a.precision == 4) t64_body<-1, true, true>(a, first, stride, lds);
+      else t64_body<-1, false, true>(a, first, stride, lds);
+    } else {
+      if (a.precision == 4) t64_body<-1, true>(a, first, stride, lds);
+      else t64_body<-1, false>(a, first, stride, lds);
+    }
+    return;
+  }
+  if (a.split > 1) {  // 32x32 FX16 tiles, one cell per workgroup of four wavefronts sharing its transforms
+    half8* eo = reinterpret_cast<half8*>(lds);
+    load_eo_table(a, eo);
+    fx16_t32_body<-1, true>(a, b - m.block_start[s], m.block_start[s + 1] - m.block_start[s],
+                            lds + (kEoLdsBytes + (threadIdx.x >> 6) * kFhatLdsBytes) / 16, eo);
     return;
   }
   const int wpb = blockDim.x >> 6;

@@ -95,6 +95,10 @@ def _load() -> ctypes.CDLL:
     lib.qcoll_plan_set_tile.restype = c_int
     lib.qcoll_plan_get_tile.argtypes = [vp, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
     lib.qcoll_plan_get_tile.restype = c_int
+    lib.qcoll_plan_set_split.argtypes = [vp, c_int]
+    lib.qcoll_plan_set_split.restype = c_int
+    lib.qcoll_plan_get_split.argtypes = [vp, ctypes.POINTER(c_int)]
+    lib.qcoll_plan_get_split.restype = c_int
     lib.qcoll_plan_autotune.argtypes = [vp, vp, vp, i64, c_int, vp]
     lib.qcoll_plan_autotune.restype = c_int
     lib.qcoll_plan_destroy.argtypes = [vp]
@@ -322,6 +326,15 @@ class Plan:
 
     def set_tile(self, tile: int) -> None:
         _check(LIB.qcoll_plan_set_tile(self._h, int(tile)), "qcoll_plan_set_tile")
+
+    def split(self) -> int:
+        """Transform split factor (see qcoll_plan_set_split)."""
+        s = ctypes.c_int()
+        _check(LIB.qcoll_plan_get_split(self._h, ctypes.byref(s)), "qcoll_plan_get_split")
+        return s.value
+
+    def set_split(self, split: int) -> None:
+        _check(LIB.qcoll_plan_set_split(self._h, int(split)), "qcoll_plan_set_split")
 
     def shape(self) -> dict:
         """The launch shape the autotuner chooses among."""

@@ -21,7 +21,14 @@ by side on one GPU:
     waiting ones; the host work of tick k + 1 overlaps the device work of
     tick k (flags and results are read one tick later);
   * faults: a cell whose update became non-finite is flagged by the kernel
-    and evicted without affecting the others.
+    and evicted without affecting the others;
+  * small groups: a group with few live cells runs in the transform split form
+    (qcoll_plan_set_split: a cell's transforms shared by several wavefronts or
+    workgroups), so a tick over a few large-grid requests fills more of the GPU.
+    The split factor follows the group's size, and it changes the order of a
+    step's FP64 gain sum, so a request's result may then differ from that of a
+    lone run in the last FP32 bits; Server(split=False) keeps every result
+    independent of what ran beside it, bitwise.
 
 Latency is completion time minus arrival time on the host monotonic clock.
 All device work is done by the HIP library through the binding.
@@ -74,12 +81,31 @@ class _Group:
 
     def __init__(self, plan: qcoll.Plan, N: int, device):
         self.plan, self.N, self.device = plan, N, device
+        self.tile = plan.tile()[0]
+        self.fx16 = plan.precision == "fx16"
+        self.split = 1
         self.cap = 0
         self.buf = None
         self.pool = None
         self.status = None
         self.live: list[int] = []          # request id of slot i
         self.left: list[int] = []          # steps remaining for slot i
+
+    def set_split_for(self, cells: int) -> None:
+        """Split factor for a step over `cells` cells, from measured step times
+        of lone groups: a tile-64 cell (one workgroup unsplit) runs as 8 parts
+        up to 8 cells, 4 up to 48 and 2 up to 112 (beyond that the chip is
+        full enough unsplit); a 32x32 FX16 cell (one wavefront unsplit) runs as
+        a workgroup of four wavefronts up to 640 cells."""
+        if self.tile == 64:
+            s = 8 if cells <= 8 else (4 if cells <= 48 else (2 if cells <= 112 else 1))
+        elif self.tile == 32 and self.fx16:
+            s = 4 if cells <= 640 else 1
+        else:
+            s = 1
+        if s != self.split:
+            self.plan.set_split(s)
+            self.split = s
 
     @staticmethod
     def footprint(N: int, cap: int) -> int:
@@ -112,9 +138,10 @@ class Server:
 
     def __init__(self, L: float = 8.0, M: int = 8, precision: str = "fx16", dt: float = 0.01,
                  eps: float = 1.0, scheme: str = "explicit", budget_bytes: int = 256 << 20,
-                 max_slots: int = 1 << 16, device=None):
+                 max_slots: int = 1 << 16, device=None, split: bool = True):
         import torch
         self.L, self.M, self.precision = L, M, precision
+        self.split = split                 # transform split for groups with few live cells
         self.dt, self.eps, self.scheme = dt, eps, scheme
         self.budget = int(budget_bytes)
         self.max_slots = max_slots
@@ -209,6 +236,9 @@ class Server:
         groups = [g for g in self.groups.values() if g.live]
         new = None
         if groups:
+            if self.split:
+                for g in groups:
+                    g.set_split_for(len(g.live))
             plans = [g.plan for g in groups]
             fs = [g.pool[:len(g.live)] for g in groups]
             st = [g.status[:len(g.live)] for g in groups]

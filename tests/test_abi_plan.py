@@ -138,6 +138,14 @@ def test_multi_and_tuning_argument_checks():
     assert qc.LIB.qcoll_plan_set_tile(None, 16) == qc.EINVAL
     assert p.tile()[1] == 0
     assert qc.LIB.qcoll_plan_autotune(p._h, None, None, 4, 1, None) == qc.EINVAL
+    # the transform split exists only for device plans with the kernels for it
+    assert p.split() == 1
+    p.set_split(1)
+    for bad in (0, 2, 3, 4, 8, -1):
+        assert qc.LIB.qcoll_plan_set_split(p._h, bad) == qc.EINVAL
+    assert p.split() == 1
+    assert qc.LIB.qcoll_plan_set_split(None, 1) == qc.EINVAL
+    assert qc.LIB.qcoll_plan_get_split(p._h, None) == qc.EINVAL
     p.close()
 
 

@@ -15,8 +15,8 @@ def sv():
     return serving
 
 
-def _alone(sv, req):
-    s = sv.Server()
+def _alone(sv, req, split=True):
+    s = sv.Server(split=split)
     alone = sv.Request(req.rid, req.N, req.kernel, req.steps, req.f0, 0.0)
     s.run([alone], realtime=False)
     out = s.results[req.rid].f
@@ -24,14 +24,22 @@ def _alone(sv, req):
     return out
 
 
-def test_each_result_same_alone_and_in_mix(sv):
+@pytest.mark.parametrize("split", [False, True])
+def test_each_result_same_alone_and_in_mix(sv, split):
+    """Unsplit, a request's result does not depend on what it ran beside,
+    bitwise. With the transform split (its factor follows the group sizes) the
+    FP64 gain sums of a step may run in another order: equal to FP32 rounding."""
     reqs = sv.poisson_requests(40, rate=2000.0, seed=5, steps=(5, 30))
-    s = sv.Server()
+    s = sv.Server(split=split)
     stats = s.run(reqs, realtime=True)
     assert stats["requests"] == 40 and stats["failed"] == 0
     assert stats["p99_latency_s"] >= stats["p50_latency_s"] > 0
     for r in reqs[:: 7]:
-        assert np.array_equal(s.results[r.rid].f, _alone(sv, r)), r.rid
+        a, b = s.results[r.rid].f, _alone(sv, r, split)
+        if split:
+            assert np.abs(a - b).max() <= 1e-6 * np.abs(b).max(), r.rid
+        else:
+            assert np.array_equal(a, b), r.rid
     # work really overlapped: fewer ticks than the sum of steps
     assert stats["ticks"] < sum(r.steps for r in reqs)
     s.close()
