@@ -312,7 +312,7 @@ __device__ __forceinline__ void fx16_t32_body(const KernelArgs& a, int64_t first
       pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, false, r0, r1, i0, i1);
       const int sd_loss = a.filt_exp[a.P] + s_fh - 9 - a2l - 9;
       // the last transform is the loss field: Q = gain - f * loss
-      load_cell<Lay32>(a, cell, lane, fv);
+      load_cell<Lay32>(a, cell, lane, fv, r0[0]);
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const double lf = ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), sd_loss);
@@ -333,7 +333,7 @@ __device__ __forceinline__ void fx16_t32_body(const KernelArgs& a, int64_t first
 #pragma unroll
           for (int v = 0; v < 16; ++v) gain[v] += other[v * 64 + lane];
         }
-        load_cell<Lay32>(a, cell, lane, fv);
+        load_cell<Lay32>(a, cell, lane, fv, static_cast<float>(gain[0]));
         finish_cell<OUT, Lay32>(a, cell, fv, gain, lane);
       }
       __syncthreads();   // the regions are rewritten by the next cell's spectrum
@@ -489,7 +489,7 @@ __device__ __forceinline__ void fx16_t32_body_pp(const KernelArgs& a, int64_t fi
     // [vector] epilogue: Q = gain - f * loss
     {
       float fv[16];
-      load_cell<Lay32>(a, cell, lane, fv);
+      load_cell<Lay32>(a, cell, lane, fv, r0[0]);
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const double lf = ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), sd_loss);
@@ -593,7 +593,7 @@ __device__ __forceinline__ void fp32_t32_body(const KernelArgs& a, int64_t first
     };
     for (int q = 0; q < a.P; ++q) transform(q, std::true_type{});
     transform(a.P, std::false_type{});
-    finish_cell<OUT, Lay32>(a, cell, fv, gain, lane);
+    finish_cell<OUT, Lay32, 2>(a, cell, fv, gain, lane);   // FP32 operands hold more registers
   }
 }
 

@@ -62,7 +62,7 @@ __device__ __forceinline__ void load_subgrid(const KernelArgs& a, int64_t cell, 
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     const int r = rrow(v, h);
-    fv[v] = (r < np && c < np) ? fc[(2 * r + p1) * n + 2 * c + p2] : 0.0f;
+    fv[v] = load_or_zero(fc, r < np && c < np, (2 * r + p1) * n + 2 * c + p2);
   }
 }
 

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void f
 }
 
 template <int OUT>
-__global__ __launch_bounds__(256) void fp32_t32_kernel(KernelArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fp32_t32_kernel(KernelArgs a) {
   const int wpb = blockDim.x >> 6;
   fp32_t32_body<OUT>(a, static_cast<int64_t>(blockIdx.x) * wpb + (threadIdx.x >> 6),
                  static_cast<int64_t>(gridDim.x) * wpb);

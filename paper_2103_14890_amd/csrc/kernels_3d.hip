@@ -472,7 +472,7 @@ __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red
 #pragma unroll
         for (int s = 0; s < S::NS; ++s) {
           const int j = S::KS * s + jl;
-          xr[s] = (t < n && x < n && j < n) ? fc[(t * n + x) * n + j] : 0.0f;
+          xr[s] = load_or_zero(fc, t < n && x < n && j < n, (t * n + x) * n + j);
           xi[s] = 0.0f;
           fsum += static_cast<double>(xr[s]);
         }

@@ -120,6 +120,15 @@ __host__ __device__ __forceinline__ double exp_nonpos(double x, const double* c)
   return __builtin_ldexp(p, static_cast<int>(k));
 }
 
+// p[idx] where `in`, else 0, without a branch: lanes outside the grid read
+// element 0 of the same cell (always present) and drop it. A conditional load
+// becomes an exec-masked block of its own, and the compiler then waits for each
+// load before the next block; unconditional loads of a row issue back to back.
+__device__ __forceinline__ float load_or_zero(const float* p, bool in, int idx) {
+  const float x = p[in ? idx : 0];
+  return in ? x : 0.0f;
+}
+
 // The table of exp_nonpos behind an opaque pointer, taken once per cell.
 __device__ __forceinline__ const double* exp_consts() {
   const double* c = kExpConst;
@@ -129,20 +138,20 @@ __device__ __forceinline__ const double* exp_consts() {
 
 // Store Q, or apply the conservation projection (FP64 moments, wave
 // reductions) and store Q as double, or apply the stage update to f.
-template <int OUT, class LY>
+// RG: rows per group of the stage update's loads (register budget of the caller).
+template <int OUT, class LY, int RG = 4>
 __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, double* q, int lane) {
-  if constexpr (OUT < 0) {  // epilogue chosen at run time (batched launches)
+  if constexpr (OUT < 0) {  // epilogue chosen at run time (batched launches: eval, projection, step)
     if (a.out_kind == 0) finish_cell<0, LY>(a, cell, fv, q, lane);
     else if (a.out_kind == 1) finish_cell<1, LY>(a, cell, fv, q, lane);
-    else if (a.out_kind == 2) finish_cell<2, LY>(a, cell, fv, q, lane);
-    else if (a.out_kind == 3) finish_cell<3, LY>(a, cell, fv, q, lane);
-    else finish_cell<4, LY>(a, cell, fv, q, lane);
+    else finish_cell<2, LY>(a, cell, fv, q, lane);
     return;
   }
   // The velocities and addresses below are the same for every cell; an opaque
-  // lane index keeps the compiler from hoisting them out of the cell loop,
-  // where they would occupy registers through the whole filter loop.
-  asm volatile("" : "+v"(lane));
+  // lane index, which depends on the cell's result, keeps the compiler from
+  // hoisting them (and the epilogue's loads) out of the cell loop or ahead of
+  // the transform loop, where they would occupy registers through it.
+  asm volatile("" : "+v"(lane) : "v"(q[0]));
   constexpr int kV = LY::V;
   const int n = a.n;
   const int c = LY::col(lane);
@@ -211,15 +220,17 @@ __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, 
     const double* At = kRkAt[sch][l - 1];
     const double* Ai = kRkA[sch][l - 1];
     float* fnp = a.rk_fn + base;
-    // f^n is read twice (moments, then the update; the second read hits the
-    // cache) instead of being held in registers through the stage sums
-    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    // the loads of each phase are unconditional (out-of-grid lanes read element
+    // 0 and drop it), so that they issue together: f^n for the moments, then
+    // per group of rows f^n again (a cache hit; not held in registers) and the
+    // earlier stages' values and Q
     const double v2c = -a.L + a.dv * c;
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
 #pragma unroll
     for (int v = 0; v < kV; ++v) {
       const int r = LY::row(v, lane);
-      const double fnv = (r < n && c < n) ? static_cast<double>(fnp[r * n + c]) : 0.0;
-      const double v1 = -a.L + a.dv * r;
+      const double fnv = static_cast<double>(load_or_zero(fnp, r < n && c < n, r * n + c));
+      const double v1 = -a.L + a.dv * LY::row(v, lane);
       s0 += fnv;
       s1 += v1 * fnv;
       s2 += v2c * fnv;
@@ -236,34 +247,66 @@ __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, 
     const double den = 1.0 + Ai[l - 1] * k * nu;
     const double* ec = exp_consts();
     int bad = 0;
+    // four rows at a time: the slot loads of the earlier stages for these rows
+    // issue together (up to 2 stage values and 3 Q values per row), then the
+    // update of each row in the order of the scheme's sums
+    constexpr int kC = kV < RG ? kV : RG;
+    double chain = q[0];   // the loads of a group wait for the previous group's update
 #pragma unroll
-    for (int v = 0; v < kV; ++v) {
-      const int r = LY::row(v, lane);
-      if (!(r < n && c < n)) continue;
-      const int o = r * n + c;
-      const double fnv = static_cast<double>(fnp[o]);
-      const double v1 = -a.L + a.dv * r;
-      const double M = cM * exp_nonpos(-((v1 - u1) * (v1 - u1) + (v2c - u2) * (v2c - u2)) / (2.0 * T), ec);
-      double rhs = fnv + Ai[l - 1] * k * nu * M;
-      for (int m = 1; m < l; ++m) {
-        const double Fm = m == 1 ? fnv
-                          : (m == l - 1 ? static_cast<double>(fv[v])
-                                        : static_cast<double>(a.rk_work[(m - 2) * a.rk_stride + base + o]));
-        const double Sm = nu * (M - Fm);
-        double acc = Ai[m - 1] * Sm;
-        if (At[m - 1] != 0.0) {
-          const double Qm = m == l - 1 ? q[v] : static_cast<double>(a.rk_work[(S - 3 + m) * a.rk_stride + base + o]);
-          acc += At[m - 1] * (Qm - Sm);
-        }
-        rhs += k * acc;
+    for (int v0 = 0; v0 < kV; v0 += kC) {
+      float Fs[4][kC], Qs[4][kC];   // [m - 1][row]: F_m (m >= 2) and Q_m of stages m < l - 1
+      float fn[kC];
+      int cc = c;
+      asm volatile("" : "+v"(cc) : "v"(chain));   // else all groups' loads are hoisted together
+#pragma unroll
+      for (int j = 0; j < kC; ++j) {
+        const int r = LY::row(v0 + j, lane);
+        fn[j] = load_or_zero(fnp, r < n && cc < n, r * n + cc);
       }
-      const float Fl = static_cast<float>(rhs / den);
-      if (l == S) {
-        bad |= !(fabsf(Fl) <= 3.0e38f);
-        fnp[o] = Fl;
-      } else {
-        a.rk_work[(l - 2) * a.rk_stride + base + o] = Fl;
-        a.rk_work[(S - 3 + (l - 1)) * a.rk_stride + base + o] = static_cast<float>(q[v]);
+#pragma unroll
+      for (int m = 1; m <= 4; ++m) {
+        if (m >= l - 1) break;       // wave-uniform
+        const float* Fp = a.rk_work + (m - 2) * a.rk_stride + base;
+        const float* Qp = a.rk_work + (S - 3 + m) * a.rk_stride + base;
+#pragma unroll
+        for (int j = 0; j < kC; ++j) {
+          const int r = LY::row(v0 + j, lane);
+          const bool in = r < n && cc < n;
+          if (m >= 2) Fs[m - 1][j] = load_or_zero(Fp, in, r * n + cc);
+          Qs[m - 1][j] = load_or_zero(Qp, in, r * n + cc);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kC; ++j) {
+        const int v = v0 + j;
+        const int r = LY::row(v, lane);
+        const double v1 = -a.L + a.dv * r;
+        const double fnv = static_cast<double>(fn[j]);
+        const double M = cM * exp_nonpos(-((v1 - u1) * (v1 - u1) + (v2c - u2) * (v2c - u2)) / (2.0 * T), ec);
+        double rhs = fnv + Ai[l - 1] * k * nu * M;
+#pragma unroll
+        for (int m = 1; m <= 4; ++m) {
+          if (m >= l) break;
+          const double Fm = m == 1 ? fnv : (m == l - 1 ? static_cast<double>(fv[v]) : static_cast<double>(Fs[m - 1][j]));
+          const double Sm = nu * (M - Fm);
+          double acc = Ai[m - 1] * Sm;
+          if (At[m - 1] != 0.0) {
+            const double Qm = m == l - 1 ? q[v] : static_cast<double>(Qs[m - 1][j]);
+            acc += At[m - 1] * (Qm - Sm);
+          }
+          rhs += k * acc;
+        }
+        chain = rhs;
+        if (!(r < n && c < n)) continue;
+        const int o = r * n + c;
+        const float Fl = static_cast<float>(rhs / den);
+        if (l == S) {
+          bad |= !(fabsf(Fl) <= 3.0e38f);
+          fnp[o] = Fl;
+        } else {
+          a.rk_work[(l - 2) * a.rk_stride + base + o] = Fl;
+          a.rk_work[(S - 3 + (l - 1)) * a.rk_stride + base + o] = static_cast<float>(q[v]);
+        }
       }
     }
     if (l == S && a.status) {
@@ -296,15 +339,18 @@ __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, 
 }
 
 // Load one cell's n x n field into a register layout, zero outside the grid.
+// `after`: a value computed just before the reload (a loads issued after the
+// transform loops must not move ahead of them, where f would be held live).
 template <class LY>
-__device__ __forceinline__ void load_cell(const KernelArgs& a, int64_t cell, int lane, float* fv) {
-  asm volatile("" : "+v"(lane));  // per-cell addresses, not hoisted (as in finish_cell)
+__device__ __forceinline__ void load_cell(const KernelArgs& a, int64_t cell, int lane, float* fv,
+                                          float after = 0.0f) {
+  asm volatile("" : "+v"(lane) : "v"(after));  // per-cell addresses, not hoisted (as in finish_cell)
   const int n = a.n, c = LY::col(lane);
   const float* fc = a.f + cell * static_cast<int64_t>(n) * n;
 #pragma unroll
   for (int v = 0; v < LY::V; ++v) {
     const int r = LY::row(v, lane);
-    fv[v] = (r < n && c < n) ? fc[r * n + c] : 0.0f;
+    fv[v] = load_or_zero(fc, r < n && c < n, r * n + c);
   }
 }
 
