@@ -262,9 +262,13 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int
 #pragma unroll
       for (int v = 0; v < kMv; ++v) mvv[v] = mq[v * 64 + ml];
       __builtin_amdgcn_sched_barrier(0);
-      const double zsc = ldexp(1.0, a.filt_exp[q]);
-      // (the maximum in FP64: true values can lie outside the FP32 range)
-      double zm = 0.0;
+      // FX16: Z_a is kept as filter mantissas times the spectrum (the filter's
+      // power of two 2^filt_exp[q] goes into the slicing scale below, exactly);
+      // FP32: true values. The maximum |component| comes from the high words of
+      // the doubles: as FP32 bit patterns with the sign cleared they order like
+      // the magnitudes (true values can lie outside the FP32 range)
+      const double zsc = FX ? 1.0 : ldexp(1.0, a.filt_exp[q]);
+      float zmh = 0.0f;
       Cd fq[16];   // f_hat_a, from this wave's slot, which then takes Z_a
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
@@ -274,15 +278,19 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int
           __builtin_amdgcn_sched_barrier(0);
         }
         fq[v] = zs[(w * 16 + v) * 64 + lane];
-        const double mr = mvv[v].x * zsc, mi = mvv[v].y * zsc;
+        const double mr = FX ? mvv[v].x : mvv[v].x * zsc, mi = FX ? mvv[v].y : mvv[v].y * zsc;
         const Cd z = {mr * fq[v].x - mi * fq[v].y, mr * fq[v].y + mi * fq[v].x};
         zs[(w * 16 + v) * 64 + lane] = z;
-        if (FX) zm = fmax(zm, fmax(fabs(z.x), fabs(z.y)));
+        if (FX)   // one v_max3_f32 with |.| operand modifiers (in C the abs becomes an integer and)
+          asm("v_max3_f32 %0, |%1|, |%2|, %3"
+              : "=v"(zmh)
+              : "v"(__double2hiint(z.x)), "v"(__double2hiint(z.y)), "v"(zmh));
         if (v & 1) __builtin_amdgcn_sched_barrier(0);
       }
       if constexpr (FX) {
-        zm = wave_max_d(zm);
-        if (lane == 0) red[w * 4 + 3] = zm;
+        // an upper bound of the wave's maximum (the high word rounded up)
+        const int hb = __float_as_int(wave_max(zmh));
+        if (lane == 0) red[w * 4 + 3] = hb > 0 ? __hiloint2double(hb + 1, 0) : 0.0;
       }
       __syncthreads();
       // |G_p| <= sum_a max |Z_a| (twiddles have modulus one): common slicing scale
@@ -325,7 +333,7 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int
       for (int v = 0; v < 16; ++v) zs[(w * 16 + v) * 64 + lane] = fq[v];
       if constexpr (FX) {
         pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
-        int sd = -b - 9;
+        int sd = a.filt_exp[q] - b - 9;   // Z_a carried the filter mantissas
         const int a2 = 9 - exp_above(tile_absmax(r0, r1, i0, i1));
         slice_tiles(r0, r1, i0, i1, ldexpf(1.0f, a2), A);
         pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, G, r0, r1, i0, i1);  // loss: real part only
