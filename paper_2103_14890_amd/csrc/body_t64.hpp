@@ -299,6 +299,8 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int
       // G_p = w^(k'.p) sum_a (-1)^(a.p) Z_a for this wave's parity class, split
       // into the left operand of the first inverse pass as it is formed (FP32:
       // rounded to the FP32 operand)
+      // (FX16: the scale 2^b rides on the lane's column twiddle, exactly)
+      const Cd c2b = FX ? Cd{ldexp(c2.x, b), ldexp(c2.y, b)} : c2;
       float zr[16], zi[16];
 #pragma unroll
       for (int v = 0; v < 16; v += 2) {
@@ -312,9 +314,9 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int
             sr += sgn[s] * t.x;
             si += sgn[s] * t.y;
           }
-          const Cd g = cmul(twv(v + u), {sr, si});
-          gr[u] = FX ? ldexp(g.x, b) : g.x;
-          gi[u] = FX ? ldexp(g.y, b) : g.y;
+          const Cd g = cmul(cmul(tw[32 * p1 + rrow(v + u, h)], c2b), {sr, si});
+          gr[u] = g.x;
+          gi[u] = g.y;
         }
         if constexpr (FX) {
           put2(A[v >> 3], v & 7, split2_f64(gr[0], gr[1]));
