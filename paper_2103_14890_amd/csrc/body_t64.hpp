@@ -48,6 +48,9 @@ struct alignas(16) Cd {
   double x, y;
 };
 
+typedef double dbl2v __attribute__((ext_vector_type(2)));   // 16-byte store units
+typedef float flt4v __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ Cd cmul(Cd a, Cd b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 
 // Parity sub-grid x[m1][m2] = f[2 m1 + p1][2 m2 + p2] of one cell in the 32x32
@@ -331,8 +334,11 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int
       }
       __syncthreads();
       // every wave has read the Z slots: f_hat_a back into this wave's slot
+      // (not after the loss transform, the last of a cell)
+      if constexpr (G) {
 #pragma unroll
-      for (int v = 0; v < 16; ++v) zs[(w * 16 + v) * 64 + lane] = fq[v];
+        for (int v = 0; v < 16; ++v) zs[(w * 16 + v) * 64 + lane] = fq[v];
+      }
       if constexpr (FX) {
         pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
         int sd = a.filt_exp[q] - b - 9;   // Z_a carried the filter mantissas
@@ -402,20 +408,37 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int
     asm volatile("" : "+v"(elane));
     const int h = elane >> 5, c = elane & 31;
     const double v2c = -a.L + a.dv * (2 * c + p2);
+    // Q leaves through LDS: each wave puts its parity class in row-major order
+    // into the exchange slots (free after the last transform), then the
+    // workgroup writes whole rows. Stored directly, the classes interleave at
+    // every other element, and each cache line reaches memory in halves.
+    // (The slots are free: the last transform of a cell, the loss transform,
+    // does not write them back after its barrier; in the split form the last
+    // transform of a part can be a gain transform, hence the first barrier.)
+    auto store_q = [&](auto* Qc, auto value) {
+      using T = std::remove_reference_t<decltype(*Qc)>;
+      using T4 = typename std::conditional<sizeof(T) == 8, dbl2v, flt4v>::type;
+      constexpr int kPer = 16 / sizeof(T);
+      T* st = reinterpret_cast<T*>(zs);
+      if constexpr (SPLIT) __syncthreads();
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int r = rrow(v, h);
+        if (r < np && c < np) st[(2 * r + p1) * n + 2 * c + p2] = value(v);
+      }
+      __syncthreads();
+      // n even: n * n is a multiple of 4 and every cell starts 16-byte aligned
+      const T4* st4 = reinterpret_cast<const T4*>(st);
+      T4* q4 = reinterpret_cast<T4*>(Qc);
+      for (int i = threadIdx.x; i < n * n / kPer; i += blockDim.x) __builtin_nontemporal_store(st4[i], &q4[i]);
+      __syncthreads();   // the next cell writes the slots
+    };
     if (can(4) && kind == 4) {  // double Q without projection (fine-grid stage of the Galerkin variant)
       double* Qc = reinterpret_cast<double*>(a.q) + cell * static_cast<int64_t>(n) * n;
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int r = rrow(v, h);
-        if (r < np && c < np) __builtin_nontemporal_store(gain[v], &Qc[(2 * r + p1) * n + 2 * c + p2]);
-      }
+      store_q(Qc, [&](int v) { return gain[v]; });
     } else if (can(0) && kind == 0) {
       float* Qc = reinterpret_cast<float*>(a.q) + cell * static_cast<int64_t>(n) * n;
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int r = rrow(v, h);
-        if (r < np && c < np) __builtin_nontemporal_store(static_cast<float>(gain[v]), &Qc[(2 * r + p1) * n + 2 * c + p2]);
-      }
+      store_q(Qc, [&](int v) { return static_cast<float>(gain[v]); });
     } else if (can(1) && kind == 1) {
       double m[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -440,13 +463,10 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int
         lam[i] = a.gram_inv[i * 4 + 0] * m[0] + a.gram_inv[i * 4 + 1] * m[1] + a.gram_inv[i * 4 + 2] * m[2] +
                  a.gram_inv[i * 4 + 3] * m[3];
       double* Qc = reinterpret_cast<double*>(a.q) + cell * static_cast<int64_t>(n) * n;
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int r = rrow(v, h);
-        const double v1 = -a.L + a.dv * (2 * r + p1);
-        const double corr = lam[0] + lam[1] * v1 + lam[2] * v2c + lam[3] * (v1 * v1 + v2c * v2c);
-        if (r < np && c < np) __builtin_nontemporal_store(gain[v] - corr, &Qc[(2 * r + p1) * n + 2 * c + p2]);
-      }
+      store_q(Qc, [&](int v) {
+        const double v1 = -a.L + a.dv * (2 * rrow(v, h) + p1);
+        return gain[v] - (lam[0] + lam[1] * v1 + lam[2] * v2c + lam[3] * (v1 * v1 + v2c * v2c));
+      });
     } else if (can(3) && kind == 3) {
       // stage l of the penalised IMEX RK step (as finish_cell<3> of the 32x32
       // kernels); fv holds the input F_{l-1}, gain its Q (FP64)
