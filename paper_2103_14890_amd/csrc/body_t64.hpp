@@ -334,11 +334,8 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int
       }
       __syncthreads();
       // every wave has read the Z slots: f_hat_a back into this wave's slot
-      // (not after the loss transform, the last of a cell)
-      if constexpr (G) {
 #pragma unroll
-        for (int v = 0; v < 16; ++v) zs[(w * 16 + v) * 64 + lane] = fq[v];
-      }
+      for (int v = 0; v < 16; ++v) zs[(w * 16 + v) * 64 + lane] = fq[v];
       if constexpr (FX) {
         pass64_lo_lds(A, E, eo, kEr, kNEi, kEi, kEr, true, r0, r1, i0, i1);
         int sd = a.filt_exp[q] - b - 9;   // Z_a carried the filter mantissas
@@ -365,17 +362,31 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int
         }
       }
     };
-    for (int q = part; q < a.P; q += S) transform(q, std::true_type{});
+    // the loss transform first (the loss term -f * L starts the gain sum), so
+    // that its read of f follows the first one closely enough to hit the
+    // cache: evaluations fetch f from memory once per cell. Then the gain
+    // transforms. (The split form keeps the loss last: its part P mod S.)
     const bool own_loss = !SPLIT || part == a.P % S;   // workgroup-uniform
-    if (own_loss) transform(a.P, std::false_type{});
-    load_subgrid(a, cell, p1, p2, fv);  // re-read: not kept live through the filter loop
-    if (own_loss) {
+    auto loss_term = [&]() {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const double lf = FX ? ldexp(static_cast<double>(r0[v]) + static_cast<double>(r1[v]), sd_last)
                              : static_cast<double>(r0[v]);
         gain[v] -= static_cast<double>(fv[v]) * lf;
       }
+    };
+    if constexpr (!SPLIT) {
+      transform(a.P, std::false_type{});
+      load_subgrid(a, cell, p1, p2, fv);   // not held in registers through the forward transform
+      loss_term();
+    }
+    for (int q = part; q < a.P; q += S) transform(q, std::true_type{});
+    if constexpr (SPLIT) {
+      if (own_loss) transform(a.P, std::false_type{});
+      load_subgrid(a, cell, p1, p2, fv);
+      if (own_loss) loss_term();
+    } else if ((can(2) && kind == 2) || (can(3) && kind == 3)) {
+      load_subgrid(a, cell, p1, p2, fv);   // the updates read f again (not held through the transforms)
     }
     if constexpr (SPLIT) {
       double* mine = a.split_ws + ((cell * S + part) * 4 + w) * 1024;
@@ -412,15 +423,12 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int
     // into the exchange slots (free after the last transform), then the
     // workgroup writes whole rows. Stored directly, the classes interleave at
     // every other element, and each cache line reaches memory in halves.
-    // (The slots are free: the last transform of a cell, the loss transform,
-    // does not write them back after its barrier; in the split form the last
-    // transform of a part can be a gain transform, hence the first barrier.)
     auto store_q = [&](auto* Qc, auto value) {
       using T = std::remove_reference_t<decltype(*Qc)>;
       using T4 = typename std::conditional<sizeof(T) == 8, dbl2v, flt4v>::type;
       constexpr int kPer = 16 / sizeof(T);
       T* st = reinterpret_cast<T*>(zs);
-      if constexpr (SPLIT) __syncthreads();
+      __syncthreads();   // every wave has written its slot back
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int r = rrow(v, h);
