@@ -763,10 +763,16 @@ def main() -> int:
             plan.apply_shape(default)
             td.append(time_launches(lambda: plan.eval(f, q), args.steps, wu, stream)[0])
             plan.apply_shape(tuned)
-            te.append(time_launches(lambda: plan.eval(f, q), args.steps, wu, stream)[0])
+            t_e, per_e = time_launches(lambda: plan.eval(f, q), args.steps, wu, stream)
+            te.append(t_e)
             t_g, per_g = time_launches(g.replay, args.steps, wu, stream)
             tg.append(t_g)
-        res[prec].update(per=per_g, step=float(np.median(tg)), graph=g, eager_tuned=float(np.median(te)),
+        # the headline form: graph replays or eager launches of the tuned shape,
+        # whichever runs the same work faster (both figures are reported)
+        form = "graph" if np.median(tg) <= np.median(te) else "eager"
+        res[prec].update(per=per_g if form == "graph" else per_e, form=form,
+                         step=float(min(np.median(tg), np.median(te))), graph=g,
+                         graph_step=float(np.median(tg)), eager_tuned=float(np.median(te)),
                          eager_default=float(np.median(td)),
                          rounds_ms={"graph": [t * 1e3 for t in tg], "eager_tuned": [t * 1e3 for t in te],
                                     "eager_default": [t * 1e3 for t in td]})
@@ -859,8 +865,10 @@ def main() -> int:
         "config": {"workload": f"{args.workload}: {DESC}",
                    "cells": cells, "N_v": f"{NN}x{NN}", "kernel": KERN, "M": MM,
                    "K_r": mix["info"]["K_r"],
-                   "timed": "K back-to-back graph replays of one evaluation over all cells between two events, "
-                            "autotuned launch shape; median of --rounds such runs"},
+                   "timed": ("K back-to-back " + ("graph replays" if mix["form"] == "graph" else "eager launches")
+                             + " of one evaluation over all cells between two events, autotuned launch shape; "
+                             "median of --rounds such runs (the faster of the graph and eager forms, both in "
+                             "graph_ms and eager_ms)")},
         "roofline": roof,
         "roofline_conventions": conv,
         "cpu_baseline": baseline_line(base, "cell-evals/s", f"first {ncpu} cells of the same workload"),
@@ -870,6 +878,7 @@ def main() -> int:
         "worst_cell_vs_rms": mix["worst_cell_rms"],
         "parity_cells": ncpu,
         "mass_defect_max": mix["mass"],
+        "graph_ms": mix["graph_step"] * 1e3,
         "eager_ms": {"default_shape": mix["eager_default"] * 1e3, "tuned_shape": mix["eager_tuned"] * 1e3},
         "rounds_ms": mix["rounds_ms"],
         "launch_shape": {"default": mix["default_shape"], "tuned": mix["tuned_shape"], "from": mix["tuned_from"]},
