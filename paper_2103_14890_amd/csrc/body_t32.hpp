@@ -593,7 +593,7 @@ __device__ __forceinline__ void fp32_t32_body(const KernelArgs& a, int64_t first
     };
     for (int q = 0; q < a.P; ++q) transform(q, std::true_type{});
     transform(a.P, std::false_type{});
-    finish_cell<OUT, Lay32, 2>(a, cell, fv, gain, lane);   // FP32 operands hold more registers
+    finish_cell<OUT, Lay32>(a, cell, fv, gain, lane);
   }
 }
 

@@ -516,15 +516,20 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int
       const double cM = rho / (2.0 * 3.14159265358979323846 * Tm);
       const double den = 1.0 + Ai[l - 1] * k * nu;
       const double* ec = exp_consts();
+      // the Maxwellian factors by velocity axis, M = cM e1(v1) e2(v2): this
+      // lane's column factor, and the factor of this wave's row 2 (lane mod 32)
+      // + p1, which the rows fetch from that lane
+      const double e2 = exp_nonpos(-(v2c - u2) * (v2c - u2) / (2.0 * Tm), ec);
+      const double vr = -a.L + a.dv * (2 * (lane & 31) + p1);
+      const double e1 = exp_nonpos(-(vr - u1) * (vr - u1) / (2.0 * Tm), ec);
       int bad = 0;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int r = rrow(v, h);
+        const double M = cM * __shfl(e1, r) * e2;   // (every lane takes part in the exchange)
         if (!(r < np && c < np)) continue;
         const int o = (2 * r + p1) * n + 2 * c + p2;
-        const double v1 = -a.L + a.dv * (2 * r + p1);
         const double fnv = static_cast<double>(fnp[o]);
-        const double M = cM * exp_nonpos(-((v1 - u1) * (v1 - u1) + (v2c - u2) * (v2c - u2)) / (2.0 * Tm), ec);
         double rhs = fnv + Ai[l - 1] * k * nu * M;
         for (int m = 1; m < l; ++m) {
           const double Fm = m == 1 ? fnv

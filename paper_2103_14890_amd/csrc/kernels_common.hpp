@@ -246,6 +246,13 @@ __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, 
     const double cM = rho / (2.0 * 3.14159265358979323846 * T);
     const double den = 1.0 + Ai[l - 1] * k * nu;
     const double* ec = exp_consts();
+    // the Maxwellian factors by velocity axis, M = cM e1(v1) e2(v2): this lane's
+    // column factor, and the row factor of row (lane mod N), which the rows'
+    // updates fetch from that lane (two exponentials per lane instead of one
+    // per point)
+    const double e2 = exp_nonpos(-(v2c - u2) * (v2c - u2) / (2.0 * T), ec);
+    const double vr = -a.L + a.dv * (lane % LY::N);
+    const double e1 = exp_nonpos(-(vr - u1) * (vr - u1) / (2.0 * T), ec);
     int bad = 0;
     // four rows at a time: the slot loads of the earlier stages for these rows
     // issue together (up to 2 stage values and 3 Q values per row), then the
@@ -282,7 +289,7 @@ __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, 
         const int r = LY::row(v, lane);
         const double v1 = -a.L + a.dv * r;
         const double fnv = static_cast<double>(fn[j]);
-        const double M = cM * exp_nonpos(-((v1 - u1) * (v1 - u1) + (v2c - u2) * (v2c - u2)) / (2.0 * T), ec);
+        const double M = cM * __shfl(e1, r) * e2;
         double rhs = fnv + Ai[l - 1] * k * nu * M;
 #pragma unroll
         for (int m = 1; m <= 4; ++m) {
