@@ -435,10 +435,15 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int
         if (r < np && c < np) st[(2 * r + p1) * n + 2 * c + p2] = value(v);
       }
       __syncthreads();
-      // n even: n * n is a multiple of 4 and every cell starts 16-byte aligned
-      const T4* st4 = reinterpret_cast<const T4*>(st);
-      T4* q4 = reinterpret_cast<T4*>(Qc);
-      for (int i = threadIdx.x; i < n * n / kPer; i += blockDim.x) __builtin_nontemporal_store(st4[i], &q4[i]);
+      // n even: n * n is a multiple of 4, so every cell starts 16-byte aligned
+      // when the output does (else element stores)
+      if ((reinterpret_cast<uintptr_t>(Qc) & 15) == 0) {
+        const T4* st4 = reinterpret_cast<const T4*>(st);
+        T4* q4 = reinterpret_cast<T4*>(Qc);
+        for (int i = threadIdx.x; i < n * n / kPer; i += blockDim.x) __builtin_nontemporal_store(st4[i], &q4[i]);
+      } else {
+        for (int i = threadIdx.x; i < n * n; i += blockDim.x) __builtin_nontemporal_store(st[i], &Qc[i]);
+      }
       __syncthreads();   // the next cell writes the slots
     };
     if (can(4) && kind == 4) {  // double Q without projection (fine-grid stage of the Galerkin variant)

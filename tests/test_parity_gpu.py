@@ -417,3 +417,22 @@ def test_step_rk_argument_checks(qc):
     with pytest.raises(qc.QcollError):
         plan.step_rk(f, -0.01, 1.0, "ars222")
     plan.close()
+
+
+@pytest.mark.parametrize("conserve", [False, True])
+def test_tile64_output_not_16_byte_aligned(qc, conserve):
+    """The tile-64 kernels write Q as whole rows with 16-byte stores when the
+    output allows it; an output only element-aligned (8 bytes for double Q,
+    4 for float) takes element stores, with the same results."""
+    N, cells = 48, 5
+    f = torch.tensor(wl.mixture_cells(2, N, 8.0, cells, 61), dtype=torch.float32, device="cuda")
+    plan = qc.Plan(2, N, 8.0, "hard_sphere", 8, precision="fx16", conserve=conserve)
+    dt = torch.float64 if conserve else torch.float32
+    ref = plan.eval(f)
+    buf = torch.full((cells * N * N + 1,), float("nan"), dtype=dt, device="cuda")
+    q = buf[1:].view(cells, N, N)
+    plan.eval(f, q)
+    torch.cuda.synchronize()
+    assert q.data_ptr() % 16 != 0
+    assert torch.equal(q, ref)
+    plan.close()
