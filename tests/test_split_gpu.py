@@ -5,6 +5,8 @@ transforms (section 3.3), so the split changes the order of that FP64 sum only:
 the results match the oracle at the precision's bound, agree with the unsplit
 results to FP64 rounding, and are deterministic."""
 
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -152,3 +154,54 @@ def test_split_rules_and_rk_ignores_split(qc):
     torch.cuda.synchronize()
     assert torch.equal(a, b)
     p.close()
+
+
+def test_split_graph_capture_and_replay(qc):
+    """Split plans captured in a graph (their buffers exist before the capture;
+    growing them under capture is refused): every replay, with eager work and
+    synchronisation in between, equals the eager split result bitwise, so the
+    arrival counters are back at zero after each launch."""
+    p64 = qc.Plan(2, 64, 8.0, "hard_sphere", 8, precision="fx16")
+    p32 = qc.Plan(2, 32, 8.0, "hard_sphere", 8, precision="fx16")
+    p64.set_split(4)
+    p32.set_split(4)
+    f64 = torch.tensor(wl.mixture_cells(2, 64, 8.0, 6, 71), dtype=torch.float32, device="cuda")
+    f32 = torch.tensor(wl.mixture_cells(2, 32, 8.0, 9, 72), dtype=torch.float32, device="cuda")
+    e64, e32 = p64.eval(f64), p32.eval(f32)          # also sizes the tile-64 buffers
+    torch.cuda.synchronize()
+    q64, q32 = torch.empty_like(e64), torch.empty_like(e32)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        qc.eval_multi([p64, p32], [f64, f32], [q64, q32])
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        qc.eval_multi([p64, p32], [f64, f32], [q64, q32])
+    for r in range(3):
+        q64.fill_(float("nan"))
+        q32.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(q64, e64) and torch.equal(q32, e32)
+        other = p64.eval(f64)                        # eager split work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(other, e64)
+    # growing the buffers under capture is refused before any device work (the
+    # raw call: no exception inside the capture)
+    big = torch.tensor(wl.mixture_cells(2, 64, 8.0, 80, 73), dtype=torch.float32, device="cuda")
+    qb = torch.empty(big.shape, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g2):
+        rc = qc.LIB.qcoll_eval(p64._h, ctypes.c_void_p(big.data_ptr()), ctypes.c_void_p(qb.data_ptr()), 80,
+                               ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    assert rc == qc.EINVAL
+    q_after = p64.eval(f64)                          # the plan still works outside the capture
+    torch.cuda.synchronize()
+    assert torch.equal(q_after, e64)
+    p64.close()
+    p32.close()
