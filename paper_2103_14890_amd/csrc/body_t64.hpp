@@ -48,9 +48,6 @@ struct alignas(16) Cd {
   double x, y;
 };
 
-typedef double dbl2v __attribute__((ext_vector_type(2)));   // 16-byte store units
-typedef float flt4v __attribute__((ext_vector_type(4)));
-
 __device__ __forceinline__ Cd cmul(Cd a, Cd b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 
 // Parity sub-grid x[m1][m2] = f[2 m1 + p1][2 m2 + p2] of one cell in the 32x32
@@ -425,8 +422,6 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int
     // every other element, and each cache line reaches memory in halves.
     auto store_q = [&](auto* Qc, auto value) {
       using T = std::remove_reference_t<decltype(*Qc)>;
-      using T4 = typename std::conditional<sizeof(T) == 8, dbl2v, flt4v>::type;
-      constexpr int kPer = 16 / sizeof(T);
       T* st = reinterpret_cast<T*>(zs);
       __syncthreads();   // every wave has written its slot back
 #pragma unroll
@@ -435,15 +430,9 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int
         if (r < np && c < np) st[(2 * r + p1) * n + 2 * c + p2] = value(v);
       }
       __syncthreads();
-      // n even: n * n is a multiple of 4, so every cell starts 16-byte aligned
-      // when the output does (else element stores)
-      if ((reinterpret_cast<uintptr_t>(Qc) & 15) == 0) {
-        const T4* st4 = reinterpret_cast<const T4*>(st);
-        T4* q4 = reinterpret_cast<T4*>(Qc);
-        for (int i = threadIdx.x; i < n * n / kPer; i += blockDim.x) __builtin_nontemporal_store(st4[i], &q4[i]);
-      } else {
-        for (int i = threadIdx.x; i < n * n; i += blockDim.x) __builtin_nontemporal_store(st[i], &Qc[i]);
-      }
+      // element stores, consecutive lanes at consecutive addresses (whole rows;
+      // any element-aligned output)
+      for (int i = threadIdx.x; i < n * n; i += blockDim.x) __builtin_nontemporal_store(st[i], &Qc[i]);
       __syncthreads();   // the next cell writes the slots
     };
     if (can(4) && kind == 4) {  // double Q without projection (fine-grid stage of the Galerkin variant)
