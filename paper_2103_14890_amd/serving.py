@@ -37,6 +37,7 @@ All device work is done by the HIP library through the binding.
 from __future__ import annotations
 
 import collections
+import ctypes
 import dataclasses
 import time
 
@@ -156,6 +157,8 @@ class Server:
         self.cell_steps = 0
         self._pending = None               # the previous tick, completed by the next tick or flush()
         self._admit_time: dict[int, float] = {}
+        self._flags = [None, None]         # pinned status buffers of alternate ticks
+        self._scheme = qcoll._SCHEMES[scheme]
 
     # ----------------------------------------------------------- admission
     def _group(self, N: int, kernel: str) -> _Group:
@@ -239,18 +242,31 @@ class Server:
             if self.split:
                 for g in groups:
                     g.set_split_for(len(g.live))
-            plans = [g.plan for g in groups]
-            fs = [g.pool[:len(g.live)] for g in groups]
-            st = [g.status[:len(g.live)] for g in groups]
-            qcoll.step_multi(plans, fs, self.dt, self.eps, self.scheme, st)
+            stream = torch.cuda.current_stream()
+            # the batched step through the C ABI (the pools are this server's own
+            # contiguous device buffers: the binding's per-tensor checks are skipped)
+            n = len(groups)
+            counts = [len(g.live) for g in groups]
+            total = sum(counts)
+            PtrArr = ctypes.c_void_p * n
+            qcoll._check(qcoll.LIB.qcoll_step_multi(
+                PtrArr(*[g.plan._h.value for g in groups]), n, PtrArr(*[g.pool.data_ptr() for g in groups]),
+                (ctypes.c_int64 * n)(*counts), self.dt, self.eps, self._scheme,
+                PtrArr(*[g.status.data_ptr() for g in groups]), ctypes.c_void_p(stream.cuda_stream)),
+                "qcoll_step_multi")
             self.ticks += 1
-            self.cell_steps += sum(len(g.live) for g in groups)
-            # status flags straight into pinned host memory (no device temporary)
-            flags = torch.empty(sum(len(g.live) for g in groups), dtype=torch.int32, pin_memory=True)
+            self.cell_steps += total
+            # status flags straight into pinned host memory (no device temporary);
+            # alternate ticks use alternate buffers (the previous tick's is read
+            # by flush() after this tick's copies are queued)
+            b = self.ticks & 1
+            if self._flags[b] is None or self._flags[b].numel() < total:
+                self._flags[b] = torch.empty(max(total, 256) * 2, dtype=torch.int32, pin_memory=True)
+            flags = self._flags[b][:total]
             k = 0
-            for s_ in st:
-                flags[k:k + s_.shape[0]].copy_(s_, non_blocking=True)
-                k += s_.shape[0]
+            for g, c in zip(groups, counts):
+                flags[k:k + c].copy_(g.status[:c], non_blocking=True)
+                k += c
             slots = [(g, list(g.live)) for g in groups]   # request of each slot in this step
             finished = []
             for g in groups:
@@ -265,7 +281,7 @@ class Server:
                     finished.append((g.live[i], host, j))
                 self._compact(g, done)
             ev = torch.cuda.Event()
-            ev.record()
+            ev.record(stream)
             new = (ev, flags, slots, finished)
         retired = self.flush(clock)
         self._pending = new
