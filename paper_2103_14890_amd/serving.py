@@ -158,6 +158,7 @@ class Server:
         self._pending = None               # the previous tick, completed by the next tick or flush()
         self._admit_time: dict[int, float] = {}
         self._flags = [None, None]         # pinned status buffers of alternate ticks
+        self._events = [None, None]        # and their completion events
         self._scheme = qcoll._SCHEMES[scheme]
 
     # ----------------------------------------------------------- admission
@@ -280,7 +281,9 @@ class Server:
                     host[j].copy_(g.pool[i], non_blocking=True)
                     finished.append((g.live[i], host, j))
                 self._compact(g, done)
-            ev = torch.cuda.Event()
+            if self._events[b] is None:
+                self._events[b] = torch.cuda.Event()
+            ev = self._events[b]
             ev.record(stream)
             new = (ev, flags, slots, finished)
         retired = self.flush(clock)
@@ -301,16 +304,17 @@ class Server:
         now = clock()
         fl = flags.numpy()
         bad, k = set(), 0
-        for g, rids in slots:
-            bad.update(rid for i, rid in enumerate(rids) if fl[k + i] != 0)
-            k += len(rids)
+        if fl.any():   # (the common case has no flagged cell)
+            for g, rids in slots:
+                bad.update(rid for i, rid in enumerate(rids) if fl[k + i] != 0)
+                k += len(rids)
         for rid, host, j in finished:
             r = self.results[rid]
             r.failed = rid in bad
             r.f = None if r.failed else host[j].numpy().copy()
             r.done = now
         retired = len(finished)
-        for g, rids in slots:
+        for g, rids in (slots if bad else ()):
             gone = [g.live.index(rid) for rid in rids if rid in bad and rid in g.live]
             for i in gone:
                 r = self.results[g.live[i]]
