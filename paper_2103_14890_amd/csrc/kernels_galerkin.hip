@@ -36,19 +36,33 @@ __global__ __launch_bounds__(256) void galerkin_interp_kernel(GalerkinArgs a) {
     const float* fc = a.f + cell * static_cast<int64_t>(n) * n;
     for (int i = threadIdx.x; i < n * n; i += blockDim.x) fs[i] = static_cast<double>(fc[i]);
     __syncthreads();
-    for (int i = threadIdx.x; i < nf * n; i += blockDim.x) {
-      const int r = i / n, c = i - r * n;
-      double s = 0.0;
-      for (int k = 0; k < n; ++k) s += I[r * n + k] * fs[k * n + c];
-      t[i] = s;
+    // two neighbouring outputs per thread and step (one 16-byte LDS read of the
+    // row operand per pair of FMAs; n and nf are even)
+    for (int i = threadIdx.x; i < nf * n / 2; i += blockDim.x) {
+      const int r = i / (n / 2), c = 2 * (i - r * (n / 2));
+      double s0 = 0.0, s1 = 0.0;
+      for (int k = 0; k < n; ++k) {
+        const double g = I[r * n + k];
+        const double2 b = *reinterpret_cast<const double2*>(&fs[k * n + c]);
+        s0 += g * b.x;
+        s1 += g * b.y;
+      }
+      t[r * n + c] = s0;
+      t[r * n + c + 1] = s1;
     }
     __syncthreads();
     float* ff = a.f_fine + cell * static_cast<int64_t>(nf) * nf;
-    for (int i = threadIdx.x; i < nf * nf; i += blockDim.x) {
-      const int r = i / nf, c = i - r * nf;
-      double s = 0.0;
-      for (int k = 0; k < n; ++k) s += t[r * n + k] * IT[k * nf + c];
-      ff[i] = static_cast<float>(s);
+    for (int i = threadIdx.x; i < nf * nf / 2; i += blockDim.x) {
+      const int r = i / (nf / 2), c = 2 * (i - r * (nf / 2));
+      double s0 = 0.0, s1 = 0.0;
+      for (int k = 0; k < n; ++k) {
+        const double g = t[r * n + k];
+        const double2 b = *reinterpret_cast<const double2*>(&IT[k * nf + c]);
+        s0 += g * b.x;
+        s1 += g * b.y;
+      }
+      ff[r * nf + c] = static_cast<float>(s0);
+      ff[r * nf + c + 1] = static_cast<float>(s1);
     }
   }
 }
@@ -74,25 +88,42 @@ __global__ __launch_bounds__(256) void galerkin_restrict_kernel(GalerkinArgs a) 
     const double* qc = a.q_fine + cell * static_cast<int64_t>(nf) * nf;
     for (int i = threadIdx.x; i < nf * nf; i += blockDim.x) qs[i] = qc[i];
     __syncthreads();
-    for (int i = threadIdx.x; i < n * nf; i += blockDim.x) {
-      const int r = i / nf, c = i - r * nf;
-      double s = 0.0;
-      for (int k = 0; k < nf; ++k) s += R[r * nf + k] * qs[k * nf + c];
-      t[i] = s;
+    // two neighbouring outputs per thread and step, as in the interpolation
+    for (int i = threadIdx.x; i < n * nf / 2; i += blockDim.x) {
+      const int r = i / (nf / 2), c = 2 * (i - r * (nf / 2));
+      double s0 = 0.0, s1 = 0.0;
+      for (int k = 0; k < nf; ++k) {
+        const double g = R[r * nf + k];
+        const double2 b = *reinterpret_cast<const double2*>(&qs[k * nf + c]);
+        s0 += g * b.x;
+        s1 += g * b.y;
+      }
+      t[r * nf + c] = s0;
+      t[r * nf + c + 1] = s1;
     }
     __syncthreads();
     // Q[r][c] = sum_k t[r][k] R[c][k]; each thread keeps its points for the projection
     double m[4] = {0, 0, 0, 0};
-    for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
-      const int r = i / n, c = i - r * n;
-      double s = 0.0;
-      for (int k = 0; k < nf; ++k) s += t[r * nf + k] * RT[k * n + c];
-      qs[i] = s;             // qs is free again: Q on the n grid
-      const double v1 = -a.L + a.dv * r, v2 = -a.L + a.dv * c;
-      m[0] += s;
-      m[1] += v1 * s;
-      m[2] += v2 * s;
-      m[3] += (v1 * v1 + v2 * v2) * s;
+    for (int i = threadIdx.x; i < n * n / 2; i += blockDim.x) {
+      const int r = i / (n / 2), c = 2 * (i - r * (n / 2));
+      double s0 = 0.0, s1 = 0.0;
+      for (int k = 0; k < nf; ++k) {
+        const double g = t[r * nf + k];
+        const double2 b = *reinterpret_cast<const double2*>(&RT[k * n + c]);
+        s0 += g * b.x;
+        s1 += g * b.y;
+      }
+      qs[r * n + c] = s0;    // qs is free again: Q on the n grid
+      qs[r * n + c + 1] = s1;
+      const double v1 = -a.L + a.dv * r, v2 = -a.L + a.dv * c, v2b = v2 + a.dv;
+      m[0] += s0;
+      m[1] += v1 * s0;
+      m[2] += v2 * s0;
+      m[3] += (v1 * v1 + v2 * v2) * s0;
+      m[0] += s1;
+      m[1] += v1 * s1;
+      m[2] += v2b * s1;
+      m[3] += (v1 * v1 + v2b * v2b) * s1;
     }
     const int64_t base = cell * static_cast<int64_t>(n) * n;
     if (!a.conserve) {
