@@ -48,6 +48,9 @@ struct alignas(16) Cd {
   double x, y;
 };
 
+typedef double dbl2v __attribute__((ext_vector_type(2)));   // 16-byte store units
+typedef float flt4v __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ Cd cmul(Cd a, Cd b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 
 // Parity sub-grid x[m1][m2] = f[2 m1 + p1][2 m2 + p2] of one cell in the 32x32
@@ -129,7 +132,9 @@ __device__ __forceinline__ void inv_fp32(const E32& E, const float* zr, const fl
 // P mod a.split the loss; the parts leave their results in a.split_ws and count
 // their arrivals in a.split_cnt; the last to arrive adds the parts in the order
 // 0, 1, ... and runs the epilogue (first and stride then count work items).
-template <int OUT, bool FX, bool SPLIT = false>
+// VEC: Q is written with 16-byte stores (the caller has checked that the output
+// is 16-byte aligned; n even makes every cell so), else with element stores.
+template <int OUT, bool FX, bool SPLIT = false, bool VEC = false>
 __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int64_t stride, double2* lds_raw) {
   const int kind = OUT < 0 ? a.out_kind : OUT;
   auto can = [](int k) { return OUT == k || (OUT < 0 && k <= 2); };
@@ -430,9 +435,16 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int
         if (r < np && c < np) st[(2 * r + p1) * n + 2 * c + p2] = value(v);
       }
       __syncthreads();
-      // element stores, consecutive lanes at consecutive addresses (whole rows;
-      // any element-aligned output)
-      for (int i = threadIdx.x; i < n * n; i += blockDim.x) __builtin_nontemporal_store(st[i], &Qc[i]);
+      // consecutive lanes at consecutive addresses (whole rows)
+      if constexpr (VEC) {
+        using T4 = typename std::conditional<sizeof(T) == 8, dbl2v, flt4v>::type;
+        constexpr int kPer = 16 / sizeof(T);
+        const T4* st4 = reinterpret_cast<const T4*>(st);
+        T4* q4 = reinterpret_cast<T4*>(Qc);
+        for (int i = threadIdx.x; i < n * n / kPer; i += blockDim.x) __builtin_nontemporal_store(st4[i], &q4[i]);
+      } else {
+        for (int i = threadIdx.x; i < n * n; i += blockDim.x) __builtin_nontemporal_store(st[i], &Qc[i]);
+      }
       __syncthreads();   // the next cell writes the slots
     };
     if (can(4) && kind == 4) {  // double Q without projection (fine-grid stage of the Galerkin variant)

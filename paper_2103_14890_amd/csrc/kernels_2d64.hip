@@ -14,54 +14,67 @@ namespace {
 // the 79 KB of LDS lets the matrix work of one cell overlap the vector and LDS
 // work of the other.
 #define T64_BOUNDS __launch_bounds__(256, 2)
-template <int OUT>
+// VEC: 16-byte stores of Q (output kinds 0, 1 and 4 into a 16-byte aligned Q)
+template <int OUT, bool VEC = false>
 __global__ T64_BOUNDS void fx16_t64_kernel(KernelArgs a) {
   extern __shared__ double2 lds_raw[];
-  t64_body<OUT, true>(a, blockIdx.x, gridDim.x, lds_raw);
+  t64_body<OUT, true, false, VEC>(a, blockIdx.x, gridDim.x, lds_raw);
 }
 
-template <int OUT>
+template <int OUT, bool VEC = false>
 __global__ T64_BOUNDS void fp32_t64_kernel(KernelArgs a) {
   extern __shared__ double2 lds_raw[];
-  t64_body<OUT, false>(a, blockIdx.x, gridDim.x, lds_raw);
+  t64_body<OUT, false, false, VEC>(a, blockIdx.x, gridDim.x, lds_raw);
 }
 
 }  // namespace
 
-template <template <int> class K>
+template <template <int, bool> class K>
 static bool set_lds_attr() {
   bool ok = true;
-  ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(K<0>::fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kT64LdsBytes) == hipSuccess;
-  ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(K<1>::fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kT64LdsBytes) == hipSuccess;
-  ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(K<2>::fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kT64LdsBytes) == hipSuccess;
-  ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(K<3>::fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kT64LdsBytes) == hipSuccess;
-  ok &= hipFuncSetAttribute(reinterpret_cast<const void*>(K<4>::fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kT64LdsBytes) == hipSuccess;
+  auto set = [&](const void* fn) {
+    ok &= hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kT64LdsBytes) == hipSuccess;
+  };
+  set(reinterpret_cast<const void*>(K<0, false>::fn));
+  set(reinterpret_cast<const void*>(K<1, false>::fn));
+  set(reinterpret_cast<const void*>(K<2, false>::fn));
+  set(reinterpret_cast<const void*>(K<3, false>::fn));
+  set(reinterpret_cast<const void*>(K<4, false>::fn));
+  set(reinterpret_cast<const void*>(K<0, true>::fn));
+  set(reinterpret_cast<const void*>(K<1, true>::fn));
+  set(reinterpret_cast<const void*>(K<4, true>::fn));
   return ok;
 }
 
-template <int OUT>
+template <int OUT, bool VEC>
 struct Fx16T64 {
-  static constexpr auto fn = fx16_t64_kernel<OUT>;
-};
-template <int OUT>
-struct Fp32T64 {
-  static constexpr auto fn = fp32_t64_kernel<OUT>;
+  static constexpr auto fn = fx16_t64_kernel<OUT, VEC>;
 };
 
-template <template <int> class K>
+template <int OUT, bool VEC>
+struct Fp32T64 {
+  static constexpr auto fn = fp32_t64_kernel<OUT, VEC>;
+};
+
+template <template <int, bool> class K>
 static void launch_t64(const KernelArgs& args, dim3 grid, hipStream_t stream) {
   const dim3 block(256);
+  const bool vec = (reinterpret_cast<uintptr_t>(args.q) & 15) == 0;   // (Q outputs only)
   switch (args.out_kind) {
-    case 0: hipLaunchKernelGGL(K<0>::fn, grid, block, kT64LdsBytes, stream, args); break;
-    case 1: hipLaunchKernelGGL(K<1>::fn, grid, block, kT64LdsBytes, stream, args); break;
-    case 2: hipLaunchKernelGGL(K<2>::fn, grid, block, kT64LdsBytes, stream, args); break;
-    case 3: hipLaunchKernelGGL(K<3>::fn, grid, block, kT64LdsBytes, stream, args); break;
-    default: hipLaunchKernelGGL(K<4>::fn, grid, block, kT64LdsBytes, stream, args); break;
+    case 0:
+      if (vec) hipLaunchKernelGGL((K<0, true>::fn), grid, block, kT64LdsBytes, stream, args);
+      else hipLaunchKernelGGL((K<0, false>::fn), grid, block, kT64LdsBytes, stream, args);
+      break;
+    case 1:
+      if (vec) hipLaunchKernelGGL((K<1, true>::fn), grid, block, kT64LdsBytes, stream, args);
+      else hipLaunchKernelGGL((K<1, false>::fn), grid, block, kT64LdsBytes, stream, args);
+      break;
+    case 2: hipLaunchKernelGGL((K<2, false>::fn), grid, block, kT64LdsBytes, stream, args); break;
+    case 3: hipLaunchKernelGGL((K<3, false>::fn), grid, block, kT64LdsBytes, stream, args); break;
+    default:
+      if (vec) hipLaunchKernelGGL((K<4, true>::fn), grid, block, kT64LdsBytes, stream, args);
+      else hipLaunchKernelGGL((K<4, false>::fn), grid, block, kT64LdsBytes, stream, args);
+      break;
   }
 }
 

@@ -421,9 +421,10 @@ def test_step_rk_argument_checks(qc):
 
 @pytest.mark.parametrize("conserve", [False, True])
 def test_tile64_output_not_16_byte_aligned(qc, conserve):
-    """The tile-64 kernels write Q through LDS as whole rows; an output aligned
-    only to its elements (8 bytes for double Q, 4 for float) gives the same
-    results as a freshly allocated one."""
+    """The tile-64 kernels write Q through LDS as whole rows, with 16-byte
+    stores when Q is 16-byte aligned (the kernel variant the host picks) and
+    element stores otherwise: an output aligned only to its elements (8 bytes
+    for double Q, 4 for float) gives the same results as an aligned one."""
     N, cells = 48, 5
     f = torch.tensor(wl.mixture_cells(2, N, 8.0, cells, 61), dtype=torch.float32, device="cuda")
     plan = qc.Plan(2, N, 8.0, "hard_sphere", 8, precision="fx16", conserve=conserve)
