@@ -196,8 +196,9 @@ int qcoll_eval_galerkin(qcoll_plan_t plan, const float* f, void* Q, int64_t cell
  * launch that evaluates Q(F_{l-1}) and forms F_l. scheme: QCOLL_IMEX_ARS222
  * (S = 3, two launches) or QCOLL_IMEX_BPR343 (S = 5, four launches). work:
  * device float buffer owned by the caller, at least qcoll_step_rk_work_bytes()
- * bytes, holding the stage values and Q of earlier stages (FP32); its content
- * is scratch. status as in qcoll_step (set by the last stage). Every device
+ * bytes, holding the stage values and Q of earlier stages (FP32) and, per
+ * cell, four FP64 moments of f^n (written by the first launch of the step,
+ * read by the later ones); its content is scratch. status as in qcoll_step (set by the last stage). Every device
  * plan (2D and 3D); 3D plans hold a scratch area (see qcoll_eval_multi). */
 int64_t qcoll_step_rk_work_bytes(qcoll_plan_t plan, int scheme, int64_t cells);
 int qcoll_step_rk(qcoll_plan_t plan, float* f, int64_t cells, double dt, double eps, int scheme, float* work,
@@ -209,8 +210,8 @@ int qcoll_step_rk(qcoll_plan_t plan, float* f, int64_t cells, double dt, double 
  * QCOLL_NOALLOC_SCRATCH_BYTES in the library's device memory (one per GPU, held
  * from the first call on that GPU until the process ends). The call allocates
  * nothing. Problems whose qcoll_step_rk_work_bytes() exceed the array return
- * QCOLL_ETOOLARGE before any device work (e.g. at most 2340 cells of 32^2 for
- * QCOLL_IMEX_BPR343, 5461 for QCOLL_IMEX_ARS222). Every call on one GPU shares
+ * QCOLL_ETOOLARGE before any device work (e.g. at most 2337 cells of 32^2 for
+ * QCOLL_IMEX_BPR343, 5447 for QCOLL_IMEX_ARS222). Every call on one GPU shares
  * that GPU's array: calls that overlap on one GPU (several streams, several
  * host threads) race and must be ordered by the caller. The array needs no
  * clearing (each stage slot is written before it is read). Other arguments,

@@ -922,11 +922,14 @@ int qcoll_eval_galerkin(qcoll_plan_t p, const float* f, void* Q, int64_t cells, 
   return qcoll::launch_galerkin_restrict(g, stream) ? QCOLL_EDEVICE : QCOLL_OK;
 }
 
+// Work of a multi-stage step: 2S - 3 FP32 stage slots of the batch, then (at
+// the next 8-byte boundary of the buffer) four FP64 moments of f^n per cell.
 int64_t qcoll_step_rk_work_bytes(qcoll_plan_t p, int scheme, int64_t cells) {
   const int S = rk_stages(scheme);
   if (!p || S == 0 || cells < 0) return -1;
   const int64_t n = static_cast<int64_t>(p->hp.N) * p->hp.N * (p->hp.d == 3 ? p->hp.N : 1);
-  return static_cast<int64_t>(2 * S - 3) * cells * n * static_cast<int64_t>(sizeof(float));
+  return static_cast<int64_t>(2 * S - 3) * cells * n * static_cast<int64_t>(sizeof(float)) + 8 +
+         cells * 4 * static_cast<int64_t>(sizeof(double));
 }
 
 int qcoll_step_rk(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps, int scheme, float* work,
@@ -956,6 +959,8 @@ int qcoll_step_rk(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps
     }
     return QCOLL_OK;
   }
+  const uintptr_t mom_at = reinterpret_cast<uintptr_t>(work + static_cast<int64_t>(2 * S - 3) * stride);
+  double* mom = reinterpret_cast<double*>((mom_at + 7) & ~static_cast<uintptr_t>(7));
   for (int l = 2; l <= S; ++l) {
     qcoll::KernelArgs a = make_args(p);
     a.f = l == 2 ? f : work + static_cast<int64_t>(l - 3) * stride;  // stage input F_{l-1}
@@ -964,6 +969,7 @@ int qcoll_step_rk(qcoll_plan_t p, float* f, int64_t cells, double dt, double eps
     a.out_kind = 3;
     a.rk_fn = f;
     a.rk_work = work;
+    a.rk_mom = mom;
     a.rk_stride = stride;
     a.rk_scheme = scheme == QCOLL_IMEX_ARS222 ? 1 : 2;
     a.rk_stage = l;

@@ -32,9 +32,12 @@ struct KernelArgs {
   // BPR(3,4,3)); f holds the stage input F_{l-1}, rk_fn the step's start value
   // f^n (overwritten with the result by the last stage), rk_work the stage
   // slots (F_m, m = 2..S-1, at slot m-2; Q(F_m), m = 1..S-1, at slot S-3+m),
-  // rk_stride floats apart.
+  // rk_stride floats apart. rk_mom: [cells][4] sums over the grid of f^n,
+  // v1 f^n, v2 f^n and |v|^2 f^n, written by stage 2 (whose input is f^n) and
+  // read by the later stages (2D grids of at most 32 points per axis).
   float* rk_fn = nullptr;
   float* rk_work = nullptr;
+  double* rk_mom = nullptr;
   int64_t rk_stride = 0;
   int rk_scheme = 0;
   int rk_stage = 0;

@@ -220,26 +220,44 @@ __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, 
     const double* At = kRkAt[sch][l - 1];
     const double* Ai = kRkA[sch][l - 1];
     float* fnp = a.rk_fn + base;
-    // the loads of each phase are unconditional (out-of-grid lanes read element
-    // 0 and drop it), so that they issue together: f^n for the moments, then
-    // per group of rows f^n again (a cache hit; not held in registers) and the
-    // earlier stages' values and Q
+    // The moments of f^n are the same in every stage of the step: stage 2,
+    // whose input F_1 is f^n (fv, zero outside the grid), sums them and keeps
+    // them for the later stages, which read them back (32 bytes per cell in
+    // place of a pass over f^n and four wavefront reductions). The address
+    // depends on the opaque lane (lane / 64 is 0), so that the read stays here.
     const double v2c = -a.L + a.dv * c;
+    double* mp = a.rk_mom + cell * 4 + (lane >> 6);
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    if (l == 2) {
 #pragma unroll
-    for (int v = 0; v < kV; ++v) {
-      const int r = LY::row(v, lane);
-      const double fnv = static_cast<double>(load_or_zero(fnp, r < n && c < n, r * n + c));
-      const double v1 = -a.L + a.dv * LY::row(v, lane);
-      s0 += fnv;
-      s1 += v1 * fnv;
-      s2 += v2c * fnv;
-      s3 += (v1 * v1 + v2c * v2c) * fnv;
+      for (int v = 0; v < kV; ++v) {
+        const double fnv = static_cast<double>(fv[v]);
+        const double v1 = -a.L + a.dv * LY::row(v, lane);
+        s0 += fnv;
+        s1 += v1 * fnv;
+        s2 += v2c * fnv;
+        s3 += (v1 * v1 + v2c * v2c) * fnv;
+      }
+      s0 = wave_sum(s0);
+      s1 = wave_sum(s1);
+      s2 = wave_sum(s2);
+      s3 = wave_sum(s3);
+      if (lane == 0) {
+        mp[0] = s0;
+        mp[1] = s1;
+        mp[2] = s2;
+        mp[3] = s3;
+      }
+    } else {
+      s0 = mp[0];
+      s1 = mp[1];
+      s2 = mp[2];
+      s3 = mp[3];
     }
-    s0 = wave_sum(s0);
-    s1 = wave_sum(s1);
-    s2 = wave_sum(s2);
-    s3 = wave_sum(s3);
+    // the update loads of each group are unconditional (out-of-grid lanes read
+    // element 0 and drop it), so that they issue together: f^n (a cache hit
+    // after the first group; not held in registers) and the earlier stages'
+    // values and Q
     const double rho = s0 * a.dv * a.dv, u1 = s1 / s0, u2 = s2 / s0;
     const double T = 0.5 * (s3 / s0 - u1 * u1 - u2 * u2);
     const double nu = rho, k = a.dt_eps;
