@@ -94,6 +94,12 @@ __constant__ double kRkA[2][5][5] = {
     {{0, 0, 0, 0, 0}, {0, kGam, 0, 0, 0}, {0, 1.0 - kGam, kGam, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}},
     {{0, 0, 0, 0, 0}, {0.5, 0.5, 0, 0, 0}, {5.0 / 18, -1.0 / 9, 0.5, 0, 0}, {0.5, 0, 0, 0.5, 0},
      {0.25, 0, 0.75, -0.5, 0.5}}};
+// A - At, entry by entry (the weight of nu (M - F_m) in the stage update).
+__constant__ double kRkD[2][5][5] = {
+    {{0, 0, 0, 0, 0}, {0 - kGam, kGam, 0, 0, 0}, {0 - kDel, (1.0 - kGam) - (1.0 - kDel), kGam, 0, 0}, {0, 0, 0, 0, 0},
+     {0, 0, 0, 0, 0}},
+    {{0, 0, 0, 0, 0}, {0.5 - 1, 0.5, 0, 0, 0}, {5.0 / 18 - 4.0 / 9, -1.0 / 9 - 2.0 / 9, 0.5, 0, 0},
+     {0.5 - 0.25, 0, 0 - 0.75, 0.5, 0}, {0.25 - 0.25, 0, 0.75 - 0.75, -0.5, 0.5}}};
 
 // exp(x) for x <= 0 in FP64 (the Maxwellian of the stage updates): x = k ln 2
 // + r with k = rint(x / ln 2) and |r| <= ln(2) / 2 (ln 2 in two parts, so that r
@@ -219,6 +225,7 @@ __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, 
     const int S = sch == 0 ? 3 : 5;
     const double* At = kRkAt[sch][l - 1];
     const double* Ai = kRkA[sch][l - 1];
+    const double* Dd = kRkD[sch][l - 1];
     float* fnp = a.rk_fn + base;
     // The moments of f^n are the same in every stage of the step: stage 2,
     // whose input F_1 is f^n (fv, zero outside the grid), sums them and keeps
@@ -262,7 +269,14 @@ __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, 
     const double T = 0.5 * (s3 / s0 - u1 * u1 - u2 * u2);
     const double nu = rho, k = a.dt_eps;
     const double cM = rho / (2.0 * 3.14159265358979323846 * T);
-    const double den = 1.0 + Ai[l - 1] * k * nu;
+    // F_l = rhs / den with rhs = f^n + k (nu (A_ll M + sum_m D_lm (M - F_m)) +
+    // sum_m At_lm Q(F_m)), D = A - At: the scheme's sums regrouped so that the
+    // weights are the tableau's own (scalar registers), and one reciprocal of
+    // den per cell instead of a division per point.
+    const double rden = 1.0 / (1.0 + Ai[l - 1] * k * nu);
+    bool useq[4];   // Q(F_m) enters the update (At_lm != 0); per cell, not per point
+#pragma unroll
+    for (int m = 1; m <= 4; ++m) useq[m - 1] = At[m - 1] != 0.0;
     const double* ec = exp_consts();
     // the Maxwellian factors by velocity axis, M = cM e1(v1) e2(v2): this lane's
     // column factor, and the row factor of row (lane mod N), which the rows'
@@ -308,23 +322,22 @@ __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, 
         const double v1 = -a.L + a.dv * r;
         const double fnv = static_cast<double>(fn[j]);
         const double M = cM * __shfl(e1, r) * e2;
-        double rhs = fnv + Ai[l - 1] * k * nu * M;
+        double t1 = Ai[l - 1] * M, t2 = 0.0;
 #pragma unroll
         for (int m = 1; m <= 4; ++m) {
           if (m >= l) break;
           const double Fm = m == 1 ? fnv : (m == l - 1 ? static_cast<double>(fv[v]) : static_cast<double>(Fs[m - 1][j]));
-          const double Sm = nu * (M - Fm);
-          double acc = Ai[m - 1] * Sm;
-          if (At[m - 1] != 0.0) {
+          t1 += Dd[m - 1] * (M - Fm);
+          if (useq[m - 1]) {
             const double Qm = m == l - 1 ? q[v] : static_cast<double>(Qs[m - 1][j]);
-            acc += At[m - 1] * (Qm - Sm);
+            t2 += At[m - 1] * Qm;
           }
-          rhs += k * acc;
         }
+        const double rhs = fnv + k * (nu * t1 + t2);
         chain = rhs;
         if (!(r < n && c < n)) continue;
         const int o = r * n + c;
-        const float Fl = static_cast<float>(rhs / den);
+        const float Fl = static_cast<float>(rhs * rden);
         if (l == S) {
           bad |= !(fabsf(Fl) <= 3.0e38f);
           fnp[o] = Fl;

@@ -419,6 +419,28 @@ def test_step_rk_argument_checks(qc):
     plan.close()
 
 
+@pytest.mark.parametrize("scheme", ["ars222", "bpr343"])
+def test_step_rk_work_buffer_4_byte_aligned(qc, scheme):
+    """The stage work buffer needs only float alignment: the FP64 moments of f^n
+    that stage 2 keeps for the later stages go to the next 8-byte boundary (the
+    size query includes the slack). A buffer one float past an aligned address
+    gives the same steps bitwise."""
+    cells, N = 5, 32
+    f0 = torch.tensor(wl.mixture_cells(2, N, 8.0, cells, 77), dtype=torch.float32, device="cuda")
+    plan = qc.Plan(2, N, 8.0, "hard_sphere", 8, precision="fx16")
+    need = int(qc.LIB.qcoll_step_rk_work_bytes(plan._h, qc._RK_SCHEMES[scheme], cells))
+    big = torch.empty(need // 4 + 1, dtype=torch.float32, device="cuda")
+    odd = big[1:]
+    assert odd.data_ptr() % 8 == 4 and odd.numel() * 4 == need
+    fa, fb = f0.clone(), f0.clone()
+    for _ in range(2):
+        plan.step_rk(fa, 0.05, 0.5, scheme)
+        plan.step_rk(fb, 0.05, 0.5, scheme, work=odd)
+    torch.cuda.synchronize()
+    assert torch.equal(fa, fb)
+    plan.close()
+
+
 @pytest.mark.parametrize("conserve", [False, True])
 def test_tile64_output_not_16_byte_aligned(qc, conserve):
     """The tile-64 kernels write Q through LDS as whole rows, with 16-byte
