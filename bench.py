@@ -819,6 +819,17 @@ def main() -> int:
                      ("bpr343", lambda: splan.step_rk(fs, 0.01, 1.0, "bpr343", work=work))):
         t_s, _ = time_launches(fn, max(3, args.steps // 5), 1, stream)
         step_ms[name] = t_s * 1e3
+    # one BPR(3,4,3) stage launch (Q plus the stage update) against one eval
+    # launch (Q plus the projection), timed in alternating rounds so that both
+    # see the same clock state; launch gaps included on both sides
+    mix_plan, mix_q = res["fx16"]["plan"], res["fx16"]["q"]
+    te_r, ts_r = [], []
+    for r in range(5):
+        te_r.append(time_launches(lambda: mix_plan.eval(f, mix_q), 12, 2, stream)[0])
+        ts_r.append(time_launches(lambda: splan.step_rk(fs, 0.01, 1.0, "bpr343", work=work), 3, 1, stream)[0] / 4)
+    step_ms["bpr343_stage_vs_eval"] = {"stage_launch_ms": float(np.median(ts_r)) * 1e3,
+                                       "eval_launch_ms": float(np.median(te_r)) * 1e3,
+                                       "ratio": float(np.median(ts_r) / np.median(te_r))}
     splan.close()
     del fs, work
 
