@@ -16,6 +16,9 @@ tables that motivate the mixed path's design:
     fx16_f32filt  the fixed-point-lead split (lead on the integer grid + FP16
                   hi and lo, six products), FP64 intermediates, FP32 filters
     fx16          the same with FP64 filters (the mixed path as built)
+    fx16_no_lo_data, fx16_no_lo_dft
+                  fx16 without the product (data lo) x (DFT lead), or without
+                  (data lead) x (DFT lo): five products each
 
   3D (hard spheres, M = 8): the FP32-intermediate FX16 variant, and which of
   its FP32 roundings (spectrum, filters, filter products, the three inverse
@@ -89,15 +92,19 @@ def _split3(y):
     return lead.astype(F32), hi, lo
 
 
-def gemm_fx16(X, E):
+def gemm_fx16(X, E, lo_data: bool = True, lo_dft: bool = True):
     """Six FP16 products with FP32 accumulation: lead x lead exact in one
-    accumulator, the five corrections in a second; returns the FP64 sum."""
+    accumulator, the five corrections in a second; returns the FP64 sum.
+    lo_data / lo_dft = False leave out (data lo) x (DFT lead) / (data lead) x
+    (DFT lo)."""
     A, B = _real_operands(X, E)
     sa, sb = pow2_scale(A, 9), 512.0
     al, ah, ao = _split3(A * sa)
     bl, bh, bo = _split3(B * sb)
     acc0 = (al.astype(np.float64) @ bl.astype(np.float64)).astype(F32)    # exact integer sums < 2^24
-    acc1 = al @ bh + ah @ bl + al @ bo + ah @ bh + ao @ bl                  # FP32 accumulation
+    zero = np.zeros((A.shape[0], B.shape[1]), dtype=F32)
+    acc1 = (al @ bh + ah @ bl + (al @ bo if lo_dft else zero) + ah @ bh       # FP32 accumulation
+            + (ao @ bl if lo_data else zero))
     Y = (acc0.astype(np.float64) + acc1.astype(np.float64)) / (sa * sb)
     return _finish(Y, E.shape[1])
 
@@ -171,6 +178,8 @@ def study_2d(cells: int, seed: int = 1001):
         "exact_f32": (gemm_exact, r32, r32),
         "fx16_f32filt": (gemm_fx16, ident, r32),
         "fx16": (gemm_fx16, ident, ident),
+        "fx16_no_lo_data": (lambda X, E: gemm_fx16(X, E, lo_data=False), ident, ident),
+        "fx16_no_lo_dft": (lambda X, E: gemm_fx16(X, E, lo_dft=False), ident, ident),
     }
     out = {}
     for name, (g, inter, filt) in variants.items():

@@ -19,3 +19,7 @@ def test_2d_orderings():
     # filters gain another order of magnitude
     assert err["fx16"] < 1e-6 < err["fx16_f32filt"] < 1e-5
     assert err["fx16"] * 5 < err["fx16_f32filt"] < err["exact_f32"] < err["fp32_mfma"]
+    # each of the six FP16 products is needed: without the data's lo part the
+    # error is far above 1e-5, without the DFT matrix's lo part an order of
+    # magnitude above the full split's
+    assert err["fx16_no_lo_data"] > 1e-4 and err["fx16_no_lo_dft"] > 10 * err["fx16"]
