@@ -214,7 +214,8 @@ int qcoll_step_rk(qcoll_plan_t plan, float* f, int64_t cells, double dt, double 
  * QCOLL_IMEX_BPR343, 5447 for QCOLL_IMEX_ARS222). Every call on one GPU shares
  * that GPU's array: calls that overlap on one GPU (several streams, several
  * host threads) race and must be ordered by the caller. The array needs no
- * clearing (each stage slot is written before it is read). Other arguments,
+ * clearing (each stage slot, and the moments of f^n, is written before it is
+ * read within the step). Other arguments,
  * errors and results as for qcoll_step_rk, whose results it reproduces
  * bitwise. */
 #define QCOLL_NOALLOC_SCRATCH_BYTES (64ll << 20)

@@ -59,8 +59,8 @@ extern "C" int qcoll_step_rk_noalloc(qcoll_plan_t plan, float* f, int64_t cells,
   if (dev < 0) return QCOLL_EUNSUPPORTED;   // host-only plan
   void* ptr = scratch_on(dev);
   if (!ptr) return QCOLL_EDEVICE;
-  // The stage slots are written before they are read within the step, so the
-  // array needs no clearing between calls.
+  // The stage slots and the moments of f^n are written before they are read
+  // within the step, so the array needs no clearing between calls.
   return qcoll_step_rk(plan, f, cells, dt, eps, scheme, static_cast<float*>(ptr), QCOLL_NOALLOC_SCRATCH_BYTES, status,
                        stream);
 }
