@@ -241,6 +241,29 @@ def test_pingpong_shape_matches_default_shape(qc, cells):
     assert (outs[8][5] == 0).all()
 
 
+@pytest.mark.parametrize("scheme", ["ars222", "bpr343"])
+@pytest.mark.parametrize("N,precision", [(32, "fx16"), (32, "fp32"), (16, "fx16")])
+def test_step_rk_grid_stride_matches_default_shape(qc, N, precision, scheme):
+    """Three one-wavefront workgroups walk 37 cells (about twelve each): the
+    moments of f^n that the first stage launch keeps per cell, and the later
+    launches read back, belong to that cell whatever wavefront computed it, so
+    two steps match the default launch shape's bitwise."""
+    cells = 37
+    f0 = torch.tensor(wl.mixture_cells(2, N, 8.0, cells, 90 + N), dtype=torch.float32, device="cuda")
+    out = []
+    for shape in (None, (1, 3)):
+        plan = qc.Plan(2, N, 8.0, "hard_sphere", 8, precision=precision)
+        if shape is not None:
+            plan.set_launch(*shape)
+        f = f0.clone()
+        for _ in range(2):
+            plan.step_rk(f, 0.02, 0.5, scheme)
+        out.append(f)
+        plan.close()
+    torch.cuda.synchronize()
+    assert torch.equal(out[0], out[1])
+
+
 def test_calls_on_a_side_stream_with_library_allocated_buffers(qc):
     """Calls queued on a stream other than the current one, with the binding
     allocating the output and work buffers: the buffers are recorded on that
