@@ -511,7 +511,6 @@ __device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c) {
 template <int OUT>  // OUT: 0 eval float, 1 eval double (projection), 2 step, -1 from a.out_kind
 __device__ __forceinline__ void fp32_t32_body(const KernelArgs& a, int64_t first, int64_t stride) {
   const int lane = threadIdx.x & 63;
-  const int h = lane >> 5, c = lane & 31;
   float Er[16], Ei[16], Ne[16];
   {
     const float* src = reinterpret_cast<const float*>(a.econst) + lane * 48;

@@ -490,7 +490,7 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int
       // loop, whose spills to vector lanes cost it its overlapped LDS reads.
       int sch = a.rk_scheme - 1, l = a.rk_stage;
       asm volatile("" : "+s"(sch), "+s"(l));
-      const int S = sch == 0 ? 3 : 5;
+      const int ns = sch == 0 ? 3 : 5;   // stages of the scheme
       const double* At = kRkAt[sch][l - 1];
       const double* Ai = kRkA[sch][l - 1];
       const int64_t base = cell * static_cast<int64_t>(n) * n;
@@ -545,21 +545,21 @@ __device__ __forceinline__ void t64_body(const KernelArgs& a, int64_t first, int
           double acc = Ai[m - 1] * Sm;
           if (At[m - 1] != 0.0) {
             const double Qm =
-                m == l - 1 ? gain[v] : static_cast<double>(__builtin_nontemporal_load(&a.rk_work[(S - 3 + m) * a.rk_stride + base + o]));
+                m == l - 1 ? gain[v] : static_cast<double>(__builtin_nontemporal_load(&a.rk_work[(ns - 3 + m) * a.rk_stride + base + o]));
             acc += At[m - 1] * (Qm - Sm);
           }
           rhs += k * acc;
         }
         const float Fl = static_cast<float>(rhs / den);
-        if (l == S) {
+        if (l == ns) {
           bad |= !(fabsf(Fl) <= 3.0e38f);
           __builtin_nontemporal_store(Fl, &fnp[o]);
         } else {
           __builtin_nontemporal_store(Fl, &a.rk_work[(l - 2) * a.rk_stride + base + o]);
-          __builtin_nontemporal_store(static_cast<float>(gain[v]), &a.rk_work[(S - 3 + (l - 1)) * a.rk_stride + base + o]);
+          __builtin_nontemporal_store(static_cast<float>(gain[v]), &a.rk_work[(ns - 3 + (l - 1)) * a.rk_stride + base + o]);
         }
       }
-      if (l == S && a.status) {
+      if (l == ns && a.status) {
         bad = __any(bad) ? 1 : 0;
         if (lane == 0) red[w * 4 + 1] = bad;
         __syncthreads();

@@ -629,7 +629,7 @@ __device__ void cell_3d(const Slot3& a, int64_t cell, char* scratch, double* red
     // grid points, zero elsewhere
     plane_passes<T>(
         E, w, plane, load_axis1,
-        [&](int t, const typename S::acc& dr, const typename S::acc& di) {
+        [&](int t, const typename S::acc& dr, const typename S::acc& /* imaginary part: unused */) {
           OPAQUE_LANE();
 #pragma unroll
           for (int v = 0; v < S::NR; ++v) {

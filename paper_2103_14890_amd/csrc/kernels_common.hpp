@@ -319,7 +319,6 @@ __device__ void finish_cell(const KernelArgs& a, int64_t cell, const float* fv, 
       for (int j = 0; j < kC; ++j) {
         const int v = v0 + j;
         const int r = LY::row(v, lane);
-        const double v1 = -a.L + a.dv * r;
         const double fnv = static_cast<double>(fn[j]);
         const double M = cM * __shfl(e1, r) * e2;
         double t1 = Ai[l - 1] * M, t2 = 0.0;

@@ -76,8 +76,8 @@ int launch_multi(const MultiArgs& args, int waves_per_block, hipStream_t stream)
                                kMaxLds) == hipSuccess;
   }();
   if (!attr_ok) return -3;
-  const int lds = t64 ? kMaxLds : kEoLdsBytes + kFhatLdsBytes * waves_per_block;
-  hipLaunchKernelGGL(multi_kernel, dim3(static_cast<unsigned>(blocks)), dim3(64 * waves_per_block), lds, stream,
+  const int lds_bytes = t64 ? kMaxLds : kEoLdsBytes + kFhatLdsBytes * waves_per_block;
+  hipLaunchKernelGGL(multi_kernel, dim3(static_cast<unsigned>(blocks)), dim3(64 * waves_per_block), lds_bytes, stream,
                      args);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }

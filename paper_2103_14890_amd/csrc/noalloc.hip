@@ -40,7 +40,7 @@ void* scratch_on(int dev) {
   if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
   void* ptr = nullptr;
   const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
-  if (cur != dev) hipSetDevice(cur);
+  if (cur != dev) (void)hipSetDevice(cur);   // the lookup's status decides
   if (e != hipSuccess || !ptr) return nullptr;
   g_scratch[dev] = ptr;
   return ptr;
